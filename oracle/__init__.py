@@ -1,0 +1,482 @@
+"""FP64 CPU oracle for the GS-Cache per-frame hot path (arXiv 2502.14938).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the GPU library or its binding.  It
+shares no code with the GPU path.  The float math lives in gsc_oracle.c
+(plain C, double precision); this module marshals arrays and adds the parts
+that are integer bookkeeping (compose, the derived-Gaussian cache, depth
+scheduling) or tiny dense maths (the reuse predictor), in NumPy float64.
+
+Section references are to the paper: Section 3.1 (eqs. 1-3, structured
+derivation), Section 4 (cache design, Alg. 1 dynamic cache depth, eq. 4
+guiding function, eqs. 5-6 binocular de-redundancy), Section 6
+(AnchorDecoder / RasterizeGaussians optimisations).
+
+Parity status: every function here is pinned by tests in
+tests/test_oracle_*.py against closed forms, brute force, library routines
+the oracle does not itself use, or invariants; see the header of each test.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+TILE = 16
+MIN_ALPHA = 1.0 / 255.0
+T_STOP = 1e-4
+
+
+class OrcCamera(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("pos", C.c_double * 3), ("fovx", C.c_double),
+                ("fovy", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
+                ("znear", C.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(
+                os.path.join(_HERE, "gsc_oracle.c")):
+            from . import build as _b
+            _b.build()
+        lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        lib.orc_unified_camera.argtypes = [P, P, P]
+        lib.orc_select.argtypes = [C.c_int64, P, P, P, P, C.c_double, P, P]
+        lib.orc_select.restype = C.c_int64
+        lib.orc_derive.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int, P, P, C.c_int,
+                                   P, P, P, P, P]
+        lib.orc_preprocess.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_rect_min_q.argtypes = [C.c_double] * 9
+        lib.orc_rect_min_q.restype = C.c_double
+        lib.orc_tile_pairs.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int64, P, P, P]
+        lib.orc_tile_pairs.restype = C.c_int64
+        lib.orc_sort_pairs.argtypes = [C.c_int64, P, P, P, P]
+        lib.orc_blend.argtypes = [C.c_int, C.c_int] + [P] * 12
+        lib.orc_round_bf16.argtypes = [C.c_double]
+        lib.orc_round_bf16.restype = C.c_double
+        lib.orc_round_e4m3.argtypes = [C.c_double]
+        lib.orc_round_e4m3.restype = C.c_double
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def to_orc(cam: dict) -> OrcCamera:
+    c = OrcCamera()
+    R = np.asarray(cam["R"], np.float64).reshape(9)
+    for i in range(9):
+        c.R[i] = R[i]
+    for i in range(3):
+        c.pos[i] = float(cam["pos"][i])
+    c.fovx, c.fovy = float(cam["fovx"]), float(cam["fovy"])
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.znear = float(cam["znear"])
+    return c
+
+
+def from_orc(c: OrcCamera) -> dict:
+    return {"R": np.array(c.R[:], np.float64).reshape(3, 3), "pos": np.array(c.pos[:], np.float64),
+            "fovx": c.fovx, "fovy": c.fovy, "width": c.width, "height": c.height, "znear": c.znear}
+
+
+def round_bf16(x: float) -> float:
+    return _load().orc_round_bf16(float(x))
+
+
+def round_e4m3(x: float) -> float:
+    return _load().orc_round_e4m3(float(x))
+
+
+# ---------------------------------------------------------------- stages
+
+def unified_camera(left: dict, right: dict) -> dict:
+    """Section 4, eqs. 5-6 (binocular de-redundancy)."""
+    lib = _load()
+    l, r, u = to_orc(left), to_orc(right), OrcCamera()
+    lib.orc_unified_camera(C.byref(l), C.byref(r), C.byref(u))
+    return from_orc(u)
+
+
+def select(scene, ucam: dict):
+    """Anchor filtering (LOD + frustum).  Returns (ids ascending int32, band uint8[n])."""
+    lib = _load()
+    pos = _c(scene.pos, np.float32); lev = _c(scene.level, np.uint8); rad = _c(scene.radius, np.float32)
+    out = np.empty(scene.n, np.int32); band = np.empty(scene.n, np.uint8)
+    u = to_orc(ucam)
+    m = lib.orc_select(scene.n, _p(pos), _p(lev), _p(rad), C.byref(u), float(scene.d_ref), _p(out), _p(band))
+    return out[:m].copy(), band
+
+
+def _mlp_ptrs(scene):
+    keep = []
+    arr = (C.c_void_p * 12)()
+    for h, name in enumerate(("alpha", "color", "cov")):
+        for i, w in enumerate(scene.mlp[name]):
+            a = _c(w, np.float32)
+            keep.append(a)
+            arr[4 * h + i] = a.ctypes.data
+    return arr, keep
+
+
+def derive(scene, ids, pu, prec: int = 0) -> dict:
+    """Section 3.1 eq. 3 (AnchorDecoder) for the anchors `ids` seen from p_u.
+    prec: 0 exact FP64, 1 bf16 emulation, 2 e4m3fn-weight emulation.
+    Returns arrays of m*k rows: mu, cov (xx xy xz yy yz zz), rgb, alpha, alpha_pre."""
+    lib = _load()
+    ids = _c(ids, np.int32)
+    m, k = len(ids), scene.k
+    out = {"mu": np.empty((m * k, 3)), "cov": np.empty((m * k, 6)), "rgb": np.empty((m * k, 3)),
+           "alpha": np.empty(m * k), "alpha_pre": np.empty(m * k)}
+    arr, keep = _mlp_ptrs(scene)
+    pu = _c(pu, np.float64)
+    pos = _c(scene.pos, np.float32); feat = _c(scene.feat, np.float32)
+    scl = _c(scene.scale, np.float32); off = _c(scene.offsets, np.float32)
+    lib.orc_derive(m, _p(ids), _p(pos), _p(feat), _p(scl), _p(off), scene.F, scene.H, k, arr, _p(pu),
+                   int(prec), _p(out["mu"]), _p(out["cov"]), _p(out["rgb"]), _p(out["alpha"]),
+                   _p(out["alpha_pre"]))
+    return out
+
+
+def compose(n_visible: int, k: int, alpha: np.ndarray) -> np.ndarray:
+    """Alg. 1 'compose' / render buffer with the opacity mask (Section 6):
+    G_t lists (visible position i, j) for i ascending, j ascending, alpha > 0.
+    Returns flat row indices i*k + j into the derived arrays."""
+    a = np.asarray(alpha).reshape(n_visible, k)
+    ii, jj = np.nonzero(a > 0.0)
+    return (ii * k + jj).astype(np.int64)
+
+
+def preprocess(mu, cov, alpha, cam: dict) -> dict:
+    """EWA projection (Section 3.1) per Gaussian for one eye."""
+    lib = _load()
+    n = len(alpha)
+    mu = _c(mu, np.float64); cov = _c(cov, np.float64); alpha = _c(alpha, np.float64)
+    out = {"mean2d": np.zeros((n, 2)), "conic": np.zeros((n, 3)), "sigma2d": np.zeros((n, 3)),
+           "depth": np.zeros(n), "keep": np.zeros(n, np.uint8), "band": np.zeros(n, np.uint8)}
+    e = to_orc(cam)
+    lib.orc_preprocess(n, _p(mu), _p(cov), _p(alpha), C.byref(e), _p(out["mean2d"]), _p(out["conic"]),
+                       _p(out["sigma2d"]), _p(out["depth"]), _p(out["keep"]), _p(out["band"]))
+    return out
+
+
+def rect_min_q(mx, my, a, b, c, x0, x1, y0, y1) -> float:
+    return _load().orc_rect_min_q(mx, my, a, b, c, x0, x1, y0, y1)
+
+
+def tile_pairs(pre: dict, alpha, W: int, H: int):
+    """Opacity-aware exact tile lists (Section 6).  Returns (tile, g, flags) in
+    emission order (g ascending, tiles row-major); flags bit0 = listed,
+    bit1 = marginal.  Marginal unlisted pairs are included with bit0 = 0."""
+    lib = _load()
+    n = len(alpha)
+    alpha = _c(alpha, np.float64)
+    args = [_p(pre["mean2d"]), _p(pre["conic"]), _p(pre["sigma2d"]), _p(alpha), _p(pre["keep"])]
+    need = lib.orc_tile_pairs(n, *args, W, H, 0, None, None, None)
+    total = -need if need < 0 else need
+    tile = np.empty(total, np.int32); g = np.empty(total, np.int32); fl = np.empty(total, np.uint8)
+    got = lib.orc_tile_pairs(n, *args, W, H, total, _p(tile), _p(g), _p(fl))
+    assert got == total
+    return tile, g, fl
+
+
+def sort_pairs(tile, g, depth) -> np.ndarray:
+    """Stable order by (tile, float32(depth)) (Section 6 key-value pairs)."""
+    lib = _load()
+    tile = _c(tile, np.int32); g = _c(g, np.int32); depth = _c(depth, np.float64)
+    order = np.empty(len(tile), np.int64)
+    lib.orc_sort_pairs(len(tile), _p(tile), _p(g), _p(depth), _p(order))
+    return order
+
+
+def tile_ranges(sorted_tile, n_tiles: int):
+    st = np.searchsorted(sorted_tile, np.arange(n_tiles), side="left").astype(np.int64)
+    en = np.searchsorted(sorted_tile, np.arange(n_tiles), side="right").astype(np.int64)
+    return st, en
+
+
+def blend(W, H, starts, ends, sorted_g, pre, alpha, rgb):
+    """Front-to-back alpha compositing per pixel (Section 3.1)."""
+    lib = _load()
+    npx = W * H
+    img = np.zeros((3, H, W)); T = np.zeros((H, W)); nc = np.zeros((H, W), np.int32)
+    band = np.zeros((H, W), np.uint8)
+    sg = _c(sorted_g, np.int32); alpha = _c(alpha, np.float64); rgb = _c(rgb, np.float64)
+    lib.orc_blend(W, H, _p(_c(starts, np.int64)), _p(_c(ends, np.int64)), _p(sg), _p(pre["mean2d"]),
+                  _p(pre["conic"]), _p(alpha), _p(rgb), _p(pre["depth"]), _p(img), _p(T), _p(nc), _p(band))
+    return img, T, nc, band
+
+
+def render_gaussians(mu, cov, rgb, alpha, cam: dict, debug: bool = False):
+    """Rasterise explicit Gaussians for one camera: preprocess -> tile lists ->
+    sort -> ranges -> blend.  Returns a dict with image [3,H,W], T, n_contrib,
+    pixel band, and (if debug) the intermediate lists."""
+    W, H = int(cam["width"]), int(cam["height"])
+    alpha = np.asarray(alpha, np.float64)
+    pre = preprocess(mu, cov, alpha, cam)
+    tile, g, fl = tile_pairs(pre, alpha, W, H)
+    listed = (fl & 1) == 1
+    lt, lg = tile[listed], g[listed]
+    order = sort_pairs(lt, lg, pre["depth"])
+    st_tile, st_g = lt[order], lg[order]
+    ntiles = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
+    s, e = tile_ranges(st_tile, ntiles)
+    img, T, nc, band = blend(W, H, s, e, st_g, pre, alpha, np.asarray(rgb, np.float64))
+    out = {"image": img, "T": T, "n_contrib": nc, "band": band, "n_pairs": int(listed.sum())}
+    if debug:
+        out.update(pre=pre, pairs_tile=tile, pairs_g=g, pairs_flags=fl, sorted_tile=st_tile,
+                   sorted_g=st_g, starts=s, ends=e)
+    return out
+
+
+# ------------------------------------------------------- derived-Gaussian cache
+
+class CacheSim:
+    """Exact integer model of the computation cache with dynamic reuse depth
+    (Section 4, Alg. 1, eq. 4), per viewer.
+
+    Readings: a line holds one anchor's k derived Gaussians and the frame tau
+    at which they were derived.  At frame t with depth d_t:
+      1. invalidate every line with t - tau > d_t (Alg. 1 'reach max cache
+         reuse depth');
+      2. a visible anchor hits iff it still holds a line (then 1 <= t - tau
+         <= d_t) and reuse is on and the predictor does not mark it stale;
+      3. misses (ascending anchor id) are re-derived with frame t's camera:
+         an anchor that holds a line keeps its slot; the others take free
+         slots in ascending slot order; if free slots are short, lines of
+         anchors not visible now are evicted in ascending (last_used, anchor)
+         order ('outdated data ... evicted'); if still short -> capacity error;
+      4. last_used <- t for every visible anchor's line, tau <- t for misses;
+      5. linear guiding function (eq. 4, update rate r = |M|/|X|):
+         d_{t+1} = clamp(round_half_up(D_max (1 - r)), 1, D_max), computed
+         exactly as floor((2 D_max (|X|-|M|) + |X|) / (2 |X|)); unchanged
+         when |X| = 0.  d_0 = D_max.
+    """
+
+    def __init__(self, n_anchors: int, capacity: int, d_max: int = 10, reuse: bool = True):
+        self.n, self.C, self.D, self.reuse = n_anchors, capacity, d_max, reuse
+        self.slot_of = np.full(n_anchors, -1, np.int64)
+        self.line_anchor = np.full(capacity, -1, np.int64)
+        self.tau = np.zeros(capacity, np.int64)
+        self.last_used = np.zeros(capacity, np.int64)
+        self.d = d_max
+        self.t = 0
+
+    def frame(self, visible: np.ndarray, stale: np.ndarray | None = None) -> dict:
+        t, d = self.t, self.d
+        vis = np.asarray(visible, np.int64)
+        # 1. invalidate lines past the current depth
+        used = self.line_anchor >= 0
+        dead = used & (t - self.tau > d)
+        self.slot_of[self.line_anchor[dead]] = -1
+        self.line_anchor[dead] = -1
+        # 2. hits
+        s = self.slot_of[vis]
+        has = s >= 0
+        hit = has & self.reuse
+        if stale is not None:
+            hit &= ~np.asarray(stale, bool)
+        miss_ids = vis[~hit]
+        # 3. slots for misses without a line
+        need = miss_ids[self.slot_of[miss_ids] < 0]
+        free = np.nonzero(self.line_anchor < 0)[0]
+        evicted = np.zeros(0, np.int64)
+        if len(need) > len(free):
+            short = len(need) - len(free)
+            in_vis = np.zeros(self.n, bool)
+            in_vis[vis] = True
+            cand = np.nonzero((self.line_anchor >= 0) & ~in_vis[np.maximum(self.line_anchor, 0)])[0]
+            if len(cand) < short:
+                raise RuntimeError("cache capacity exceeded")
+            order = np.lexsort((self.line_anchor[cand], self.last_used[cand]))
+            ev = cand[order[:short]]
+            evicted = self.line_anchor[ev].copy()
+            self.slot_of[self.line_anchor[ev]] = -1
+            self.line_anchor[ev] = -1
+            free = np.nonzero(self.line_anchor < 0)[0]
+        slots = free[:len(need)]
+        self.slot_of[need] = slots
+        self.line_anchor[slots] = need
+        # 4. bookkeeping
+        ms = self.slot_of[miss_ids]
+        self.tau[ms] = t
+        self.last_used[self.slot_of[vis]] = t
+        # 5. depth
+        nx, nm = len(vis), len(miss_ids)
+        if nx > 0:
+            dn = (2 * self.D * (nx - nm) + nx) // (2 * nx)
+            self.d = int(min(max(dn, 1), self.D))
+        self.t += 1
+        return {"t": t, "d_used": d, "d_next": self.d, "hit": hit, "misses": miss_ids,
+                "n_visible": nx, "n_miss": nm, "evicted": evicted, "slot": self.slot_of[vis].copy()}
+
+
+# ----------------------------------------------------------- whole frame
+
+def render_frame(scene, left: dict, right: dict, cache: CacheSim | None = None, cache_lines: dict | None = None,
+                 prec: int = 0, deredundancy: bool = True, stale=None, debug: bool = False):
+    """One stereo frame of the cache-centric pipeline (Alg. 1 with eqs. 5-6):
+    unified camera -> selection -> cache schedule -> derive misses -> compose
+    -> per-eye rasterisation.  `cache_lines` maps anchor id -> derived rows
+    (k rows each) and persists across frames together with `cache`.
+    With deredundancy=False each eye selects and derives with its own camera
+    (no cache)."""
+    out = {}
+    if not deredundancy:
+        imgs = []
+        for eye in (left, right):
+            ids, _ = select(scene, eye)
+            der = derive(scene, ids, eye["pos"], prec)
+            G = compose(len(ids), scene.k, der["alpha"])
+            imgs.append(render_gaussians(der["mu"][G], der["cov"][G], der["rgb"][G], der["alpha"][G], eye))
+        return {"left": imgs[0], "right": imgs[1]}
+    U = unified_camera(left, right)
+    ids, sel_band = select(scene, U)
+    k = scene.k
+    if cache is None:
+        der = derive(scene, ids, U["pos"], prec)
+        info = None
+    else:
+        info = cache.frame(ids, stale)
+        miss = info["misses"]
+        fresh = derive(scene, miss, U["pos"], prec)
+        for i, a in enumerate(miss):
+            cache_lines[int(a)] = {key: v[i * k:(i + 1) * k].copy() for key, v in fresh.items()}
+        der = {key: np.concatenate([cache_lines[int(a)][key] for a in ids]) if len(ids) else
+               np.zeros((0,) + fresh[key].shape[1:]) for key in fresh}
+    G = compose(len(ids), k, der["alpha"])
+    mu, cov, rgb, al = der["mu"][G], der["cov"][G], der["rgb"][G], der["alpha"][G]
+    out["left"] = render_gaussians(mu, cov, rgb, al, left, debug)
+    out["right"] = render_gaussians(mu, cov, rgb, al, right, debug)
+    out.update(unified=U, visible=ids, select_band=sel_band, G=G, cache=info,
+               mask_band=np.abs(der["alpha_pre"]) < 1e-6)
+    if debug:
+        out["derived"] = der
+    return out
+
+
+# ------------------------------------------------------------------ metrics
+
+def psnr(img, ref) -> float:
+    """10 log10(1 / MSE) over all 3*H*W values (values in [0,1])."""
+    mse = float(np.mean((np.asarray(img, np.float64) - np.asarray(ref, np.float64)) ** 2))
+    return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
+
+
+def max_abs(img, ref) -> float:
+    return float(np.max(np.abs(np.asarray(img, np.float64) - np.asarray(ref, np.float64))))
+
+
+# -------------------------------------------------------- reuse predictor
+
+PRED_FEATURES = 6
+
+
+def reuse_features(scene, anchors, pu_now, pu_then, age, d_max, fx):
+    """Six per-candidate features for the learned reuse decision:
+    1 - cos(angle between view directions then and now); log(dist_now /
+    dist_then); age / D_max; level / L_max; |p_u(now) - p_u(then)| / dist_now;
+    log2(s_level * fx / dist_now) with s_level the anchor's largest offset
+    scale (its voxel size)."""
+    a = np.asarray(anchors, np.int64)
+    x = scene.pos[a].astype(np.float64)
+    vn = x - np.asarray(pu_now, np.float64)
+    vt = x - np.asarray(pu_then, np.float64).reshape(-1, 3)
+    dn = np.linalg.norm(vn, axis=1); dt = np.linalg.norm(vt, axis=1)
+    cosang = np.sum(vn * vt, axis=1) / (dn * dt)
+    lmax = max(int(scene.l_max), 1)
+    f = np.empty((len(a), PRED_FEATURES))
+    f[:, 0] = 1.0 - cosang
+    f[:, 1] = np.log(dn / dt)
+    f[:, 2] = np.asarray(age, np.float64) / d_max
+    f[:, 3] = scene.level[a].astype(np.float64) / lmax
+    f[:, 4] = np.linalg.norm(np.asarray(pu_now) - np.asarray(pu_then).reshape(-1, 3), axis=1) / dn
+    f[:, 5] = np.log2(scene.scale[a, 0:3].astype(np.float64).max(1) * fx / dn)
+    return f
+
+
+def reuse_label(cached: dict, fresh: dict, k: int) -> np.ndarray:
+    """1 (re-derive) iff any of the anchor's k Gaussians changed by more than
+    1/255 in opacity or any colour channel, or its covariance changed by more
+    than 1 % of its largest entry."""
+    da = np.abs(cached["alpha"] - fresh["alpha"]).reshape(-1, k)
+    dc = np.abs(cached["rgb"] - fresh["rgb"]).reshape(-1, k, 3).max(2)
+    app = np.maximum(da, dc).max(1) > 1.0 / 255.0
+    ds = np.abs(cached["cov"] - fresh["cov"]).reshape(-1, k, 6).max(2)
+    sm = np.abs(fresh["cov"]).reshape(-1, k, 6).max(2)
+    geo = (ds / sm).max(1) > 1e-2
+    return (app | geo).astype(np.uint8)
+
+
+def pred_init(seed: int = 3, width: int = 64):
+    """Predictor weights Linear(6,64)-ReLU-Linear(64,64)-ReLU-Linear(64,1):
+    Glorot-uniform weights, zero biases, PCG64(seed) in layer order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = [(width, PRED_FEATURES), (width, width), (1, width)]
+    params = []
+    for o, i in dims:
+        lim = math.sqrt(6.0 / (o + i))
+        params.append(rng.uniform(-lim, lim, size=(o, i)))
+        params.append(np.zeros(o))
+    return params
+
+
+def pred_forward(params, X):
+    W1, b1, W2, b2, W3, b3 = params
+    z1 = X @ W1.T + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ W2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    logit = (h2 @ W3.T + b3)[:, 0]
+    return logit, (X, z1, h1, z2, h2)
+
+
+def pred_loss_grad(params, X, y, pos_weight: float):
+    """Mean weighted binary cross-entropy on sigmoid(logit) and its analytic
+    gradient: loss_i = -(w y log p + (1-y) log(1-p)), w = pos_weight."""
+    W1, b1, W2, b2, W3, b3 = params
+    logit, (X, z1, h1, z2, h2) = pred_forward(params, X)
+    y = np.asarray(y, np.float64)
+    n = len(y)
+    # log p = -softplus(-l), log(1-p) = -softplus(l)
+    sp_neg = np.logaddexp(0.0, -logit)
+    sp_pos = np.logaddexp(0.0, logit)
+    loss = float(np.mean(pos_weight * y * sp_neg + (1.0 - y) * sp_pos))
+    p = 1.0 / (1.0 + np.exp(-logit))
+    dlogit = (pos_weight * y * (p - 1.0) + (1.0 - y) * p) / n
+    gW3 = dlogit[None, :] @ h2
+    gb3 = np.array([dlogit.sum()])
+    dh2 = dlogit[:, None] @ W3
+    dz2 = dh2 * (z2 > 0)
+    gW2 = dz2.T @ h1
+    gb2 = dz2.sum(0)
+    dh1 = dz2 @ W2
+    dz1 = dh1 * (z1 > 0)
+    gW1 = dz1.T @ X
+    gb1 = dz1.sum(0)
+    return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def adam_step(params, grads, m, v, step: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (bias-corrected), in place; step counts from 1."""
+    for i in range(len(params)):
+        m[i] = b1 * m[i] + (1 - b1) * grads[i]
+        v[i] = b2 * v[i] + (1 - b2) * grads[i] ** 2
+        mh = m[i] / (1 - b1 ** step)
+        vh = v[i] / (1 - b2 ** step)
+        params[i] = params[i] - lr * mh / (np.sqrt(vh) + eps)
+    return params
