@@ -1,0 +1,270 @@
+/*
+ * gscache.h -- C ABI of libgscache.so, an MI355X (gfx950) implementation of
+ * the per-frame hot path of a cache-centric structured-3DGS stereo renderer
+ * (GS-Cache, arXiv 2502.14938).
+ *
+ * One frame of one viewer is:
+ *   gsc_set_camera_pair   unified camera of the stereo pair (Section 4,
+ *                         binocular stereo de-redundancy, eqs. 5-6)
+ *   gsc_derive            anchor indexing and filtering, cache scheduling
+ *                         with dynamic reuse depth, derivation of the misses,
+ *                         compose of the render buffer (Section 4, Alg. 1,
+ *                         eq. 4; Section 3.1 eq. 3; Section 6 AnchorDecoder)
+ *   gsc_render_stereo     per-eye EWA projection, opacity-aware exact tile
+ *                         binning, (tile | depth) radix sort, front-to-back
+ *                         compositing (Section 3.1; Section 6
+ *                         RasterizeGaussians)
+ *
+ * Conventions for every call:
+ *   - Return value: GSC_OK (0) or a negative GSC_E_* code.  No exception or
+ *     abort crosses the ABI; gsc_last_error() gives a message.
+ *   - "device" pointers are HIP device memory on the context's device
+ *     (e.g. a torch CUDA tensor's data_ptr()); "host" pointers are ordinary
+ *     process memory.  The library never frees caller memory and never keeps
+ *     a caller pointer after a call returns unless stated.
+ *   - Work is enqueued on the context's HIP stream (set at creation, NULL =
+ *     the legacy default stream) and is asynchronous unless stated; the
+ *     caller synchronises that stream (or calls gsc_sync) before reading
+ *     outputs.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef GSCACHE_H
+#define GSCACHE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSC_OK 0
+#define GSC_E_INVALID_ARG (-1) /* null pointer, size out of range, bad enum */
+#define GSC_E_NOT_LOADED (-2)  /* call needs gsc_load_anchors / a camera pair / a derive first */
+#define GSC_E_OOM (-3)         /* device allocation failed */
+#define GSC_E_CAPACITY (-4)    /* tile-pair or cache capacity exceeded this frame (see stats) */
+#define GSC_E_BUDGET (-5)      /* serving: viewer does not fit the HBM budget now */
+#define GSC_E_HIP (-6)         /* a HIP runtime call failed */
+
+/* Derivation arithmetic (the projection and compositing are always FP32). */
+#define GSC_PREC_F32 0  /* FP32 weights, activations and accumulation */
+#define GSC_PREC_BF16 1 /* BF16 weights and activations on MFMA, FP32 accumulate */
+#define GSC_PREC_FP8 2  /* e4m3fn weights (per-output-row FP32 scale), BF16 activations, FP32 accumulate */
+
+/* Pipeline switches (gsc_config.flags). */
+#define GSC_FLAG_DEREDUNDANCY 1u  /* derive once per pair with the unified camera (eqs. 5-6);
+                                     off: each eye selects and derives with its own camera */
+#define GSC_FLAG_REUSE 2u         /* computation cache across frames (Section 4, Alg. 1) */
+#define GSC_FLAG_PREDICTOR 4u     /* learned reuse: cached anchors the predictor marks stale are
+                                     re-derived (only adds misses) */
+#define GSC_FLAG_FULL_KEY_SORT 8u /* sort full 64-bit (tile<<32 | depth) keys after duplication
+                                     instead of pre-sorting depths per Gaussian; same order */
+
+/* Cache depth guiding function H (eq. 4). */
+#define GSC_GUIDE_LINEAR 0 /* d = clamp(round_half_up(d_max (1 - r)), 1, d_max), r = misses/visible */
+#define GSC_GUIDE_FIXED 1  /* d = d_max every frame */
+
+typedef struct gsc_config {
+    int32_t k;                  /* neural Gaussians per anchor (offsets), 1..16 */
+    int32_t feat_dim;           /* anchor feature length F, must be 32 */
+    int32_t hidden;             /* MLP hidden width, must be 32 */
+    int32_t d_max;              /* maximum reuse depth D_max (the paper uses 10), 1..64 */
+    int32_t guide;              /* GSC_GUIDE_* */
+    int32_t precision;          /* GSC_PREC_* */
+    uint32_t flags;             /* GSC_FLAG_* */
+    float predictor_threshold;  /* re-derive when p(stale) > this */
+    int64_t cache_capacity;     /* cache lines (anchors); 0 = number of anchors */
+    int32_t max_width;          /* largest eye image the context renders */
+    int32_t max_height;
+    int64_t max_pairs;          /* tile-pair capacity per eye; 0 = 24 x max Gaussians */
+} gsc_config;
+
+/* Pinhole camera: world -> camera rotation R (row-major 3x3, rows = right,
+ * down, forward), centre pos, full fields of view (radians), image size,
+ * near plane.  Pixel (u, v) has its centre at (u + 0.5, v + 0.5);
+ * fx = width / (2 tan(fovx / 2)), principal point (width/2, height/2). */
+typedef struct gsc_camera {
+    double R[9];
+    double pos[3];
+    double fovx, fovy;
+    int32_t width, height;
+    double znear;
+} gsc_camera;
+
+/* Anchor scene (Section 3.1: anchors with feature f, derived by MLP_theta).
+ * All arrays are row-major float32 (level uint8) in host memory
+ * (is_device = 0) or device memory (is_device = 1):
+ *   pos [n,3], level [n], radius [n] (bounding sphere of everything the
+ *   anchor derives), feat [n,F], scale [n,6] ([0:3] offset scale, [3:6]
+ *   base Gaussian scale), offsets [n,k,3].
+ * d_ref: LOD reference distance; an anchor of level l > 0 is used only
+ * within d_ref * 2^-l of the unified camera. */
+typedef struct gsc_anchors {
+    int64_t n;
+    const float* pos;
+    const uint8_t* level;
+    const float* radius;
+    const float* feat;
+    const float* scale;
+    const float* offsets;
+    double d_ref;
+    int32_t is_device;
+} gsc_anchors;
+
+/* Derivation MLPs (eq. 3), host float32, row-major [out, in] like
+ * torch.nn.Linear; head 0 = opacity (k outputs), 1 = colour (3k), 2 =
+ * covariance (7k: 3 scale logits then quaternion w,x,y,z per Gaussian).
+ * W1[h] is [hidden, F+3] (inputs: feature then view direction), W2[h] is
+ * [c_h k, hidden]. */
+typedef struct gsc_mlp {
+    const float* W1[3];
+    const float* b1[3];
+    const float* W2[3];
+    const float* b2[3];
+} gsc_mlp;
+
+/* Explicit Gaussians for the raster-only entry, device float32:
+ * mu [n,3], cov [n,6] (xx xy xz yy yz zz), rgb [n,3], alpha [n]. */
+typedef struct gsc_gaussians {
+    int64_t n;
+    const float* mu;
+    const float* cov;
+    const float* rgb;
+    const float* alpha;
+} gsc_gaussians;
+
+/* Per-frame counters, valid after gsc_sync. */
+typedef struct gsc_frame_stats {
+    int64_t frame;          /* frame index t of the last derive */
+    int64_t n_visible;      /* |X_t| */
+    int64_t n_miss;         /* |M_t| anchors derived this frame */
+    int64_t n_gauss;        /* |G_t| Gaussians in the render buffer */
+    int64_t n_pairs[2];     /* tile pairs per eye */
+    int64_t n_evicted;      /* lines evicted for capacity this frame */
+    int32_t depth_used;     /* reuse depth d_t applied this frame */
+    int32_t depth_next;     /* d_{t+1} */
+    int32_t overflow;       /* bit0 pair capacity, bit1 cache capacity */
+    int32_t pad;
+    int64_t device_bytes;   /* device memory owned by the context */
+} gsc_frame_stats;
+
+typedef struct gsc_ctx gsc_ctx;
+
+/* Create a context on the current HIP device.  cfg is copied; stream is a
+ * hipStream_t (NULL = default stream).  *out receives the context. */
+int gsc_create(const gsc_config* cfg, void* stream, gsc_ctx** out);
+/* Free the context and every device buffer it owns (synchronises first). */
+void gsc_destroy(gsc_ctx* ctx);
+/* Message for the last error on this context (or a global one if ctx is
+ * NULL); valid until the next call. */
+const char* gsc_last_error(const gsc_ctx* ctx);
+/* Change the stream later calls enqueue on. */
+int gsc_set_stream(gsc_ctx* ctx, void* stream);
+
+/* Copy the scene and MLP weights into the library's own device layout (SoA
+ * positions, packed weights in every precision), then synchronise: the
+ * caller may free its arrays on return.  Resets the cache and frame count. */
+int gsc_load_anchors(gsc_ctx* ctx, const gsc_anchors* anchors, const gsc_mlp* mlp);
+
+/* Set the next frame's stereo pair (host structs, copied).  Both eyes must
+ * share fov, size and near plane; size must fit max_width x max_height.
+ * Computes the unified camera in FP64 on the host (eqs. 5-6; roll from the
+ * mean of the eyes' right axes).  t_arrival is recorded for latency stats. */
+int gsc_set_camera_pair(gsc_ctx* ctx, const gsc_camera* left, const gsc_camera* right, double t_arrival);
+
+/* Enqueue anchor selection, cache scheduling (+ learned reuse), derivation
+ * of the misses, depth update and compose for frame t, then t += 1.
+ * Needs gsc_load_anchors and gsc_set_camera_pair. */
+int gsc_derive(gsc_ctx* ctx);
+
+/* Enqueue rasterisation of the composed render buffer for both eyes into
+ * caller-owned device buffers: rgb planar [3,H,W] float32 per eye; final
+ * transmittance [H,W] float32 per eye (may be NULL).  Needs gsc_derive. */
+int gsc_render_stereo(gsc_ctx* ctx, float* left_chw, float* right_chw, float* left_T, float* right_T);
+
+/* Raster-only entry: rasterise explicit Gaussians (device arrays) for one
+ * camera into out_chw [3,H,W] float32, out_T [H,W] (may be NULL) and
+ * out_ncontrib [H,W] int32 (may be NULL).  n must not exceed the context's
+ * Gaussian capacity.  Does not touch the cache. */
+int gsc_render_gaussians(gsc_ctx* ctx, const gsc_gaussians* g, const gsc_camera* cam, float* out_chw,
+                         float* out_T, int32_t* out_ncontrib);
+
+/* Wait for the stream, then report GSC_E_CAPACITY if the last frame
+ * overflowed a capacity, else GSC_OK. */
+int gsc_sync(gsc_ctx* ctx);
+/* Synchronise and fill *st with the last frame's counters. */
+int gsc_get_stats(gsc_ctx* ctx, gsc_frame_stats* st);
+/* Drop every cache line and reset the depth to d_max and t to 0. */
+int gsc_reset_cache(gsc_ctx* ctx);
+
+/* Debug copies for parity tests (synchronous).  what: */
+#define GSC_DBG_VISIBLE 0   /* int32 [n_visible] anchor ids, ascending */
+#define GSC_DBG_MISSES 1    /* int32 [n_miss] anchor ids, ascending */
+#define GSC_DBG_GAUSS 2     /* int32 [n_gauss] (visible position * k + j) of the render buffer */
+#define GSC_DBG_DERIVED 3   /* float32 [n_gauss, 13]: mu3 cov6 rgb3 alpha, render-buffer order */
+#define GSC_DBG_PAIRS 4     /* int32 [n_pairs(eye), 2]: (tile, render-buffer index), sorted order */
+#define GSC_DBG_RANGES 5    /* int32 [n_tiles(eye), 2]: [start, end) per tile */
+#define GSC_DBG_PREPROC 6   /* float32 [n_gauss, 8]: mean2d.x, .y, conic a b c, alpha, depth,
+                               tile count (as float) for eye */
+#define GSC_DBG_DEPTH 7     /* int32 [1]: current reuse depth */
+/* Copies at most cap elements (of the unit above: ints, floats or rows) to
+ * host_dst and writes the full count to *n. */
+int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap, int64_t* n);
+
+/* ---------------- learned reuse predictor (Linear 6-64-64-1, sigmoid) ---- */
+#define GSC_PRED_NPARAMS (64 * 6 + 64 + 64 * 64 + 64 + 64 + 1)
+/* Load predictor parameters (host float32, order W1[64,6] b1 W2[64,64] b2
+ * W3[1,64] b3). */
+int gsc_predictor_load(gsc_ctx* ctx, const float* params, int64_t n);
+/* Read the current parameters back (host float32, same order). */
+int gsc_predictor_get(gsc_ctx* ctx, float* params, int64_t n);
+/* Train on the device with the library's own forward/backward/Adam
+ * kernels: X host float32 [n,6] features, y host uint8 [n] labels.  Mini
+ * batches of `batch` rows in a seeded shuffled order for `epochs` epochs;
+ * BCE with positive-class weight pos_weight; Adam(lr, 0.9, 0.999, 1e-8).
+ * loss_out (host, may be NULL) receives one mean loss per epoch. */
+int gsc_predictor_train(gsc_ctx* ctx, const float* X, const uint8_t* y, int64_t n, int32_t batch,
+                        int32_t epochs, float lr, float pos_weight, uint64_t seed, float* loss_out);
+/* One forward/backward pass on device buffers (for gradient checks):
+ * X [n,6] float32, y [n] float32 (0/1), device; grads_out host float32
+ * [GSC_PRED_NPARAMS]; loss_out host. */
+int gsc_predictor_grad(gsc_ctx* ctx, const float* X, const float* y, int64_t n, float pos_weight,
+                       float* grads_out, float* loss_out);
+/* Probabilities for X [n,6] (device) into p_out [n] (device), BF16 inference path. */
+int gsc_predictor_infer(gsc_ctx* ctx, const float* X, int64_t n, float* p_out);
+/* Features of the current frame's reuse candidates (device float32 out
+ * [cap,6], ids int32 [cap] of the anchors); synchronous; *n = count.
+ * Valid after gsc_derive. */
+int gsc_predictor_features(gsc_ctx* ctx, float* X_out, int32_t* ids_out, int64_t cap, int64_t* n);
+
+/* ---------------- serving: several viewers, one device ------------------- */
+typedef struct gsc_server gsc_server;
+/* A server shares the scene of `scene_ctx` (which must stay alive) among
+ * viewers.  budget_bytes caps the device memory of all admitted viewers. */
+int gsc_server_create(gsc_ctx* scene_ctx, int64_t budget_bytes, void* stream, gsc_server** out);
+void gsc_server_destroy(gsc_server* s);
+/* Admit a viewer whose eyes are at most max_width x max_height: returns a
+ * viewer id >= 0, or GSC_E_BUDGET if its buffers do not fit the budget
+ * now (the caller retries after a viewer leaves). */
+int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height);
+/* Bytes a viewer of this size would take (for admission planning). */
+int64_t gsc_server_viewer_bytes(gsc_server* s, int32_t max_width, int32_t max_height);
+/* Queue one stereo frame for a viewer: cameras are copied; outputs are
+ * caller device buffers [3,H,W] float32 per eye that stay valid until the
+ * frame completes.  Returns a request id >= 0. */
+int64_t gsc_server_submit(gsc_server* s, int32_t viewer, const gsc_camera* left, const gsc_camera* right,
+                          double t_arrival, float* out_left, float* out_right);
+/* Launch every queued request of every viewer as one batch: per viewer the
+ * derive stage, then one persistent blend launch over all (viewer, eye,
+ * tile) work items.  Returns the number of requests launched (asynchronous). */
+int gsc_server_step(gsc_server* s);
+/* Completed requests since the last poll (non-blocking): writes up to cap
+ * request ids and their completion times (seconds, host monotonic clock,
+ * taken when the device finished) and returns the count. */
+int gsc_server_poll(gsc_server* s, int64_t* ids, double* t_done, int32_t cap);
+/* Remove a viewer and free its buffers (after its requests complete). */
+int gsc_server_leave(gsc_server* s, int32_t viewer);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSCACHE_H */

@@ -1,0 +1,758 @@
+// C ABI of libgscache (declared in include/gscache.h): context lifetime,
+// scene loading, the stereo camera pair, and the frame entry points.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gsc_common.h"
+#include "gsc_ctx.h"
+
+using namespace gsc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(gsc_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+int hip_fail(gsc_ctx* c, hipError_t e, const char* where) {
+    return fail(c, GSC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(c, x)                                   \
+    do {                                                    \
+        hipError_t e_ = (x);                                \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #x);   \
+    } while (0)
+
+// ------------------------------------------------------------ conversions
+
+uint16_t f32_to_bf16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
+// OCP float8 e4m3fn encoding, round to nearest even, saturating at 448.
+uint8_t f32_to_e4m3(float x) {
+    uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+    double a = std::fabs((double)x);
+    if (a == 0.0) return sign;
+    if (a >= 448.0) return sign | 0x7e;
+    int e;
+    std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
+    int ex = e - 1;     // a in [2^ex, 2^(ex+1))
+    if (ex < -6) {      // subnormal: multiples of 2^-9
+        double m = std::nearbyint(a / std::ldexp(1.0, -9));
+        return sign | (uint8_t)m;  // m == 8 encodes 2^-6 (exponent field 1)
+    }
+    double m = std::nearbyint(a / std::ldexp(1.0, ex - 3));  // in [8, 16]
+    if (m >= 16.0) {
+        m = 8.0;
+        ++ex;
+    }
+    int field = ex + 7;
+    int mant = (int)m - 8;
+    if (field > 15 || (field == 15 && mant == 7)) return sign | 0x7e;
+    return sign | (uint8_t)((field << 3) | mant);
+}
+
+// --------------------------------------------------------- unified camera
+// Binocular stereo de-redundancy (Section 4, eqs. 5-6), in double precision.
+
+void unified_camera(const gsc_camera& l, const gsc_camera& r, gsc_camera& u) {
+    double d[3], rt[3], dn[3];
+    for (int i = 0; i < 3; ++i) d[i] = l.R[6 + i] + r.R[6 + i];
+    double nd = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int i = 0; i < 3; ++i) d[i] /= nd;
+    double bx = l.pos[0] - r.pos[0], by = l.pos[1] - r.pos[1], bz = l.pos[2] - r.pos[2];
+    double setback = std::sqrt(bx * bx + by * by + bz * bz) / (2.0 * std::tan(0.5 * l.fovx));
+    for (int i = 0; i < 3; ++i) rt[i] = l.R[i] + r.R[i];
+    double pr = rt[0] * d[0] + rt[1] * d[1] + rt[2] * d[2];
+    for (int i = 0; i < 3; ++i) rt[i] -= pr * d[i];
+    double nr = std::sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    for (int i = 0; i < 3; ++i) rt[i] /= nr;
+    dn[0] = d[1] * rt[2] - d[2] * rt[1];
+    dn[1] = d[2] * rt[0] - d[0] * rt[2];
+    dn[2] = d[0] * rt[1] - d[1] * rt[0];
+    u = l;
+    for (int i = 0; i < 3; ++i) {
+        u.R[i] = rt[i];
+        u.R[3 + i] = dn[i];
+        u.R[6 + i] = d[i];
+        u.pos[i] = 0.5 * (l.pos[i] + r.pos[i]) - d[i] * setback;
+    }
+}
+
+// Frustum planes of a camera in world space, inward: n.x + w >= -radius.
+DeriveCam derive_cam(const gsc_camera& c, double d_ref) {
+    DeriveCam dc;
+    double tx = std::tan(0.5 * c.fovx), ty = std::tan(0.5 * c.fovy);
+    double nx = std::sqrt(1.0 + tx * tx), ny = std::sqrt(1.0 + ty * ty);
+    double cam_n[5][3] = {{0.0, 0.0, 1.0},
+                          {1.0 / nx, 0.0, tx / nx},
+                          {-1.0 / nx, 0.0, tx / nx},
+                          {0.0, 1.0 / ny, ty / ny},
+                          {0.0, -1.0 / ny, ty / ny}};
+    for (int p = 0; p < 5; ++p) {
+        double w[3];
+        for (int j = 0; j < 3; ++j)
+            w[j] = c.R[0 * 3 + j] * cam_n[p][0] + c.R[1 * 3 + j] * cam_n[p][1] + c.R[2 * 3 + j] * cam_n[p][2];
+        double off = -(w[0] * c.pos[0] + w[1] * c.pos[1] + w[2] * c.pos[2]);
+        if (p == 0) off -= c.znear;
+        for (int j = 0; j < 3; ++j) dc.planes[p][j] = (float)w[j];
+        dc.planes[p][3] = (float)off;
+    }
+    for (int i = 0; i < 3; ++i) dc.pos[i] = (float)c.pos[i];
+    dc.d_ref = (float)d_ref;
+    dc.fx = (float)(c.width / (2.0 * tx));
+    return dc;
+}
+
+bool valid_camera(const gsc_camera& c) {
+    return c.width > 0 && c.height > 0 && c.fovx > 0 && c.fovx < M_PI && c.fovy > 0 && c.fovy < M_PI &&
+           c.znear > 0 && std::isfinite(c.pos[0]) && std::isfinite(c.pos[1]) && std::isfinite(c.pos[2]);
+}
+
+}  // namespace
+
+namespace gsc {
+
+template <typename T>
+hipError_t dalloc(gsc_ctx* c, size_t& acct, T** p, int64_t count) {
+    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e == hipSuccess) {
+        acct += bytes;
+        (c->alloc_list ? c->alloc_list : &c->allocs)->push_back((void*)*p);
+    }
+    return e;
+}
+
+void free_explicit(gsc_ctx* c) {
+    if (c->xallocs.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->xallocs) (void)hipFree(p);
+    c->xallocs.clear();
+    for (void* p : c->xhost_allocs) (void)hipHostFree(p);
+    c->xhost_allocs.clear();
+    c->xg = {};
+    c->xg_cap = 0;
+    c->xg_bytes = 0;
+    c->xraster = Raster();
+}
+
+void free_all(gsc_ctx* c) {
+    if (c->allocs.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    for (void* p : c->host_allocs) (void)hipHostFree(p);
+    c->host_allocs.clear();
+    c->scene = Scene();
+    c->view[0] = View();
+    c->view[1] = View();
+    c->raster = Raster();
+    c->loaded = false;
+}
+
+hipError_t alloc_view(gsc_ctx* c, View& v, int64_t n, int64_t C, int k) {
+    size_t& b = v.bytes;
+    v.C = C;
+    v.max_gauss = C * k;
+    int64_t m = n > C ? n : C;
+    hipError_t e;
+#define A_(p, cnt) if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) return e
+    A_(v.slot_of, n); A_(v.line_anchor, C); A_(v.line_tau, C); A_(v.line_last, C);
+    A_(v.L0, C * k); A_(v.L1, C * k); A_(v.L2, C * k); A_(v.L3, C * k);
+    A_(v.pu_hist, 64 * 4); A_(v.visible, n); A_(v.vslot, n);
+    A_(v.tmp_a, m); A_(v.tmp_b, m); A_(v.tmp_c, m); A_(v.tmp_d, m);
+    A_(v.evict_hist, 64); A_(v.evict_scan_n, 1);
+    A_(v.misses, n); A_(v.free_list, C); A_(v.G, v.max_gauss); A_(v.block_sums, kScanBlocks);
+    A_(v.cand_feat, n * kPredIn); A_(v.cand_id, n); A_(v.cnt, 1);
+#undef A_
+    if ((e = hipHostMalloc((void**)&v.cnt_host, sizeof(Counters))) != hipSuccess) return e;
+    c->host_allocs.push_back(v.cnt_host);
+    return hipSuccess;
+}
+
+hipError_t alloc_raster(gsc_ctx* c, Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles,
+                        bool full_key) {
+    size_t& b = r.bytes;
+    r.max_entries = max_entries;
+    r.max_pairs = max_pairs;
+    r.max_tiles = max_tiles;
+    hipError_t e;
+#define A_(p, cnt) if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) return e
+    A_(r.recA, max_entries); A_(r.recB, max_entries); A_(r.recC, max_entries); A_(r.ntiles, max_entries);
+    A_(r.rect, max_entries); A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
+    A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
+    A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
+    if (full_key) { A_(r.pkey64[0], max_pairs); A_(r.pkey64[1], max_pairs); }
+    A_(r.ranges, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks); A_(r.block_sums, kScanBlocks);
+    A_(r.n_sort, 1); A_(r.cnt, 1);
+#undef A_
+    if ((e = hipHostMalloc((void**)&r.cnt_host, sizeof(RasterCounters))) != hipSuccess) return e;
+    (c->alloc_list ? &c->xhost_allocs : &c->host_allocs)->push_back(r.cnt_host);
+    return hipSuccess;
+}
+
+__global__ void k_reset_view(int32_t* slot_of, int64_t n, int32_t* line_anchor, int32_t* line_tau, int32_t* line_last,
+                             int64_t C, Counters* cnt, int32_t dmax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t a = i; a < n; a += st) slot_of[a] = -1;
+    for (int64_t s = i; s < C; s += st) {
+        line_anchor[s] = -1;
+        line_tau[s] = 0;
+        line_last[s] = 0;
+    }
+    if (i == 0) {
+        Counters z = {};
+        z.depth = dmax;
+        z.depth_used = dmax;
+        *cnt = z;
+    }
+}
+
+hipError_t reset_view(gsc_ctx* c, View& v, int64_t n, int dmax) {
+    hipLaunchKernelGGL(k_reset_view, dim3(1024), dim3(256), 0, c->stream, v.slot_of, n, v.line_anchor, v.line_tau,
+                       v.line_last, v.C, v.cnt, dmax);
+    v.t = 0;
+    return hipGetLastError();
+}
+
+__global__ void k_pack_explicit(const float* __restrict__ mu, const float* __restrict__ cov,
+                                const float* __restrict__ rgb, const float* __restrict__ alpha, int64_t n, float4* L0,
+                                float4* L1, float4* L2, float* L3) {
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) {
+        L0[i] = make_float4(mu[3 * i], mu[3 * i + 1], mu[3 * i + 2], alpha[i]);
+        L1[i] = make_float4(cov[6 * i], cov[6 * i + 1], cov[6 * i + 2], cov[6 * i + 3]);
+        L2[i] = make_float4(cov[6 * i + 4], cov[6 * i + 5], rgb[3 * i], rgb[3 * i + 1]);
+        L3[i] = rgb[3 * i + 2];
+    }
+}
+
+hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles) {
+    int64_t need = g.n > 1 ? g.n : 1;
+    if (c->xg_cap < need || c->xraster.max_tiles < ntiles) {
+        free_explicit(c);
+        int64_t cap = 1024;
+        while (cap < need) cap <<= 1;
+        int64_t pairs = c->cfg.max_pairs > 0 ? c->cfg.max_pairs : 64 * cap;
+        if (pairs > (1ll << 31) - 1) pairs = (1ll << 31) - 1;
+        int64_t tiles = ntiles > 1 ? ntiles : 1;
+        c->alloc_list = &c->xallocs;
+        hipError_t e = hipSuccess;
+        if ((e = dalloc(c, c->xg_bytes, &c->xg.L0, cap)) == hipSuccess &&
+            (e = dalloc(c, c->xg_bytes, &c->xg.L1, cap)) == hipSuccess &&
+            (e = dalloc(c, c->xg_bytes, &c->xg.L2, cap)) == hipSuccess &&
+            (e = dalloc(c, c->xg_bytes, &c->xg.L3, cap)) == hipSuccess)
+            e = alloc_raster(c, c->xraster, cap, pairs, tiles, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
+        c->alloc_list = nullptr;
+        if (e != hipSuccess) {
+            free_explicit(c);
+            return e;
+        }
+        c->xg_cap = cap;
+    }
+    if (g.n > 0) {
+        int64_t blocks = (g.n + 255) / 256;
+        if (blocks > kGridBlocks) blocks = kGridBlocks;
+        hipLaunchKernelGGL(k_pack_explicit, dim3((unsigned)blocks), dim3(256), 0, c->stream, g.mu, g.cov, g.rgb,
+                           g.alpha, g.n, c->xg.L0, c->xg.L1, c->xg.L2, c->xg.L3);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gsc
+
+// ====================================================================== ABI
+
+extern "C" {
+
+int gsc_create(const gsc_config* cfg, void* stream, gsc_ctx** out) {
+    if (!cfg || !out) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: null argument");
+    *out = nullptr;
+    if (cfg->k < 1 || cfg->k > kMaxK) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: k must be in [1, 16]");
+    if (cfg->feat_dim != kF || cfg->hidden != kH)
+        return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: feat_dim and hidden must be 32");
+    if (cfg->d_max < 1 || cfg->d_max > 63) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: d_max must be in [1, 63]");
+    if (cfg->precision < GSC_PREC_F32 || cfg->precision > GSC_PREC_FP8)
+        return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: bad precision");
+    if (cfg->guide != GSC_GUIDE_LINEAR && cfg->guide != GSC_GUIDE_FIXED)
+        return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: bad guide");
+    if (cfg->max_width < 1 || cfg->max_height < 1 || cfg->max_width > 16384 || cfg->max_height > 16384)
+        return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: max image size out of range");
+    if (cfg->cache_capacity < 0 || cfg->max_pairs < 0) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: negative size");
+    gsc_ctx* c = new (std::nothrow) gsc_ctx();
+    if (!c) return fail(nullptr, GSC_E_OOM, "gsc_create: out of host memory");
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, GSC_E_HIP, "gsc_create: no HIP device");
+    }
+    *out = c;
+    return GSC_OK;
+}
+
+void gsc_destroy(gsc_ctx* c) {
+    if (!c) return;
+    gsc::pred_free(c);
+    gsc::free_explicit(c);
+    gsc::free_all(c);
+    delete c;
+}
+
+const char* gsc_last_error(const gsc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int gsc_set_stream(gsc_ctx* c, void* stream) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_set_stream: null context");
+    c->stream = (hipStream_t)stream;
+    return GSC_OK;
+}
+
+int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
+    if (!c || !an || !mlp) return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: null argument");
+    if (an->n < 1 || an->n > (1ll << 30)) return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: n out of range");
+    if (!an->pos || !an->level || !an->radius || !an->feat || !an->scale || !an->offsets)
+        return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: null array");
+    for (int h = 0; h < 3; ++h)
+        if (!mlp->W1[h] || !mlp->b1[h] || !mlp->W2[h] || !mlp->b2[h])
+            return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: null weight");
+    if (!(an->d_ref > 0)) return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: d_ref must be positive");
+    const int64_t n = an->n;
+    const int k = c->cfg.k;
+    free_all(c);
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+
+    // host copies of the inputs (device inputs are staged through the host)
+    auto fetch = [&](const void* src, size_t bytes, std::vector<uint8_t>& buf) -> const void* {
+        if (!an->is_device) return src;
+        buf.resize(bytes);
+        if (hipMemcpy(buf.data(), src, bytes, hipMemcpyDeviceToHost) != hipSuccess) return nullptr;
+        return buf.data();
+    };
+    std::vector<uint8_t> bpos, blev, brad, bfeat, bscale, boff;
+    const float* pos = (const float*)fetch(an->pos, n * 12, bpos);
+    const uint8_t* lev = (const uint8_t*)fetch(an->level, n, blev);
+    const float* rad = (const float*)fetch(an->radius, n * 4, brad);
+    const float* feat = (const float*)fetch(an->feat, n * kF * 4, bfeat);
+    const float* scl = (const float*)fetch(an->scale, n * 24, bscale);
+    const float* off = (const float*)fetch(an->offsets, n * k * 12, boff);
+    if (!pos || !lev || !rad || !feat || !scl || !off) return fail(c, GSC_E_HIP, "gsc_load_anchors: device read failed");
+
+    Scene& sc = c->scene;
+    sc.n = n;
+    sc.k = k;
+    sc.d_ref = (float)an->d_ref;
+    int lmax = 0;
+    for (int64_t a = 0; a < n; ++a) lmax = lev[a] > lmax ? lev[a] : lmax;
+    sc.l_max = lmax;
+    std::vector<float4> posr(n);
+    for (int64_t a = 0; a < n; ++a) posr[a] = make_float4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], rad[a]);
+
+    WeightLayout L = weight_layout(k);
+    std::vector<float> w32(L.total, 0.f);
+    std::vector<uint16_t> wbf(L.total, 0);
+    std::vector<uint8_t> w8(L.total, 0);
+    std::vector<float> w8s(L.scale_total, 1.f);
+    const int cH[3] = {1, 3, 7};
+    for (int h = 0; h < 3; ++h) {
+        std::memcpy(&w32[L.W1[h]], mlp->W1[h], sizeof(float) * kH * (kF + 3));
+        std::memcpy(&w32[L.b1[h]], mlp->b1[h], sizeof(float) * kH);
+        std::memcpy(&w32[L.W2[h]], mlp->W2[h], sizeof(float) * cH[h] * k * kH);
+        std::memcpy(&w32[L.b2[h]], mlp->b2[h], sizeof(float) * cH[h] * k);
+        struct M { int off, rows, cols, soff; } mats[2] = {{L.W1[h], kH, kF + 3, L.scale_W1[h]},
+                                                          {L.W2[h], cH[h] * k, kH, L.scale_W2[h]}};
+        for (auto& m : mats)
+            for (int r = 0; r < m.rows; ++r) {
+                float amax = 0.f;
+                for (int q = 0; q < m.cols; ++q) amax = std::fmax(amax, std::fabs(w32[m.off + r * m.cols + q]));
+                float s = amax > 0.f ? amax / 448.0f : 1.0f;
+                w8s[m.soff + r] = s;
+                for (int q = 0; q < m.cols; ++q) {
+                    float wv = w32[m.off + r * m.cols + q];
+                    wbf[m.off + r * m.cols + q] = f32_to_bf16(wv);
+                    w8[m.off + r * m.cols + q] = f32_to_e4m3(wv / s);
+                }
+            }
+    }
+
+    const int nviews = (c->cfg.flags & GSC_FLAG_DEREDUNDANCY) ? 1 : 2;
+    int64_t C = c->cfg.cache_capacity > 0 ? c->cfg.cache_capacity : n;
+    // the no-cache schedule (reuse off, or per-eye views) derives visible anchor i into line i
+    if ((!(c->cfg.flags & GSC_FLAG_REUSE) || nviews == 2) && C < n) C = n;
+    const int64_t max_gauss = C * k;
+    int64_t ntx = (c->cfg.max_width + kTile - 1) / kTile, nty = (c->cfg.max_height + kTile - 1) / kTile;
+    int64_t max_entries = 2 * max_gauss;
+    if (max_entries > (1ll << 31) - 1) max_entries = (1ll << 31) - 1;
+    int64_t max_pairs = c->cfg.max_pairs > 0 ? c->cfg.max_pairs : 24 * max_entries;
+    const int64_t pair_cap = (int64_t)1 << 28;
+    if (c->cfg.max_pairs == 0 && max_pairs > pair_cap) max_pairs = pair_cap;
+    if (max_pairs > (1ll << 31) - 1) max_pairs = (1ll << 31) - 1;
+
+    size_t& b = sc.bytes;
+    hipError_t e;
+#define A_(p, cnt)                                                         \
+    if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) {                       \
+        free_all(c);                                                       \
+        return fail(c, GSC_E_OOM, "gsc_load_anchors: device allocation"); \
+    }
+    A_(sc.posr, n); A_(sc.level, n); A_(sc.feat, n * kF); A_(sc.scale, n * 6); A_(sc.offsets, n * k * 3);
+    A_(sc.w32, L.total); A_(sc.wbf16, L.total); A_(sc.wfp8, L.total); A_(sc.wfp8_scale, L.scale_total);
+#undef A_
+    for (int vi = 0; vi < nviews; ++vi)
+        if (alloc_view(c, c->view[vi], n, C, k) != hipSuccess) {
+            free_all(c);
+            return fail(c, GSC_E_OOM, "gsc_load_anchors: view allocation");
+        }
+    if (alloc_raster(c, c->raster, max_entries, max_pairs, 2 * ntx * nty,
+                     (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0) != hipSuccess) {
+        free_all(c);
+        return fail(c, GSC_E_OOM, "gsc_load_anchors: raster allocation");
+    }
+    hipStream_t st = c->stream;
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.posr, posr.data(), n * sizeof(float4), hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.level, lev, n, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.feat, feat, n * kF * 4, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.scale, scl, n * 24, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.offsets, off, n * k * 12, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.w32, w32.data(), L.total * 4, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.wbf16, wbf.data(), L.total * 2, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.wfp8, w8.data(), L.total, hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(sc.wfp8_scale, w8s.data(), L.scale_total * 4, hipMemcpyHostToDevice, st));
+    for (int vi = 0; vi < nviews; ++vi) HIP_OR_FAIL(c, reset_view(c, c->view[vi], n, c->cfg.d_max));
+    HIP_OR_FAIL(c, hipStreamSynchronize(st));
+    c->nviews = nviews;
+    c->loaded = true;
+    c->have_pair = false;
+    c->derived = false;
+    return GSC_OK;
+}
+
+int gsc_set_camera_pair(gsc_ctx* c, const gsc_camera* left, const gsc_camera* right, double t_arrival) {
+    if (!c || !left || !right) return fail(c, GSC_E_INVALID_ARG, "gsc_set_camera_pair: null argument");
+    if (!valid_camera(*left) || !valid_camera(*right))
+        return fail(c, GSC_E_INVALID_ARG, "gsc_set_camera_pair: invalid camera");
+    if (left->width != right->width || left->height != right->height || left->fovx != right->fovx ||
+        left->fovy != right->fovy || left->znear != right->znear)
+        return fail(c, GSC_E_INVALID_ARG, "gsc_set_camera_pair: eyes must share intrinsics");
+    if (left->width > c->cfg.max_width || left->height > c->cfg.max_height)
+        return fail(c, GSC_E_INVALID_ARG, "gsc_set_camera_pair: image larger than max_width x max_height");
+    c->eye[0] = *left;
+    c->eye[1] = *right;
+    unified_camera(*left, *right, c->unified);
+    c->t_arrival = t_arrival;
+    c->have_pair = true;
+    return GSC_OK;
+}
+
+int gsc_derive(gsc_ctx* c) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_derive: null context");
+    if (!c->loaded) return fail(c, GSC_E_NOT_LOADED, "gsc_derive: no scene loaded");
+    if (!c->have_pair) return fail(c, GSC_E_NOT_LOADED, "gsc_derive: no camera pair set");
+    if ((c->cfg.flags & GSC_FLAG_PREDICTOR) && !c->pred_loaded)
+        return fail(c, GSC_E_NOT_LOADED, "gsc_derive: predictor flag set but no predictor loaded");
+    for (int vi = 0; vi < c->nviews; ++vi) {
+        DeriveArgs a;
+        a.sc = &c->scene;
+        a.v = &c->view[vi];
+        const gsc_camera& cam = c->nviews == 1 ? c->unified : c->eye[vi];
+        a.cam = derive_cam(cam, c->scene.d_ref);
+        a.precision = c->cfg.precision;
+        a.flags = c->cfg.flags;
+        if (c->nviews == 2) a.flags &= ~(GSC_FLAG_REUSE | GSC_FLAG_PREDICTOR);
+        a.d_max = c->cfg.d_max;
+        a.guide = c->cfg.guide;
+        a.pred_thr = c->cfg.predictor_threshold;
+        a.pred_w = c->pred_w;
+        a.pred_wbf = c->pred_wbf;
+        a.collect = c->collect_features;
+        hipError_t e = derive_frame(a, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "gsc_derive");
+        c->view[vi].t += 1;
+    }
+    c->frame = c->view[0].t - 1;
+    c->derived = true;
+    return GSC_OK;
+}
+
+int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left_T, float* right_T) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_render_stereo: null context");
+    if (!left_chw || !right_chw) return fail(c, GSC_E_INVALID_ARG, "gsc_render_stereo: null output");
+    if (!c->derived) return fail(c, GSC_E_NOT_LOADED, "gsc_render_stereo: call gsc_derive first");
+    SegTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    tab.n = 2;
+    int tiles = 0;
+    float* outs[2] = {left_chw, right_chw};
+    float* Ts[2] = {left_T, right_T};
+    for (int e = 0; e < 2; ++e) {
+        View& v = c->view[c->nviews == 1 ? 0 : e];
+        Seg& s = tab.s[e];
+        s.L0 = v.L0; s.L1 = v.L1; s.L2 = v.L2; s.L3 = v.L3; s.G = v.G; s.nG = &v.cnt->n_gauss; s.nG_host = 0;
+        seg_camera(s, c->eye[e]);
+        s.tile_base = tiles;
+        tiles += s.ntx * s.nty;
+        s.out_rgb = outs[e];
+        s.out_T = Ts[e];
+        s.out_nc = nullptr;
+    }
+    tab.total_tiles = tiles;
+    hipError_t e = raster_batch(tab, c->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "gsc_render_stereo");
+    c->last_tab = tab;
+    c->rendered = true;
+    c->explicit_render = false;
+    return GSC_OK;
+}
+
+int gsc_render_gaussians(gsc_ctx* c, const gsc_gaussians* g, const gsc_camera* cam, float* out_chw, float* out_T,
+                         int32_t* out_nc) {
+    if (!c || !g || !cam || !out_chw) return fail(c, GSC_E_INVALID_ARG, "gsc_render_gaussians: null argument");
+    if (g->n < 0 || (g->n > 0 && (!g->mu || !g->cov || !g->rgb || !g->alpha)))
+        return fail(c, GSC_E_INVALID_ARG, "gsc_render_gaussians: bad Gaussian arrays");
+    if (!valid_camera(*cam) || cam->width > c->cfg.max_width || cam->height > c->cfg.max_height)
+        return fail(c, GSC_E_INVALID_ARG, "gsc_render_gaussians: invalid camera or image too large");
+    if (g->n > (1ll << 30)) return fail(c, GSC_E_INVALID_ARG, "gsc_render_gaussians: too many Gaussians");
+    int64_t ntiles = (int64_t)((cam->width + kTile - 1) / kTile) * ((cam->height + kTile - 1) / kTile);
+    hipError_t e = explicit_gaussians(c, *g, ntiles);
+    if (e != hipSuccess) return hip_fail(c, e, "gsc_render_gaussians");
+    SegTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    tab.n = 1;
+    Seg& s = tab.s[0];
+    s.L0 = c->xg.L0; s.L1 = c->xg.L1; s.L2 = c->xg.L2; s.L3 = c->xg.L3; s.G = nullptr; s.nG = nullptr;
+    s.nG_host = (int32_t)g->n;
+    seg_camera(s, *cam);
+    s.tile_base = 0;
+    s.out_rgb = out_chw; s.out_T = out_T; s.out_nc = out_nc;
+    tab.total_tiles = s.ntx * s.nty;
+    e = raster_batch(tab, c->xraster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "gsc_render_gaussians");
+    c->last_tab = tab;
+    c->rendered = true;
+    c->explicit_render = true;
+    return GSC_OK;
+}
+
+int gsc_sync(gsc_ctx* c) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_sync: null context");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    int of = 0;
+    if (c->rendered) {
+        Raster& R = c->explicit_render ? c->xraster : c->raster;
+        HIP_OR_FAIL(c, hipMemcpy(R.cnt_host, R.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
+        of |= R.cnt_host->overflow & 1;
+    }
+    if (c->loaded && c->derived) {
+        HIP_OR_FAIL(c, hipMemcpy(c->view[0].cnt_host, c->view[0].cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+        of |= c->view[0].cnt_host->overflow & 2;
+    }
+    if (of) return fail(c, GSC_E_CAPACITY, of & 1 ? "tile-pair capacity exceeded" : "cache capacity exceeded");
+    return GSC_OK;
+}
+
+int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
+    if (!c || !st) return fail(c, GSC_E_INVALID_ARG, "gsc_get_stats: null argument");
+    std::memset(st, 0, sizeof(*st));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (!c->loaded) return GSC_OK;
+    HIP_OR_FAIL(c, hipMemcpy(c->view[0].cnt_host, c->view[0].cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(c, hipMemcpy(c->raster.cnt_host, c->raster.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
+    const Counters& k = *c->view[0].cnt_host;
+    const RasterCounters& r = *c->raster.cnt_host;
+    st->frame = c->frame;
+    st->n_visible = k.n_visible;
+    st->n_miss = k.n_miss;
+    st->n_gauss = k.n_gauss;
+    st->n_pairs[0] = r.seg_pairs[0];
+    st->n_pairs[1] = r.seg_pairs[1];
+    st->n_evicted = k.n_evict;
+    st->depth_used = k.depth_used;
+    st->depth_next = k.depth;
+    st->overflow = (r.overflow & 1) | (k.overflow & 2);
+    size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
+    st->device_bytes = (int64_t)bytes;
+    return GSC_OK;
+}
+
+int gsc_reset_cache(gsc_ctx* c) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_reset_cache: null context");
+    if (!c->loaded) return fail(c, GSC_E_NOT_LOADED, "gsc_reset_cache: no scene loaded");
+    for (int vi = 0; vi < c->nviews; ++vi) HIP_OR_FAIL(c, reset_view(c, c->view[vi], c->scene.n, c->cfg.d_max));
+    c->derived = false;
+    return GSC_OK;
+}
+
+int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_t* n) {
+    if (!c || !n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: null argument");
+    if (!c->loaded && !c->explicit_render) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing to copy");
+    Raster& R = c->explicit_render ? c->xraster : c->raster;
+    const bool view_item = what <= GSC_DBG_DERIVED || what == GSC_DBG_DEPTH;
+    if (view_item && !c->loaded) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: no scene loaded");
+    if (eye < 0 || eye > 1) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: eye must be 0 or 1");
+    if (cap > 0 && !dst) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: null destination");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    View& v = c->view[c->nviews == 1 ? 0 : eye];
+    Counters kz = {};
+    if (c->loaded) {
+        HIP_OR_FAIL(c, hipMemcpy(v.cnt_host, v.cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+        kz = *v.cnt_host;
+    }
+    RasterCounters rz = {};
+    if (c->rendered) {
+        HIP_OR_FAIL(c, hipMemcpy(R.cnt_host, R.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
+        rz = *R.cnt_host;
+    }
+    const Counters& k = kz;
+    const RasterCounters& r = rz;
+    int64_t count = 0;
+    std::vector<uint8_t> tmp;
+    switch (what) {
+        case GSC_DBG_VISIBLE:
+        case GSC_DBG_MISSES: {
+            count = what == GSC_DBG_VISIBLE ? k.n_visible : k.n_miss;
+            int64_t m = count < cap ? count : cap;
+            if (m > 0) {
+                if (what == GSC_DBG_VISIBLE) {
+                    HIP_OR_FAIL(c, hipMemcpy(dst, v.visible, m * 4, hipMemcpyDeviceToHost));
+                } else {
+                    std::vector<int32_t> pos(m), vis(k.n_visible);
+                    HIP_OR_FAIL(c, hipMemcpy(pos.data(), v.misses, m * 4, hipMemcpyDeviceToHost));
+                    HIP_OR_FAIL(c, hipMemcpy(vis.data(), v.visible, (size_t)k.n_visible * 4, hipMemcpyDeviceToHost));
+                    for (int64_t i = 0; i < m; ++i) ((int32_t*)dst)[i] = vis[pos[i]];
+                }
+            }
+            break;
+        }
+        case GSC_DBG_GAUSS:
+        case GSC_DBG_DERIVED: {
+            count = k.n_gauss;
+            int64_t m = count < cap ? count : cap;
+            if (m <= 0) break;
+            std::vector<int32_t> G(m), vslot(k.n_visible);
+            HIP_OR_FAIL(c, hipMemcpy(G.data(), v.G, m * 4, hipMemcpyDeviceToHost));
+            if (what == GSC_DBG_GAUSS) {
+                HIP_OR_FAIL(c, hipMemcpy(vslot.data(), v.vslot, (size_t)k.n_visible * 4, hipMemcpyDeviceToHost));
+                // cache entry (line * k + j) -> (visible position * k + j)
+                std::vector<int64_t> pos_of_line;
+                int64_t kk = c->scene.k;
+                std::vector<int32_t> inv((size_t)v.C, -1);
+                for (int64_t i = 0; i < k.n_visible; ++i)
+                    if (vslot[i] >= 0) inv[vslot[i]] = (int32_t)i;
+                for (int64_t i = 0; i < m; ++i) ((int32_t*)dst)[i] = (int32_t)(inv[G[i] / kk] * kk + G[i] % kk);
+            } else {
+                int64_t E = v.C * c->scene.k;
+                std::vector<float4> l0(E), l1(E), l2(E);
+                std::vector<float> l3(E);
+                HIP_OR_FAIL(c, hipMemcpy(l0.data(), v.L0, E * 16, hipMemcpyDeviceToHost));
+                HIP_OR_FAIL(c, hipMemcpy(l1.data(), v.L1, E * 16, hipMemcpyDeviceToHost));
+                HIP_OR_FAIL(c, hipMemcpy(l2.data(), v.L2, E * 16, hipMemcpyDeviceToHost));
+                HIP_OR_FAIL(c, hipMemcpy(l3.data(), v.L3, E * 4, hipMemcpyDeviceToHost));
+                float* o = (float*)dst;
+                for (int64_t i = 0; i < m; ++i) {
+                    int64_t e = G[i];
+                    float row[13] = {l0[e].x, l0[e].y, l0[e].z, l1[e].x, l1[e].y, l1[e].z, l1[e].w,
+                                     l2[e].x, l2[e].y, l2[e].z, l2[e].w, l3[e], l0[e].w};
+                    std::memcpy(o + 13 * i, row, sizeof(row));
+                }
+            }
+            break;
+        }
+        case GSC_DBG_PAIRS: {
+            if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
+            const SegTable& tab = c->last_tab;
+            if (eye >= tab.n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: no such eye");
+            int32_t total = r.n_pairs < R.max_pairs ? r.n_pairs : (int32_t)R.max_pairs;
+            std::vector<int32_t> ranges(2 * (size_t)tab.total_tiles);
+            HIP_OR_FAIL(c, hipMemcpy(ranges.data(), R.ranges, ranges.size() * 4, hipMemcpyDeviceToHost));
+            const Seg& s = tab.s[eye];
+            int64_t lo = -1, hi = -1;
+            for (int64_t t = s.tile_base; t < s.tile_base + (int64_t)s.ntx * s.nty; ++t)
+                if (ranges[2 * t + 1] > ranges[2 * t]) {
+                    if (lo < 0) lo = ranges[2 * t];
+                    hi = ranges[2 * t + 1];
+                }
+            count = lo < 0 ? 0 : hi - lo;
+            int64_t m = count < cap ? count : cap;
+            if (m <= 0) break;
+            std::vector<uint32_t> val(m);
+            HIP_OR_FAIL(c, hipMemcpy(val.data(), R.pval[R.sorted_buf] + lo, m * 4,
+                                     hipMemcpyDeviceToHost));
+            std::vector<int32_t> tile_of(m);
+            for (int64_t t = s.tile_base; t < s.tile_base + (int64_t)s.ntx * s.nty; ++t)
+                for (int64_t i = ranges[2 * t]; i < ranges[2 * t + 1]; ++i)
+                    if (i - lo < m) tile_of[i - lo] = (int32_t)(t - s.tile_base);
+            int32_t* o = (int32_t*)dst;
+            for (int64_t i = 0; i < m; ++i) {
+                o[2 * i] = tile_of[i];
+                o[2 * i + 1] = (int32_t)(val[i] - (uint32_t)r.entry_base[eye]);
+            }
+            (void)total;
+            break;
+        }
+        case GSC_DBG_RANGES: {
+            if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
+            const SegTable& tab = c->last_tab;
+            if (eye >= tab.n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: no such eye");
+            const Seg& s = tab.s[eye];
+            count = (int64_t)s.ntx * s.nty;
+            int64_t m = count < cap ? count : cap;
+            if (m <= 0) break;
+            std::vector<int32_t> rg(2 * m);
+            HIP_OR_FAIL(c, hipMemcpy(rg.data(), R.ranges + 2 * (int64_t)s.tile_base, 2 * m * 4,
+                                     hipMemcpyDeviceToHost));
+            int32_t base = -1;
+            for (int64_t t = 0; t < count && t < m; ++t)
+                if (rg[2 * t + 1] > rg[2 * t]) { base = rg[2 * t]; break; }
+            int32_t* o = (int32_t*)dst;
+            for (int64_t t = 0; t < m; ++t) {
+                bool empty = rg[2 * t + 1] <= rg[2 * t];
+                o[2 * t] = empty ? 0 : rg[2 * t] - base;
+                o[2 * t + 1] = empty ? 0 : rg[2 * t + 1] - base;
+            }
+            break;
+        }
+        case GSC_DBG_PREPROC: {
+            if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
+            if (eye >= c->last_tab.n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: no such eye");
+            int64_t b0 = r.entry_base[eye], b1 = r.entry_base[eye + 1];
+            count = b1 - b0;
+            int64_t m = count < cap ? count : cap;
+            if (m <= 0) break;
+            std::vector<float4> A(m), B(m);
+            std::vector<uint32_t> nt(m), dk(m);
+            HIP_OR_FAIL(c, hipMemcpy(A.data(), R.recA + b0, m * 16, hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(c, hipMemcpy(B.data(), R.recB + b0, m * 16, hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(c, hipMemcpy(nt.data(), R.ntiles + b0, m * 4, hipMemcpyDeviceToHost));
+            float* o = (float*)dst;
+            for (int64_t i = 0; i < m; ++i) {
+                float row[8] = {A[i].x, A[i].y, A[i].z, A[i].w, B[i].x, B[i].y, 0.f, (float)nt[i]};
+                std::memcpy(o + 8 * i, row, sizeof(row));
+            }
+            break;
+        }
+        case GSC_DBG_DEPTH: {
+            count = 1;
+            if (cap >= 1) ((int32_t*)dst)[0] = k.depth;
+            break;
+        }
+        default:
+            return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: unknown item");
+    }
+    *n = count;
+    return GSC_OK;
+}
+
+}  // extern "C"

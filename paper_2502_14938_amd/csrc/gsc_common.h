@@ -1,0 +1,215 @@
+// Internal declarations shared by the libgscache translation units.
+// Not part of the public ABI (include/gscache.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gscache.h"
+
+namespace gsc {
+
+constexpr int kTile = 16;             // 16x16 pixel tiles
+constexpr int kBlendThreads = 256;    // one thread per pixel of a tile
+constexpr int kMaxSeg = 16;           // (viewer, eye) images per raster batch
+constexpr int kGridBlocks = 2048;     // fixed grid of the grid-stride kernels
+constexpr int kScanBlocks = 1024;     // blocks of the device-wide scan
+constexpr int kSortBlocks = 512;      // blocks of each radix pass
+constexpr int kF = 32;                // feature length the kernels are built for
+constexpr int kH = 32;                // MLP hidden width the kernels are built for
+constexpr int kMaxK = 16;             // max neural Gaussians per anchor
+constexpr int kPredW = 64;            // reuse predictor width
+constexpr int kPredIn = 6;            // reuse predictor features
+
+// Device counters of one view (viewer).  Every frame-dependent size lives
+// here so that a frame never waits on the host.
+struct Counters {
+    int32_t n_visible;
+    int32_t n_miss;
+    int32_t n_need;      // misses without a line
+    int32_t n_free;      // free lines after invalidation
+    int32_t n_gauss;
+    int32_t n_evict;
+    int32_t depth;       // d_t for the next frame to run
+    int32_t depth_used;  // d_t applied by the last frame
+    int32_t n_cand;      // reuse candidates (predictor inputs)
+    int32_t overflow;    // bit1: cache capacity
+    int32_t evict_short; // lines still to evict
+    int32_t evict_thr;   // last_used threshold of partial eviction bin
+    int32_t evict_left;  // evictions taken from the threshold bin
+    int32_t pad[3];
+};
+
+// Device counters of one raster batch.
+struct RasterCounters {
+    int32_t n_entries;            // total (segment, Gaussian) entries
+    int32_t entry_base[kMaxSeg + 1];
+    int32_t n_pairs;              // total tile pairs (all segments)
+    int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
+    int32_t overflow;             // bit0: pair capacity
+    int32_t pad[2];
+};
+
+// One (viewer, eye) image of a raster batch; passed by value in kernel args.
+struct Seg {
+    const float4* L0;   // mu.xyz, alpha      [entries of the view's cache]
+    const float4* L1;   // cov xx xy xz yy
+    const float4* L2;   // cov yz zz, r, g
+    const float* L3;    // b
+    const int32_t* G;   // render buffer: cache entry per Gaussian (nullptr = identity)
+    const int32_t* nG;  // device count of G (nullptr = nG_host)
+    int32_t nG_host;
+    int32_t W, H, ntx, nty;
+    int32_t tile_base;  // first global tile id of this image
+    float R[9];
+    float pos[3];
+    float fx, fy, cx, cy, limx, limy, znear;
+    float* out_rgb;     // [3,H,W]
+    float* out_T;       // [H,W] or nullptr
+    int32_t* out_nc;    // [H,W] or nullptr
+};
+
+struct SegTable {
+    int32_t n;
+    int32_t total_tiles;
+    Seg s[kMaxSeg];
+};
+
+// Unified-camera constants for the derive stage (FP32, computed in FP64).
+struct DeriveCam {
+    float pos[3];        // p_u
+    float planes[5][4];  // inward world planes n.x + w >= -radius keeps
+    float d_ref;
+    float fx;            // unified focal length (predictor feature)
+};
+
+// Scene on the device (shared by views).
+struct Scene {
+    int64_t n = 0;
+    int k = 0;
+    float d_ref = 0.f;
+    int l_max = 0;
+    float4* posr = nullptr;     // x, y, z, radius
+    uint8_t* level = nullptr;
+    float* feat = nullptr;      // [n, F]
+    float* scale = nullptr;     // [n, 6]
+    float* offsets = nullptr;   // [n, k, 3]
+    // weights, packed per head h: W1 [H][F+3], b1 [H], W2 [c k][H], b2 [c k]
+    float* w32 = nullptr;
+    uint16_t* wbf16 = nullptr;  // same layout, bf16 (biases stay in w32)
+    uint8_t* wfp8 = nullptr;    // same layout, e4m3fn
+    float* wfp8_scale = nullptr;// per output row (W1 rows then W2 rows per head)
+    size_t bytes = 0;
+};
+
+// Offsets of each head's arrays inside the packed weight buffer.
+struct WeightLayout {
+    int W1[3], b1[3], W2[3], b2[3], rows1[3], rows2[3];
+    int total;
+    int scale_W1[3], scale_W2[3], scale_total;
+};
+WeightLayout weight_layout(int k);
+
+// Per-viewer derive state: cache lines and the render buffer.
+struct View {
+    int64_t C = 0;              // cache lines
+    int64_t max_gauss = 0;
+    int32_t* slot_of = nullptr; // [n] line of each anchor or -1
+    int32_t* line_anchor = nullptr, *line_tau = nullptr, *line_last = nullptr;  // [C]
+    float4* L0 = nullptr, *L1 = nullptr, *L2 = nullptr;  // [C*k]
+    float* L3 = nullptr;
+    float* pu_hist = nullptr;   // [64][4] unified camera centre per frame (t mod 64)
+    int32_t* visible = nullptr; // [n]
+    int32_t* vslot = nullptr;   // [n] line per visible position
+    uint32_t* tmp_a = nullptr;  // [max(n, C)] scratch
+    uint32_t* tmp_b = nullptr;  // [max(n, C)] scratch
+    uint32_t* tmp_c = nullptr;  // [max(n, C)] scratch
+    uint32_t* tmp_d = nullptr;  // [max(n, C)] scratch
+    uint32_t* evict_hist = nullptr;  // [64]
+    int32_t* evict_scan_n = nullptr; // [1] count for the eviction scans
+    int32_t* misses = nullptr;  // [n] visible positions of misses
+    int32_t* free_list = nullptr; // [C]
+    int32_t* G = nullptr;       // [max_gauss]
+    uint32_t* block_sums = nullptr;  // scan scratch
+    float* cand_feat = nullptr; // [n, 6] predictor features
+    int32_t* cand_id = nullptr; // [n]
+    Counters* cnt = nullptr;
+    Counters* cnt_host = nullptr;  // pinned mirror
+    int64_t t = 0;
+    size_t bytes = 0;
+};
+
+// Raster batch buffers.
+struct Raster {
+    int64_t max_entries = 0, max_pairs = 0, max_tiles = 0;
+    float4* recA = nullptr;     // mean2d.xy, conic a b
+    float4* recB = nullptr;     // conic c, alpha, r, g
+    float* recC = nullptr;      // b
+    uint32_t* ntiles = nullptr; // per entry
+    uint2* rect = nullptr;      // per entry: tile x0|x1<<16, y0|y1<<16
+    int32_t* n_sort = nullptr;  // [1] pairs to sort (clamped to capacity)
+    uint32_t* dkey[2] = {nullptr, nullptr};  // depth keys (double buffer)
+    uint32_t* dval[2] = {nullptr, nullptr};  // entry ids
+    uint32_t* offs = nullptr;   // pair offset per depth rank
+    uint32_t* pkey[2] = {nullptr, nullptr};  // global tile id
+    uint32_t* pval[2] = {nullptr, nullptr};  // entry id
+    uint64_t* pkey64[2] = {nullptr, nullptr};// full-key mode
+    int32_t* ranges = nullptr;  // [max_tiles][2]
+    uint32_t* hist = nullptr;   // [256 * kSortBlocks]
+    uint32_t* block_sums = nullptr;
+    RasterCounters* cnt = nullptr;
+    RasterCounters* cnt_host = nullptr;
+    int sorted_buf = 0;         // which pkey/pval buffer holds the sorted pairs
+    size_t bytes = 0;
+};
+
+// ----------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns hipSuccess or the launch error.
+
+// Device-wide exclusive scan of n uint32 values (n from *n_dev if non-null),
+// writing exclusive prefixes to out and the total to *total (device).
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int64_t n_host, int32_t* total,
+                    uint32_t* block_sums, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs over bits [bit0, bit1).
+// Count from *n_dev (device) or n_host.  Returns in *which the buffer index
+// (0/1) holding the result.  hist: [256 * kSortBlocks], block_sums: scan scratch.
+hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
+hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
+
+// Derive stage of one view.
+struct DeriveArgs {
+    const Scene* sc;
+    View* v;
+    DeriveCam cam;
+    int precision;
+    uint32_t flags;
+    int d_max;
+    int guide;
+    float pred_thr;
+    const float* pred_w;      // predictor params (device fp32)
+    const uint16_t* pred_wbf; // bf16 copy for inference
+    int collect;              // store reuse-candidate features for label collection
+};
+hipError_t derive_frame(const DeriveArgs& a, hipStream_t st);
+
+// Raster stage of a batch of segments.
+hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st);
+
+// Fill a segment's camera fields from a public camera.
+void seg_camera(Seg& s, const gsc_camera& c);
+
+// Predictor kernels.
+hipError_t pred_forward_bwd(const float* w, const float* X, const float* y, int n, float pos_weight, float* grads,
+                            float* loss, hipStream_t st);
+hipError_t pred_adam(float* w, const float* grads, float* m, float* v, int nparams, int step, float lr,
+                     hipStream_t st);
+hipError_t pred_infer(const uint16_t* wbf, const float* w32, const float* X, int n, float* p, hipStream_t st);
+hipError_t pred_to_bf16(const float* w, uint16_t* wbf, int n, hipStream_t st);
+
+}  // namespace gsc

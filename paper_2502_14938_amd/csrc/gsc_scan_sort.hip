@@ -1,0 +1,281 @@
+// Device-wide primitives: exclusive scan and stable LSD radix sort.
+//
+// Both use a fixed grid whose blocks own contiguous chunks of the input and
+// read the element count from device memory, so a frame never needs a host
+// round trip to size a launch.  Wave64 throughout: wave scans use
+// __shfl_up over 64 lanes, digit ranking uses 64-bit ballots.
+#include "gsc_common.h"
+
+namespace gsc {
+
+namespace {
+
+constexpr int NT = 256;        // threads per block (4 waves)
+constexpr int SCAN_TILE = 1024;  // elements per scan step (4 per thread)
+constexpr int SORT_IPT = 8;      // elements per thread per sort step
+constexpr int SORT_TILE = NT * SORT_IPT;
+constexpr int SORT_WSEG = SORT_TILE / 4;  // elements per wave per step
+
+__device__ __forceinline__ int64_t count_of(const int32_t* n_dev, int64_t n_host) {
+    return n_dev ? (int64_t)(*n_dev) : n_host;
+}
+
+__device__ __forceinline__ void chunk_of(int64_t n, int64_t align, int64_t& b0, int64_t& b1) {
+    int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    per = (per + align - 1) / align * align;
+    b0 = (int64_t)blockIdx.x * per;
+    b1 = b0 + per < n ? b0 + per : n;
+}
+
+// Exclusive scan across the 256 threads of a block (one value each).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        uint32_t s = wsum[i];
+        pre += i < w ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* wsum) {
+    uint32_t t;
+    block_excl_scan(v, wsum, t);
+    return t;
+}
+
+// ------------------------------------------------------------------ scan
+
+__global__ __launch_bounds__(NT) void k_scan_reduce(const uint32_t* __restrict__ in, const int32_t* n_dev,
+                                                    int64_t n_host, uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t wsum[NT / 64];
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, n_host), SCAN_TILE, b0, b1);
+    uint32_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) s += in[i];
+    uint32_t t = block_sum(s, wsum);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
+}
+
+// One block scans the per-block sums (nb <= 4 * NT).
+__global__ __launch_bounds__(NT) void k_scan_top(uint32_t* __restrict__ block_sums, int nb, int32_t* total) {
+    __shared__ uint32_t wsum[NT / 64];
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int i = threadIdx.x * 4 + r;
+        v[r] = i < nb ? block_sums[i] : 0u;
+        s += v[r];
+    }
+    uint32_t tot;
+    uint32_t e = block_excl_scan(s, wsum, tot);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int i = threadIdx.x * 4 + r;
+        if (i < nb) block_sums[i] = e;
+        e += v[r];
+    }
+    if (threadIdx.x == 0 && total) *total = (int32_t)tot;
+}
+
+__global__ __launch_bounds__(NT) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                  const int32_t* n_dev, int64_t n_host,
+                                                  const uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t wsum[NT / 64];
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, n_host), SCAN_TILE, b0, b1);
+    uint32_t carry = block_sums[blockIdx.x];
+    for (int64_t base = b0; base < b1; base += SCAN_TILE) {
+        uint32_t v[4], s = 0;
+        int64_t i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v[r] = i0 + r < b1 ? in[i0 + r] : 0u;
+            s += v[r];
+        }
+        uint32_t tot;
+        uint32_t e = carry + block_excl_scan(s, wsum, tot);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (i0 + r < b1) out[i0 + r] = e;
+            e += v[r];
+        }
+        carry += tot;
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit(K key, int shift, uint32_t mask) {
+    return (uint32_t)(key >> shift) & mask;
+}
+
+// Lanes of the wave holding the same digit (among `active`), from one
+// ballot per digit bit.
+__device__ __forceinline__ uint64_t peers_of(uint32_t d, bool valid, int bits) {
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+        bool bit = (d >> b) & 1u;
+        uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+template <typename K>
+__global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ keys, const int32_t* n_dev, int64_t n_host,
+                                                   int shift, int bits, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t nbins = 1u << bits, mask = nbins - 1u;
+    for (int i = threadIdx.x; i < 4 * 256; i += NT) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, n_host), SORT_TILE, b0, b1);
+    for (int64_t base = b0; base < b1; base += NT) {
+        int64_t i = base + threadIdx.x;
+        bool valid = i < b1;
+        uint32_t d = valid ? digit(keys[i], shift, mask) : 0u;
+        uint64_t peers = peers_of(d, valid, bits);
+        if (valid) {
+            uint64_t below = peers & ((1ull << lane) - 1ull);
+            if (below == 0ull) atomicAdd(&h[w][d], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nbins; d += NT)
+        hist[(int64_t)d * gridDim.x + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+template <typename K>
+__global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                      K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                      const int32_t* n_dev, int64_t n_host, int shift, int bits,
+                                                      const uint32_t* __restrict__ offs) {
+    __shared__ uint32_t cnt[4][256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t texcl[256];
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ K skey[SORT_TILE];
+    __shared__ uint32_t sval[SORT_TILE];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t nbins = 1u << bits, mask = nbins - 1u;
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, n_host), SORT_TILE, b0, b1);
+    if (b0 >= b1) return;
+    if (threadIdx.x < nbins) run[threadIdx.x] = offs[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int64_t base = b0; base < b1; base += SORT_TILE) {
+        for (int i = threadIdx.x; i < 4 * 256; i += NT) (&cnt[0][0])[i] = 0u;
+        __syncthreads();
+        K key[SORT_IPT];
+        uint32_t val[SORT_IPT], dg[SORT_IPT], lr[SORT_IPT];
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            int64_t i = base + w * SORT_WSEG + r * 64 + lane;
+            bool valid = i < b1;
+            key[r] = valid ? kin[i] : (K)0;
+            val[r] = valid ? vin[i] : 0u;
+            uint32_t d = valid ? digit(key[r], shift, mask) : 0u;
+            uint64_t peers = peers_of(d, valid, bits);
+            // every peer reads the wave's running count before the group's
+            // first lane advances it (one wave, in-order LDS accesses)
+            uint32_t c = valid ? cnt[w][d] : 0u;
+            uint32_t rank = (uint32_t)__popcll(peers & lt);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && rank == 0u) cnt[w][d] = c + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            dg[r] = valid ? d : 0xffffffffu;
+            lr[r] = c + rank;
+        }
+        __syncthreads();
+        uint32_t tot_d = 0;
+        if (threadIdx.x < nbins) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t c = cnt[q][threadIdx.x];
+                cnt[q][threadIdx.x] = s;
+                s += c;
+            }
+            tot_d = s;
+        }
+        uint32_t all;
+        uint32_t ex = block_excl_scan(tot_d, wsum, all);
+        texcl[threadIdx.x] = ex;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            if (dg[r] != 0xffffffffu) {
+                uint32_t lp = texcl[dg[r]] + cnt[w][dg[r]] + lr[r];
+                skey[lp] = key[r];
+                sval[lp] = val[r];
+            }
+        }
+        __syncthreads();
+        int n_tile = (int)(b1 - base < SORT_TILE ? b1 - base : SORT_TILE);
+        for (int i = threadIdx.x; i < n_tile; i += NT) {
+            K k = skey[i];
+            uint32_t d = digit(k, shift, mask);
+            uint32_t pos = run[d] + (uint32_t)i - texcl[d];
+            kout[pos] = k;
+            vout[pos] = sval[i];
+        }
+        __syncthreads();
+        if (threadIdx.x < nbins) run[threadIdx.x] += tot_d;
+        __syncthreads();
+    }
+}
+
+template <typename K>
+hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0, int bit1,
+                           uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
+    int cur = 0;
+    for (int shift = bit0; shift < bit1; shift += 8) {
+        int bits = bit1 - shift < 8 ? bit1 - shift : 8;
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3(kSortBlocks), dim3(NT), 0, st, keys[cur], n_dev, n_host, shift,
+                           bits, hist);
+        hipError_t e = scan_u32(hist, hist, nullptr, (int64_t)(1 << bits) * kSortBlocks, nullptr, block_sums, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kSortBlocks), dim3(NT), 0, st, keys[cur], vals[cur],
+                           keys[cur ^ 1], vals[cur ^ 1], n_dev, n_host, shift, bits, hist);
+        cur ^= 1;
+    }
+    *which = cur;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int64_t n_host, int32_t* total,
+                    uint32_t* block_sums, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(NT), 0, st, in, n_dev, n_host, block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(NT), 0, st, block_sums, kScanBlocks, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(NT), 0, st, in, out, n_dev, n_host, block_sums);
+    return hipGetLastError();
+}
+
+hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
+    return radix_sort_impl<uint32_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st);
+}
+
+hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
+    return radix_sort_impl<uint64_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st);
+}
+
+}  // namespace gsc
