@@ -9,6 +9,7 @@
 
 #include "gsc_common.h"
 #include "gsc_ctx.h"
+#include "gsc_derive_mfma.h"
 
 using namespace gsc;
 
@@ -31,39 +32,6 @@ int hip_fail(gsc_ctx* c, hipError_t e, const char* where) {
         hipError_t e_ = (x);                                \
         if (e_ != hipSuccess) return hip_fail(c, e_, #x);   \
     } while (0)
-
-// ------------------------------------------------------------ conversions
-
-uint16_t f32_to_bf16(float x) {
-    uint32_t u;
-    std::memcpy(&u, &x, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
-}
-
-// OCP float8 e4m3fn encoding, round to nearest even, saturating at 448.
-uint8_t f32_to_e4m3(float x) {
-    uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
-    double a = std::fabs((double)x);
-    if (a == 0.0) return sign;
-    if (a >= 448.0) return sign | 0x7e;
-    int e;
-    std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
-    int ex = e - 1;     // a in [2^ex, 2^(ex+1))
-    if (ex < -6) {      // subnormal: multiples of 2^-9
-        double m = std::nearbyint(a / std::ldexp(1.0, -9));
-        return sign | (uint8_t)m;  // m == 8 encodes 2^-6 (exponent field 1)
-    }
-    double m = std::nearbyint(a / std::ldexp(1.0, ex - 3));  // in [8, 16]
-    if (m >= 16.0) {
-        m = 8.0;
-        ++ex;
-    }
-    int field = ex + 7;
-    int mant = (int)m - 8;
-    if (field > 15 || (field == 15 && mant == 7)) return sign | 0x7e;
-    return sign | (uint8_t)((field << 3) | mant);
-}
 
 // --------------------------------------------------------- unified camera
 // Binocular stereo de-redundancy (Section 4, eqs. 5-6), in double precision.
@@ -192,8 +160,8 @@ hipError_t alloc_raster(gsc_ctx* c, Raster& r, int64_t max_entries, int64_t max_
     r.max_tiles = max_tiles;
     hipError_t e;
 #define A_(p, cnt) if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) return e
-    A_(r.recA, max_entries); A_(r.recB, max_entries); A_(r.recC, max_entries); A_(r.ntiles, max_entries);
-    A_(r.rect, max_entries); A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
+    A_(r.rec, 3 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
+    A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
     if (full_key) { A_(r.pkey64[0], max_pairs); A_(r.pkey64[1], max_pairs); }
@@ -361,33 +329,6 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
     std::vector<float4> posr(n);
     for (int64_t a = 0; a < n; ++a) posr[a] = make_float4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], rad[a]);
 
-    WeightLayout L = weight_layout(k);
-    std::vector<float> w32(L.total, 0.f);
-    std::vector<uint16_t> wbf(L.total, 0);
-    std::vector<uint8_t> w8(L.total, 0);
-    std::vector<float> w8s(L.scale_total, 1.f);
-    const int cH[3] = {1, 3, 7};
-    for (int h = 0; h < 3; ++h) {
-        std::memcpy(&w32[L.W1[h]], mlp->W1[h], sizeof(float) * kH * (kF + 3));
-        std::memcpy(&w32[L.b1[h]], mlp->b1[h], sizeof(float) * kH);
-        std::memcpy(&w32[L.W2[h]], mlp->W2[h], sizeof(float) * cH[h] * k * kH);
-        std::memcpy(&w32[L.b2[h]], mlp->b2[h], sizeof(float) * cH[h] * k);
-        struct M { int off, rows, cols, soff; } mats[2] = {{L.W1[h], kH, kF + 3, L.scale_W1[h]},
-                                                          {L.W2[h], cH[h] * k, kH, L.scale_W2[h]}};
-        for (auto& m : mats)
-            for (int r = 0; r < m.rows; ++r) {
-                float amax = 0.f;
-                for (int q = 0; q < m.cols; ++q) amax = std::fmax(amax, std::fabs(w32[m.off + r * m.cols + q]));
-                float s = amax > 0.f ? amax / 448.0f : 1.0f;
-                w8s[m.soff + r] = s;
-                for (int q = 0; q < m.cols; ++q) {
-                    float wv = w32[m.off + r * m.cols + q];
-                    wbf[m.off + r * m.cols + q] = f32_to_bf16(wv);
-                    w8[m.off + r * m.cols + q] = f32_to_e4m3(wv / s);
-                }
-            }
-    }
-
     const int nviews = (c->cfg.flags & GSC_FLAG_DEREDUNDANCY) ? 1 : 2;
     int64_t C = c->cfg.cache_capacity > 0 ? c->cfg.cache_capacity : n;
     // the no-cache schedule (reuse off, or per-eye views) derives visible anchor i into line i
@@ -409,7 +350,12 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
         return fail(c, GSC_E_OOM, "gsc_load_anchors: device allocation"); \
     }
     A_(sc.posr, n); A_(sc.level, n); A_(sc.feat, n * kF); A_(sc.scale, n * 6); A_(sc.offsets, n * k * 3);
-    A_(sc.w32, L.total); A_(sc.wbf16, L.total); A_(sc.wfp8, L.total); A_(sc.wfp8_scale, L.scale_total);
+    HostFrags hf = pack_frags(*mlp, k);
+    A_(sc.fr_l1_f32, hf.l1_f32.size()); A_(sc.fr_l2_f32, hf.l2_f32.size());
+    A_(sc.fr_l1_bf16, hf.l1_bf16.size()); A_(sc.fr_l2_bf16, hf.l2_bf16.size());
+    A_(sc.fr_l1_fp8, hf.l1_fp8.size()); A_(sc.fr_l2_fp8, hf.l2_fp8.size());
+    A_(sc.fr_b1, hf.b1.size()); A_(sc.fr_b2, hf.b2.size()); A_(sc.fr_s1, hf.s1.size()); A_(sc.fr_s2, hf.s2.size());
+    sc.n_at = hf.n_at; sc.n_ct = hf.n_ct; sc.n_vt = hf.n_vt;
 #undef A_
     for (int vi = 0; vi < nviews; ++vi)
         if (alloc_view(c, c->view[vi], n, C, k) != hipSuccess) {
@@ -427,10 +373,19 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
     HIP_OR_FAIL(c, hipMemcpyAsync(sc.feat, feat, n * kF * 4, hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(c, hipMemcpyAsync(sc.scale, scl, n * 24, hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(c, hipMemcpyAsync(sc.offsets, off, n * k * 12, hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(c, hipMemcpyAsync(sc.w32, w32.data(), L.total * 4, hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(c, hipMemcpyAsync(sc.wbf16, wbf.data(), L.total * 2, hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(c, hipMemcpyAsync(sc.wfp8, w8.data(), L.total, hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(c, hipMemcpyAsync(sc.wfp8_scale, w8s.data(), L.scale_total * 4, hipMemcpyHostToDevice, st));
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    HIP_OR_FAIL(c, up(sc.fr_l1_f32, hf.l1_f32.data(), hf.l1_f32.size() * 4));
+    HIP_OR_FAIL(c, up(sc.fr_l2_f32, hf.l2_f32.data(), hf.l2_f32.size() * 4));
+    HIP_OR_FAIL(c, up(sc.fr_l1_bf16, hf.l1_bf16.data(), hf.l1_bf16.size() * 2));
+    HIP_OR_FAIL(c, up(sc.fr_l2_bf16, hf.l2_bf16.data(), hf.l2_bf16.size() * 2));
+    HIP_OR_FAIL(c, up(sc.fr_l1_fp8, hf.l1_fp8.data(), hf.l1_fp8.size() * 2));
+    HIP_OR_FAIL(c, up(sc.fr_l2_fp8, hf.l2_fp8.data(), hf.l2_fp8.size() * 2));
+    HIP_OR_FAIL(c, up(sc.fr_b1, hf.b1.data(), hf.b1.size() * 4));
+    HIP_OR_FAIL(c, up(sc.fr_b2, hf.b2.data(), hf.b2.size() * 4));
+    HIP_OR_FAIL(c, up(sc.fr_s1, hf.s1.data(), hf.s1.size() * 4));
+    HIP_OR_FAIL(c, up(sc.fr_s2, hf.s2.data(), hf.s2.size() * 4));
     for (int vi = 0; vi < nviews; ++vi) HIP_OR_FAIL(c, reset_view(c, c->view[vi], n, c->cfg.d_max));
     HIP_OR_FAIL(c, hipStreamSynchronize(st));
     c->nviews = nviews;
@@ -694,6 +649,12 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
             for (int64_t t = s.tile_base; t < s.tile_base + (int64_t)s.ntx * s.nty; ++t)
                 for (int64_t i = ranges[2 * t]; i < ranges[2 * t + 1]; ++i)
                     if (i - lo < m) tile_of[i - lo] = (int32_t)(t - s.tile_base);
+            if (R.order) {  // pair values are depth ranks: map them back to entries
+                int32_t ne = r.n_entries;
+                std::vector<uint32_t> ord(ne > 0 ? ne : 1);
+                if (ne > 0) HIP_OR_FAIL(c, hipMemcpy(ord.data(), R.order, (size_t)ne * 4, hipMemcpyDeviceToHost));
+                for (int64_t i = 0; i < m; ++i) val[i] = val[i] < (uint32_t)ne ? ord[val[i]] : 0xffffffffu;
+            }
             int32_t* o = (int32_t*)dst;
             for (int64_t i = 0; i < m; ++i) {
                 o[2 * i] = tile_of[i];
@@ -731,14 +692,15 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
             count = b1 - b0;
             int64_t m = count < cap ? count : cap;
             if (m <= 0) break;
-            std::vector<float4> A(m), B(m);
-            std::vector<uint32_t> nt(m), dk(m);
-            HIP_OR_FAIL(c, hipMemcpy(A.data(), R.recA + b0, m * 16, hipMemcpyDeviceToHost));
-            HIP_OR_FAIL(c, hipMemcpy(B.data(), R.recB + b0, m * 16, hipMemcpyDeviceToHost));
+            std::vector<float4> rr(3 * m);
+            std::vector<uint32_t> nt(m);
+            HIP_OR_FAIL(c, hipMemcpy(rr.data(), R.rec + 3 * b0, m * 48, hipMemcpyDeviceToHost));
             HIP_OR_FAIL(c, hipMemcpy(nt.data(), R.ntiles + b0, m * 4, hipMemcpyDeviceToHost));
             float* o = (float*)dst;
             for (int64_t i = 0; i < m; ++i) {
-                float row[8] = {A[i].x, A[i].y, A[i].z, A[i].w, B[i].x, B[i].y, 0.f, (float)nt[i]};
+                const float4& A = rr[3 * i];
+                const float4& B = rr[3 * i + 1];
+                float row[8] = {A.x, A.y, A.z, A.w, B.x, B.y, 0.f, (float)nt[i]};
                 std::memcpy(o + 8 * i, row, sizeof(row));
             }
             break;

@@ -17,7 +17,7 @@ constexpr int kBlendThreads = 256;    // one thread per pixel of a tile
 constexpr int kMaxSeg = 16;           // (viewer, eye) images per raster batch
 constexpr int kGridBlocks = 2048;     // fixed grid of the grid-stride kernels
 constexpr int kScanBlocks = 1024;     // blocks of the device-wide scan
-constexpr int kSortBlocks = 512;      // blocks of each radix pass
+constexpr int kSortBlocks = 1024;     // blocks of each radix pass
 constexpr int kF = 32;                // feature length the kernels are built for
 constexpr int kH = 32;                // MLP hidden width the kernels are built for
 constexpr int kMaxK = 16;             // max neural Gaussians per anchor
@@ -97,21 +97,20 @@ struct Scene {
     float* feat = nullptr;      // [n, F]
     float* scale = nullptr;     // [n, 6]
     float* offsets = nullptr;   // [n, k, 3]
-    // weights, packed per head h: W1 [H][F+3], b1 [H], W2 [c k][H], b2 [c k]
-    float* w32 = nullptr;
-    uint16_t* wbf16 = nullptr;  // same layout, bf16 (biases stay in w32)
-    uint8_t* wfp8 = nullptr;    // same layout, e4m3fn
-    float* wfp8_scale = nullptr;// per output row (W1 rows then W2 rows per head)
+    // MFMA weight fragments (see gsc_derive_mfma.h)
+    float* fr_l1_f32 = nullptr;
+    float* fr_l2_f32 = nullptr;
+    uint16_t* fr_l1_bf16 = nullptr;
+    uint16_t* fr_l2_bf16 = nullptr;
+    uint16_t* fr_l1_fp8 = nullptr;
+    uint16_t* fr_l2_fp8 = nullptr;
+    float* fr_b1 = nullptr;
+    float* fr_b2 = nullptr;
+    float* fr_s1 = nullptr;
+    float* fr_s2 = nullptr;
+    int n_at = 0, n_ct = 0, n_vt = 0;
     size_t bytes = 0;
 };
-
-// Offsets of each head's arrays inside the packed weight buffer.
-struct WeightLayout {
-    int W1[3], b1[3], W2[3], b2[3], rows1[3], rows2[3];
-    int total;
-    int scale_W1[3], scale_W2[3], scale_total;
-};
-WeightLayout weight_layout(int k);
 
 // Per-viewer derive state: cache lines and the render buffer.
 struct View {
@@ -145,11 +144,9 @@ struct View {
 // Raster batch buffers.
 struct Raster {
     int64_t max_entries = 0, max_pairs = 0, max_tiles = 0;
-    float4* recA = nullptr;     // mean2d.xy, conic a b
-    float4* recB = nullptr;     // conic c, alpha, r, g
-    float* recC = nullptr;      // b
-    uint32_t* ntiles = nullptr; // per entry
-    uint2* rect = nullptr;      // per entry: tile x0|x1<<16, y0|y1<<16
+    float4* rec = nullptr;      // [3 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count)
+    uint32_t* ntiles = nullptr; // tile count per entry
+    uint32_t* scnt = nullptr;   // tile count per depth rank
     int32_t* n_sort = nullptr;  // [1] pairs to sort (clamped to capacity)
     uint32_t* dkey[2] = {nullptr, nullptr};  // depth keys (double buffer)
     uint32_t* dval[2] = {nullptr, nullptr};  // entry ids
@@ -163,6 +160,7 @@ struct Raster {
     RasterCounters* cnt = nullptr;
     RasterCounters* cnt_host = nullptr;
     int sorted_buf = 0;         // which pkey/pval buffer holds the sorted pairs
+    const uint32_t* order = nullptr;  // depth rank -> entry (null: pair values are entries)
     size_t bytes = 0;
 };
 

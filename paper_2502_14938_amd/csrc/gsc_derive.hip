@@ -3,7 +3,7 @@
 //   cache scheduling             -> k_cache_* (invalidate at the reuse depth,
 //                                   hit/miss, learned staleness, slot
 //                                   allocation, eviction of outdated lines)
-//   decode new anchors           -> k_derive_f32 / derive_mfma (eq. 3, eq. 2)
+//   decode new anchors           -> derive_mfma (eq. 3, eq. 2; matrix cores)
 //   configure the cache depth    -> k_depth_update (eq. 4, linear guide)
 //   update the render buffer     -> k_compose_* (opacity mask, Section 6)
 // Every count stays on the device (Counters); the host only enqueues.
@@ -341,125 +341,6 @@ __global__ void k_store_pu(float* pu_hist, int32_t t, DeriveCam cam) {
     if (threadIdx.x < 3) pu_hist[4 * (t & 63) + threadIdx.x] = cam.pos[threadIdx.x];
 }
 
-// ---------------------------------------------------------- derivation FP32
-// One thread per missed anchor: the three heads' hidden layers (F+3 -> H)
-// are computed once per anchor and shared by its k Gaussians (the anchor row
-// is loaded once, no per-offset copies), then each Gaussian's 11 outputs are
-// produced and written straight into the cache line arrays.
-struct DeriveK {
-    const float4* posr;
-    const float* feat;
-    const float* scale;
-    const float* offsets;
-    const float* w;  // packed fp32 weights
-    WeightLayout L;
-    int k;
-    const int32_t* visible;
-    const int32_t* misses;
-    const int32_t* vslot;
-    float4* L0;
-    float4* L1;
-    float4* L2;
-    float* L3;
-    DeriveCam cam;
-    Counters* cnt;
-};
-
-__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
-
-__device__ __forceinline__ void write_gaussian(const DeriveK& a, int64_t e, float4 x, const float* sc, const float* O,
-                                               float oa, const float* oc, const float* os) {
-    float alpha = tanhf(oa);
-    float s0 = sc[3] * sigm(os[0]), s1 = sc[4] * sigm(os[1]), s2 = sc[5] * sigm(os[2]);
-    float qw = os[3], qx = os[4], qy = os[5], qz = os[6];
-    float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-    if (qn > 0.f) {
-        float inv = 1.0f / qn;
-        qw *= inv; qx *= inv; qy *= inv; qz *= inv;
-    } else {
-        qw = 1.f; qx = qy = qz = 0.f;
-    }
-    float R[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
-                     {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
-                     {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
-    float v[3] = {s0 * s0, s1 * s1, s2 * s2};
-    float S[6];
-    int idx = 0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = r; c < 3; ++c) S[idx++] = R[r][0] * v[0] * R[c][0] + R[r][1] * v[1] * R[c][1] + R[r][2] * v[2] * R[c][2];
-    float mx = x.x + sc[0] * O[0], my = x.y + sc[1] * O[1], mz = x.z + sc[2] * O[2];
-    a.L0[e] = make_float4(mx, my, mz, alpha);
-    a.L1[e] = make_float4(S[0], S[1], S[2], S[3]);
-    a.L2[e] = make_float4(S[4], S[5], sigm(oc[0]), sigm(oc[1]));
-    a.L3[e] = sigm(oc[2]);
-}
-
-__global__ __launch_bounds__(NT) void k_derive_f32(DeriveK a) {
-    const float* __restrict__ w = a.w;
-    int32_t nm = a.cnt->n_miss;
-    for (int64_t j = gtid(); j < nm; j += gstride()) {
-        int32_t pos = a.misses[j];
-        int32_t aid = a.visible[pos];
-        int64_t line = a.vslot[pos];
-        if (line < 0) continue;  // no line (cache capacity exceeded this frame)
-        float4 x = a.posr[aid];
-        float z[kF + 3];
-        const float4* f4 = reinterpret_cast<const float4*>(a.feat + (int64_t)aid * kF);
-#pragma unroll
-        for (int q = 0; q < kF / 4; ++q) {
-            float4 v = f4[q];
-            z[4 * q] = v.x; z[4 * q + 1] = v.y; z[4 * q + 2] = v.z; z[4 * q + 3] = v.w;
-        }
-        float vx = x.x - a.cam.pos[0], vy = x.y - a.cam.pos[1], vz = x.z - a.cam.pos[2];
-        float inv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
-        z[kF] = vx * inv; z[kF + 1] = vy * inv; z[kF + 2] = vz * inv;
-        float h[3][kH];
-#pragma unroll
-        for (int hd = 0; hd < 3; ++hd) {
-            const float* W1 = w + a.L.W1[hd];
-            const float* b1 = w + a.L.b1[hd];
-#pragma unroll
-            for (int r = 0; r < kH; ++r) {
-                float acc = b1[r];
-#pragma unroll
-                for (int c = 0; c < kF + 3; ++c) acc = fmaf(W1[r * (kF + 3) + c], z[c], acc);
-                h[hd][r] = fmaxf(acc, 0.f);
-            }
-        }
-        float sc[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) sc[q] = a.scale[(int64_t)aid * 6 + q];
-        const float* W2a = w + a.L.W2[0]; const float* b2a = w + a.L.b2[0];
-        const float* W2c = w + a.L.W2[1]; const float* b2c = w + a.L.b2[1];
-        const float* W2s = w + a.L.W2[2]; const float* b2s = w + a.L.b2[2];
-        for (int g = 0; g < a.k; ++g) {
-            float oa = b2a[g];
-#pragma unroll
-            for (int c = 0; c < kH; ++c) oa = fmaf(W2a[g * kH + c], h[0][c], oa);
-            float oc[3], os[7];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                float acc = b2c[3 * g + q];
-#pragma unroll
-                for (int c = 0; c < kH; ++c) acc = fmaf(W2c[(3 * g + q) * kH + c], h[1][c], acc);
-                oc[q] = acc;
-            }
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                float acc = b2s[7 * g + q];
-#pragma unroll
-                for (int c = 0; c < kH; ++c) acc = fmaf(W2s[(7 * g + q) * kH + c], h[2][c], acc);
-                os[q] = acc;
-            }
-            const float* O = a.offsets + ((int64_t)aid * a.k + g) * 3;
-            float Ov[3] = {O[0], O[1], O[2]};
-            write_gaussian(a, line * a.k + g, x, sc, Ov, oa, oc, os);
-        }
-    }
-}
-
 // ------------------------------------------------------------- compose
 // G_t = [(i, j) : i visible ascending, j ascending, alpha_ij > 0]; each entry
 // is the cache entry (line * k + j).
@@ -499,26 +380,6 @@ inline dim3 grid_for(int64_t n) {
 }
 
 }  // namespace
-
-WeightLayout weight_layout(int k) {
-    WeightLayout L;
-    const int c[3] = {1, 3, 7};
-    int off = 0, soff = 0;
-    for (int h = 0; h < 3; ++h) {
-        L.rows1[h] = kH;
-        L.rows2[h] = c[h] * k;
-        L.W1[h] = off; off += kH * (kF + 3);
-        L.b1[h] = off; off += kH;
-        L.W2[h] = off; off += c[h] * k * kH;
-        L.b2[h] = off; off += c[h] * k;
-        L.scale_W1[h] = soff; soff += kH;
-        L.scale_W2[h] = soff; soff += c[h] * k;
-    }
-    // pad so that bf16 / fp8 copies stay 16-byte aligned per array
-    L.total = (off + 15) / 16 * 16;
-    L.scale_total = soff;
-    return L;
-}
 
 #define GSC_TRY(x)                              \
     do {                                        \
@@ -588,20 +449,17 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st) {
                            v.line_tau, v.line_last, need, need_rank, v.free_list, t, C, cnt);
         hipLaunchKernelGGL(k_vslot, grid_for(n), dim3(NT), 0, st, v.visible, v.slot_of, v.vslot, cnt);
     }
-    // decode the misses
-    if (a.precision == GSC_PREC_F32) {
-        DeriveK dk;
-        dk.posr = sc.posr; dk.feat = sc.feat; dk.scale = sc.scale; dk.offsets = sc.offsets; dk.w = sc.w32;
-        dk.L = weight_layout(sc.k); dk.k = sc.k; dk.visible = v.visible; dk.misses = v.misses; dk.vslot = v.vslot;
-        dk.L0 = v.L0; dk.L1 = v.L1; dk.L2 = v.L2; dk.L3 = v.L3; dk.cam = a.cam; dk.cnt = cnt;
-        hipLaunchKernelGGL(k_derive_f32, grid_for(n), dim3(NT), 0, st, dk);
-    } else {
+    // decode the misses on the matrix cores
+    {
         MfmaDeriveArgs m;
-        m.posr = sc.posr; m.feat = sc.feat; m.scale = sc.scale; m.offsets = sc.offsets; m.w32 = sc.w32;
-        m.wbf16 = sc.wbf16; m.wfp8 = sc.wfp8; m.wfp8_scale = sc.wfp8_scale; m.L = weight_layout(sc.k); m.k = sc.k;
+        m.posr = sc.posr; m.feat = sc.feat; m.scale = sc.scale; m.offsets = sc.offsets; m.k = sc.k;
         m.visible = v.visible; m.misses = v.misses; m.vslot = v.vslot; m.L0 = v.L0; m.L1 = v.L1; m.L2 = v.L2;
         m.L3 = v.L3; m.cam_pos[0] = a.cam.pos[0]; m.cam_pos[1] = a.cam.pos[1]; m.cam_pos[2] = a.cam.pos[2];
-        m.n_miss = &cnt->n_miss; m.fp8 = a.precision == GSC_PREC_FP8;
+        m.n_miss = &cnt->n_miss; m.mode = a.precision;
+        m.fr.l1_f32 = sc.fr_l1_f32; m.fr.l2_f32 = sc.fr_l2_f32; m.fr.l1_bf16 = sc.fr_l1_bf16;
+        m.fr.l2_bf16 = sc.fr_l2_bf16; m.fr.l1_fp8 = sc.fr_l1_fp8; m.fr.l2_fp8 = sc.fr_l2_fp8;
+        m.fr.b1 = sc.fr_b1; m.fr.b2 = sc.fr_b2; m.fr.s1 = sc.fr_s1; m.fr.s2 = sc.fr_s2;
+        m.fr.n_at = sc.n_at; m.fr.n_ct = sc.n_ct; m.fr.n_vt = sc.n_vt;
         GSC_TRY(derive_mfma(m, n, st));
     }
     hipLaunchKernelGGL(k_depth_update, dim3(1), dim3(1), 0, st, cnt, a.d_max, a.guide);

@@ -8,7 +8,7 @@
 //                      bits of the (tile | depth) key, applied per Gaussian
 //                      before duplication)
 //   scan + k_duplicate one (global tile id, entry) pair per covered tile,
-//                      emitted in depth order
+//                      emitted in depth order (LDS-staged, coalesced)
 //   tile radix pass    stable sort of pairs by global tile id (the high bits)
 //   k_ranges           [start, end) of every tile's run
 //   k_blend            front-to-back compositing, one block per tile,
@@ -16,6 +16,7 @@
 // With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
 // key and are sorted after duplication instead; the order is the same.
 #include <cmath>
+#include <type_traits>
 
 #include "gsc_common.h"
 
@@ -61,9 +62,11 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
 }
 
 // Minimum of q(d) = a dx^2 + 2 b dx dy + c dy^2 over the closed rectangle
-// [x0,x1] x [y0,y1] of offsets d (q convex: 0 inside, else on an edge).
+// [x0,x1] x [y0,y1] of offsets d (q convex: 0 inside, else on an edge; the
+// edge minimiser of a 1-D quadratic, clamped).  ia = 1/a, ic = 1/c.
 // Contraction is off so that the count and emit passes agree exactly.
-__device__ __forceinline__ float rect_min_q(float a, float b, float c, float x0, float x1, float y0, float y1) {
+__device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia, float ic, float x0, float x1,
+                                            float y0, float y1) {
 #pragma clang fp contract(off)
     if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
     float best = INFINITY;
@@ -71,186 +74,407 @@ __device__ __forceinline__ float rect_min_q(float a, float b, float c, float x0,
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         float dx = fx[i];
-        float dy = fminf(fmaxf(-b * dx / c, y0), y1);
+        float dy = fminf(fmaxf(-b * dx * ic, y0), y1);
         best = fminf(best, a * dx * dx + 2.f * b * dx * dy + c * dy * dy);
         float ey = fy[i];
-        float ex = fminf(fmaxf(-b * ey / a, x0), x1);
+        float ex = fminf(fmaxf(-b * ey * ia, x0), x1);
         best = fminf(best, a * ex * ex + 2.f * b * ex * ey + c * ey * ey);
     }
     return best;
 }
 
-// Does the footprint {q <= tau} of a Gaussian centred at (mx, my) reach the
-// pixel-centre rectangle of tile (tx, ty)?
-__device__ __forceinline__ bool tile_hit(float mx, float my, float ca, float cb, float cc, float tau, int tx, int ty,
-                                         int W, int H) {
+// Exact tile span of one tile row.  The footprint E = {q <= tau} meets the
+// pixel-centre rectangle of a tile iff the x-extent of E inside the row's
+// pixel-centre band overlaps the tile's x-span; the tiles hit in a row are
+// therefore contiguous.  The extent is computed analytically; tiles clearly
+// inside it (by a margin far above FP32 error) are hit, tiles near its ends
+// get the exact rectangle test.  Count and emit both call this function.
+struct Ellipse {
+    float mx, my, ca, cb, cc, tau;
+    float det, xmax, ymax, kr;  // kr: dy of the rightmost point is -cb * kr
+    float margin;
+    float ia, ic;               // 1/ca, 1/cc
+};
+
+__device__ __forceinline__ Ellipse make_ellipse(float mx, float my, float ca, float cb, float cc, float tau) {
+#pragma clang fp contract(off)
+    Ellipse e;
+    e.mx = mx; e.my = my; e.ca = ca; e.cb = cb; e.cc = cc; e.tau = tau;
+    e.det = ca * cc - cb * cb;
+    float id = e.det > 0.f ? 1.0f / e.det : 0.f;
+    e.xmax = sqrtf(tau * cc * id);
+    e.ymax = sqrtf(tau * ca * id);
+    e.kr = sqrtf(tau * id / cc);
+    e.margin = 2e-3f * (e.xmax + e.ymax) + 0.05f;
+    e.ia = 1.0f / ca;
+    e.ic = 1.0f / cc;
+    return e;
+}
+
+// Does the footprint reach the pixel-centre rectangle of tile (tx, ty)?
+__device__ __forceinline__ bool tile_hit(const Ellipse& e, int tx, int ty, int W, int H) {
 #pragma clang fp contract(off)
     float x0 = (float)(kTile * tx) + 0.5f, y0 = (float)(kTile * ty) + 0.5f;
     float x1 = (float)min(kTile * tx + kTile - 1, W - 1) + 0.5f;
     float y1 = (float)min(kTile * ty + kTile - 1, H - 1) + 0.5f;
-    return rect_min_q(ca, cb, cc, x0 - mx, x1 - mx, y0 - my, y1 - my) <= tau;
+    return rect_min_q(e.ca, e.cb, e.cc, e.ia, e.ic, x0 - e.mx, x1 - e.mx, y0 - e.my, y1 - e.my) <= e.tau;
 }
 
+__device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int W, int H, int& lo, int& hi) {
+#pragma clang fp contract(off)
+    lo = 0;
+    hi = -1;
+    const float y0 = (float)(kTile * ty) + 0.5f - e.my;
+    const float y1 = (float)min(kTile * ty + kTile - 1, H - 1) + 0.5f - e.my;
+    if (y0 > e.ymax + e.margin || y1 < -e.ymax - e.margin) return;  // band clear of E
+    float L, R;       // x-extent of E inside the band (offsets from mx)
+    bool certain;     // extent reliable enough to classify interior tiles
+    const float b0 = fmaxf(y0, -e.ymax), b1 = fminf(y1, e.ymax);
+    if (b0 > b1) {    // band grazes a tip of E: let the exact test decide
+        L = -e.xmax;
+        R = e.xmax;
+        certain = false;
+    } else {
+        float dyr = fminf(fmaxf(-e.cb * e.kr, b0), b1);
+        float dyl = fminf(fmaxf(e.cb * e.kr, b0), b1);
+        float sr = sqrtf(fmaxf(e.ca * e.tau - e.det * dyr * dyr, 0.f));
+        float sl = sqrtf(fmaxf(e.ca * e.tau - e.det * dyl * dyl, 0.f));
+        R = (-e.cb * dyr + sr) * e.ia;
+        L = (-e.cb * dyl - sl) * e.ia;
+        certain = true;
+    }
+    const float m = e.margin;
+    // tile tx spans x in [16 tx + 0.5, 16 tx + 15.5] (clipped at the image edge)
+    float ca_lo = ceilf((e.mx + L - m - 15.5f) * (1.0f / kTile));
+    float ca_hi = floorf((e.mx + R + m - 0.5f) * (1.0f / kTile));
+    int c_lo = (int)fminf(fmaxf(ca_lo, 0.f), (float)ntx);
+    int c_hi = (int)fminf(fmaxf(ca_hi, -1.f), (float)(ntx - 1));
+    if (c_lo > c_hi) return;
+    int s_lo = c_hi + 1, s_hi = c_hi;  // certain interior [s_lo, s_hi]
+    if (certain && R - L > 2.f * m) {
+        float sa = ceilf((e.mx + L + m - 15.5f) * (1.0f / kTile));
+        float sb = floorf((e.mx + R - m - 0.5f) * (1.0f / kTile));
+        int last_full = (W % kTile) ? ntx - 2 : ntx - 1;  // a clipped last tile is always tested
+        s_lo = (int)fminf(fmaxf(sa, (float)c_lo), (float)(c_hi + 1));
+        s_hi = (int)fminf(fmaxf(sb, (float)(s_lo - 1)), (float)min(c_hi, last_full));
+    }
+    const bool has_s = s_lo <= s_hi;
+    int l = -1;
+    int lim = has_s ? s_lo - 1 : c_hi;
+    for (int tx = c_lo; tx <= lim; ++tx)
+        if (tile_hit(e, tx, ty, W, H)) { l = tx; break; }
+    if (l < 0) {
+        if (!has_s) return;
+        l = s_lo;
+    }
+    int h = -1;
+    int stop = has_s ? s_hi + 1 : l;
+    for (int tx = c_hi; tx >= stop; --tx)
+        if (tile_hit(e, tx, ty, W, H)) { h = tx; break; }
+    if (h < 0) h = has_s ? s_hi : l;
+    lo = l;
+    hi = h;
+}
+
+// Exclusive scan over one wave64 (total in `total`).
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
+    Ellipse eb;
+    eb.mx = __shfl(el.mx, src, 64); eb.my = __shfl(el.my, src, 64);
+    eb.ca = __shfl(el.ca, src, 64); eb.cb = __shfl(el.cb, src, 64); eb.cc = __shfl(el.cc, src, 64);
+    eb.tau = __shfl(el.tau, src, 64); eb.det = __shfl(el.det, src, 64);
+    eb.xmax = __shfl(el.xmax, src, 64); eb.ymax = __shfl(el.ymax, src, 64);
+    eb.kr = __shfl(el.kr, src, 64); eb.margin = __shfl(el.margin, src, 64);
+    eb.ia = __shfl(el.ia, src, 64); eb.ic = __shfl(el.ic, src, 64);
+    return eb;
+}
+
+// Footprints taller than this many tile rows are counted by the whole wave
+// (lanes split the rows); entries with more pairs than kSmallPairs are
+// emitted by the whole wave (lanes split each row's tiles).
+constexpr int kSmallRows = 4;
+constexpr uint32_t kSmallPairs = 32;
+
+// Per-entry record, 3 x float4 (48 B):
+//   A = (mean2d.x, mean2d.y, conic a, conic b)
+//   B = (conic c, alpha, r, g)
+//   C = (b, bits: tile rows y0 | y1 << 16, bits: segment, bits: tile count)
 struct PreArgs {
     SegTable tab;
     RasterCounters* rc;
-    float4* recA;
-    float4* recB;
-    float* recC;
+    float4* rec;
     uint32_t* ntiles;
-    uint2* rect;
     uint32_t* dkey;
     uint32_t* dval;
 };
 
 __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
     const int64_t ne = p.rc->n_entries;
-    for (int64_t e = gtid(); e < ne; e += gstride()) {
-        int si = seg_of_entry(p.rc, p.tab.n, e);
-        const Seg& s = p.tab.s[si];
-        int64_t g = e - p.rc->entry_base[si];
-        int64_t src = s.G ? (int64_t)s.G[g] : g;
-        float4 l0 = s.L0[src], l1 = s.L1[src], l2 = s.L2[src];
-        float lb = s.L3[src];
-        uint32_t count = 0;
+    const int lane = threadIdx.x & 63;
+    // block-uniform loop so that whole waves stay together for the
+    // cooperative counting of tall footprints
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
+        const int64_t e = base + threadIdx.x;
+        const bool valid = e < ne;
+        int si = 0;
+        uint32_t count = 0, rows = 0;
         float depth = 0.f;
         float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint2 rc = make_uint2(0u, 0u);
-        float vx = l0.x - s.pos[0], vy = l0.y - s.pos[1], vz = l0.z - s.pos[2];
-        float tx = s.R[0] * vx + s.R[1] * vy + s.R[2] * vz;
-        float ty = s.R[3] * vx + s.R[4] * vy + s.R[5] * vz;
-        float tz = s.R[6] * vx + s.R[7] * vy + s.R[8] * vz;
-        float alpha = l0.w;
-        if (tz > s.znear && alpha >= kMinAlpha) {
-            float iz = 1.0f / tz;
-            float rx = fminf(fmaxf(tx * iz, -s.limx), s.limx);
-            float ry = fminf(fmaxf(ty * iz, -s.limy), s.limy);
-            float j00 = s.fx * iz, j02 = -s.fx * rx * iz, j11 = s.fy * iz, j12 = -s.fy * ry * iz;
-            float T0[3], T1[3];
+        float lb = 0.f;
+        Ellipse el{};
+        int y0 = 0, y1 = -1;
+        if (valid) {
+            si = seg_of_entry(p.rc, p.tab.n, e);
+            const Seg& s = p.tab.s[si];
+            int64_t g = e - p.rc->entry_base[si];
+            int64_t src = s.G ? (int64_t)s.G[g] : g;
+            float4 l0 = s.L0[src], l1 = s.L1[src], l2 = s.L2[src];
+            lb = s.L3[src];
+            float vx = l0.x - s.pos[0], vy = l0.y - s.pos[1], vz = l0.z - s.pos[2];
+            float tx = s.R[0] * vx + s.R[1] * vy + s.R[2] * vz;
+            float ty = s.R[3] * vx + s.R[4] * vy + s.R[5] * vz;
+            float tz = s.R[6] * vx + s.R[7] * vy + s.R[8] * vz;
+            float alpha = l0.w;
+            if (tz > s.znear && alpha >= kMinAlpha) {
+                // EWA: Jacobian of the perspective map (off-axis slope clamped)
+                float iz = 1.0f / tz;
+                float rx = fminf(fmaxf(tx * iz, -s.limx), s.limx);
+                float ry = fminf(fmaxf(ty * iz, -s.limy), s.limy);
+                float j00 = s.fx * iz, j02 = -s.fx * rx * iz, j11 = s.fy * iz, j12 = -s.fy * ry * iz;
+                float T0[3], T1[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                T0[k] = j00 * s.R[k] + j02 * s.R[6 + k];
-                T1[k] = j11 * s.R[3 + k] + j12 * s.R[6 + k];
-            }
-            float S[3][3] = {{l1.x, l1.y, l1.z}, {l1.y, l1.w, l2.x}, {l1.z, l2.x, l2.y}};
-            float u0[3], u1[3];
+                for (int k = 0; k < 3; ++k) {
+                    T0[k] = j00 * s.R[k] + j02 * s.R[6 + k];
+                    T1[k] = j11 * s.R[3 + k] + j12 * s.R[6 + k];
+                }
+                float S[3][3] = {{l1.x, l1.y, l1.z}, {l1.y, l1.w, l2.x}, {l1.z, l2.x, l2.y}};
+                float u0[3], u1[3];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                u0[r] = S[r][0] * T0[0] + S[r][1] * T0[1] + S[r][2] * T0[2];
-                u1[r] = S[r][0] * T1[0] + S[r][1] * T1[1] + S[r][2] * T1[2];
+                for (int r = 0; r < 3; ++r) {
+                    u0[r] = S[r][0] * T0[0] + S[r][1] * T0[1] + S[r][2] * T0[2];
+                    u1[r] = S[r][0] * T1[0] + S[r][1] * T1[1] + S[r][2] * T1[2];
+                }
+                float a = T0[0] * u0[0] + T0[1] * u0[1] + T0[2] * u0[2] + 0.3f;
+                float b = T0[0] * u1[0] + T0[1] * u1[1] + T0[2] * u1[2];
+                float c = T1[0] * u1[0] + T1[1] * u1[1] + T1[2] * u1[2] + 0.3f;
+                float det = a * c - b * b;
+                if (det > 0.f) {
+                    float id = 1.0f / det;
+                    float ca = c * id, cb = -b * id, cc = a * id;
+                    float mx = s.fx * tx * iz + s.cx, my = s.fy * ty * iz + s.cy;
+                    A = make_float4(mx, my, ca, cb);
+                    B = make_float4(cc, alpha, l2.z, l2.w);
+                    depth = tz;
+                    // opacity-aware extent: alpha exp(-q/2) >= 1/255  <=>  q <= 2 ln(255 alpha)
+                    float tau = fmaxf(2.0f * logf(255.0f * alpha), 0.f);
+                    el = make_ellipse(mx, my, ca, cb, cc, tau);
+                    float fy0 = floorf((my - el.ymax - el.margin - 0.5f) * (1.0f / kTile));
+                    float fy1 = floorf((my + el.ymax + el.margin - 0.5f) * (1.0f / kTile));
+                    y0 = (int)fminf(fmaxf(fy0, 0.f), (float)s.nty);
+                    y1 = (int)fminf(fmaxf(fy1, -1.f), (float)(s.nty - 1));
+                }
             }
-            float a = T0[0] * u0[0] + T0[1] * u0[1] + T0[2] * u0[2] + 0.3f;
-            float b = T0[0] * u1[0] + T0[1] * u1[1] + T0[2] * u1[2];
-            float c = T1[0] * u1[0] + T1[1] * u1[1] + T1[2] * u1[2] + 0.3f;
-            float det = a * c - b * b;
-            if (det > 0.f) {
-                float id = 1.0f / det;
-                float ca = c * id, cb = -b * id, cc = a * id;
-                float mx = s.fx * tx * iz + s.cx, my = s.fy * ty * iz + s.cy;
-                A = make_float4(mx, my, ca, cb);
-                B = make_float4(cc, alpha, l2.z, l2.w);
-                depth = tz;
-                // opacity-aware extent: alpha exp(-q/2) >= 1/255  <=>  q <= 2 ln(255 alpha)
-                float tau = 2.0f * logf(255.0f * alpha);
-                tau = fmaxf(tau, 0.f);
-                float cdet = ca * cc - cb * cb;
-                float sxx = cc / cdet, syy = ca / cdet;
-                float ex = sqrtf(tau * sxx) + 1.0f, ey = sqrtf(tau * syy) + 1.0f;
-                float fx0 = floorf((mx - ex - 0.5f) * (1.0f / kTile)), fx1 = floorf((mx + ex - 0.5f) * (1.0f / kTile));
-                float fy0 = floorf((my - ey - 0.5f) * (1.0f / kTile)), fy1 = floorf((my + ey - 0.5f) * (1.0f / kTile));
-                int x0 = (int)fminf(fmaxf(fx0, 0.f), (float)(s.ntx - 1)), x1 = (int)fminf(fmaxf(fx1, -1.f), (float)(s.ntx - 1));
-                int y0 = (int)fminf(fmaxf(fy0, 0.f), (float)(s.nty - 1)), y1 = (int)fminf(fmaxf(fy1, -1.f), (float)(s.nty - 1));
-                if (fx0 > (float)(s.ntx - 1) || fy0 > (float)(s.nty - 1)) x1 = -1;
-                if (x0 <= x1 && y0 <= y1) {
-                    for (int yy = y0; yy <= y1; ++yy)
-                        for (int xx = x0; xx <= x1; ++xx)
-                            count += tile_hit(mx, my, ca, cb, cc, tau, xx, yy, s.W, s.H) ? 1u : 0u;
-                    rc = make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16));
+            if (y1 - y0 + 1 <= kSmallRows) {
+                for (int yy = y0; yy <= y1; ++yy) {
+                    int lo, hi;
+                    row_span(el, yy, s.ntx, s.W, s.H, lo, hi);
+                    count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
                 }
             }
         }
-        p.recA[e] = A;
-        p.recB[e] = B;
-        p.recC[e] = lb;
-        p.rect[e] = rc;
-        p.ntiles[e] = count;
-        p.dkey[e] = count ? __float_as_uint(depth) : 0u;
-        p.dval[e] = (uint32_t)e;
+        uint64_t big = __ballot(valid && y1 - y0 + 1 > kSmallRows);
+        while (big) {
+            const int src = __ffsll((long long)big) - 1;
+            big &= big - 1ull;
+            const Ellipse eb = shfl_ellipse(el, src);
+            const int by0 = __shfl(y0, src, 64), by1 = __shfl(y1, src, 64), bsi = __shfl(si, src, 64);
+            const Seg& s = p.tab.s[bsi];
+            uint32_t part = 0;
+            for (int yy = by0 + lane; yy <= by1; yy += 64) {
+                int lo, hi;
+                row_span(eb, yy, s.ntx, s.W, s.H, lo, hi);
+                part += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+            }
+            uint32_t tot;
+            wave_excl_scan(part, tot);
+            if (lane == src) count = tot;
+        }
+        if (valid) {
+            rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
+            p.rec[3 * e] = A;
+            p.rec[3 * e + 1] = B;
+            p.rec[3 * e + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
+                                           __uint_as_float(count));
+            p.ntiles[e] = count;
+            p.dkey[e] = count ? __float_as_uint(depth) : 0u;
+            p.dval[e] = (uint32_t)e;
+        }
     }
 }
 
-// counts in depth order for the offset scan
-__global__ __launch_bounds__(NT) void k_gather_counts(const uint32_t* __restrict__ order, const uint32_t* __restrict__ ntiles,
-                                                      const RasterCounters* rc, uint32_t* __restrict__ out) {
+// Tile counts in depth-rank order, for the offset scan (4 gathers in flight
+// per thread).
+__global__ __launch_bounds__(NT) void k_gather_counts(const uint32_t* __restrict__ order,
+                                                      const uint32_t* __restrict__ ntiles, const RasterCounters* rc,
+                                                      uint32_t* __restrict__ out) {
     const int64_t ne = rc->n_entries;
-    for (int64_t r = gtid(); r < ne; r += gstride()) out[r] = ntiles[order[r]];
+    for (int64_t r0 = gtid() * 4; r0 < ne; r0 += gstride() * 4) {
+        uint32_t e[4], c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = r0 + q < ne ? order[r0 + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = r0 + q < ne ? ntiles[e[q]] : 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (r0 + q < ne) out[r0 + q] = c[q];
+    }
 }
 
 struct DupArgs {
     SegTable tab;
     RasterCounters* rc;
-    const uint32_t* order;   // depth-sorted entry ids (nullptr = entry order)
-    const uint32_t* offs;    // pair offset per rank
-    const uint32_t* ntiles;
-    const uint2* rect;
-    const float4* recA;
-    const float4* recB;
+    const uint32_t* order;   // depth rank -> entry (depth-presorted mode)
+    const uint32_t* offs;    // pair offset per rank (per entry in full-key mode)
+    const float4* rec;
+    const uint32_t* dkey;    // depth key per entry (full-key mode)
     uint32_t* key32;         // global tile id (depth-presorted mode)
     uint64_t* key64;         // (global tile << 32 | depth bits) (full-key mode)
-    uint32_t* val;
+    uint32_t* val;           // entry id
     int64_t max_pairs;
 };
 
-__global__ __launch_bounds__(NT) void k_duplicate(DupArgs d) {
-    const int64_t ne = d.rc->n_entries;
-    for (int64_t r = gtid(); r < ne; r += gstride()) {
-        uint32_t e = d.order[r];
-        uint32_t cnt = d.ntiles[e];
-        if (!cnt) continue;
-        int si = seg_of_entry(d.rc, d.tab.n, e);
-        const Seg& s = d.tab.s[si];
-        float4 A = d.recA[e], B = d.recB[e];
-        float tau = fmaxf(2.0f * logf(255.0f * B.y), 0.f);
-        uint2 rc = d.rect[e];
-        int x0 = rc.x & 0xffff, x1 = rc.x >> 16, y0 = rc.y & 0xffff, y1 = rc.y >> 16;
-        int64_t o = d.offs[r];
-        uint32_t w = 0;
-        for (int yy = y0; yy <= y1 && w < cnt; ++yy)
-            for (int xx = x0; xx <= x1 && w < cnt; ++xx) {
-                if (!tile_hit(A.x, A.y, A.z, A.w, B.x, tau, xx, yy, s.W, s.H)) continue;
-                int64_t q = o + w;
-                ++w;
-                if (q >= d.max_pairs) continue;
-                d.key32[q] = (uint32_t)(s.tile_base + yy * s.ntx + xx);
-                d.val[q] = e;
-            }
-    }
-}
+// Pair emission, balanced by output: block work item c owns the output
+// slice [c S, (c + 1) S) of the pair list (S = kStage).  It finds the first
+// entry overlapping the slice by binary search over the pair offsets, walks
+// the overlapping entries (in depth-rank order; entry order with full keys),
+// writes each entry's pairs that fall in the slice into LDS, and flushes the
+// slice with coalesced stores.  Entries with more than kSmallPairs pairs are
+// emitted by the whole wave (lanes compute row spans, then stride along each
+// row), so one huge footprint never serialises a lane.
+constexpr int kStage = 4096;
 
-__global__ __launch_bounds__(NT) void k_duplicate64(DupArgs d, const uint32_t* __restrict__ dkey) {
+template <bool kFull>
+__global__ __launch_bounds__(NT) void k_duplicate(DupArgs d) {
+    typedef typename std::conditional<kFull, uint64_t, uint32_t>::type Key;
+    __shared__ Key skey[kStage];
+    __shared__ uint32_t sval[kStage];
+    __shared__ int64_t s_first;
     const int64_t ne = d.rc->n_entries;
-    for (int64_t e = gtid(); e < ne; e += gstride()) {
-        uint32_t cnt = d.ntiles[e];
-        if (!cnt) continue;
-        int si = seg_of_entry(d.rc, d.tab.n, e);
-        const Seg& s = d.tab.s[si];
-        float4 A = d.recA[e], B = d.recB[e];
-        float tau = fmaxf(2.0f * logf(255.0f * B.y), 0.f);
-        uint2 rc = d.rect[e];
-        int x0 = rc.x & 0xffff, x1 = rc.x >> 16, y0 = rc.y & 0xffff, y1 = rc.y >> 16;
-        int64_t o = d.offs[e];
-        uint32_t w = 0;
-        uint64_t low = dkey[e];
-        for (int yy = y0; yy <= y1 && w < cnt; ++yy)
-            for (int xx = x0; xx <= x1 && w < cnt; ++xx) {
-                if (!tile_hit(A.x, A.y, A.z, A.w, B.x, tau, xx, yy, s.W, s.H)) continue;
-                int64_t q = o + w;
-                ++w;
-                if (q >= d.max_pairs) continue;
-                uint64_t gt = (uint64_t)(s.tile_base + yy * s.ntx + xx);
-                d.key64[q] = (gt << 32) | low;
-                d.val[q] = (uint32_t)e;
+    const int64_t np = d.rc->n_pairs < d.max_pairs ? d.rc->n_pairs : d.max_pairs;
+    const int lane = threadIdx.x & 63;
+    for (int64_t q0 = (int64_t)blockIdx.x * kStage; q0 < np; q0 += (int64_t)gridDim.x * kStage) {
+        const int64_t q1 = q0 + kStage < np ? q0 + kStage : np;
+        if (threadIdx.x == 0) {  // largest rank with offs[rank] <= q0
+            int64_t lo = 0, hi = ne - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) >> 1;
+                if ((int64_t)d.offs[mid] <= q0) lo = mid;
+                else hi = mid - 1;
             }
+            s_first = lo;
+        }
+        __syncthreads();
+        const int64_t first = s_first;
+        for (int64_t rb = first;; rb += NT) {
+            const int64_t r = rb + threadIdx.x;
+            bool valid = r < ne && (int64_t)d.offs[r] < q1;
+            if (!__syncthreads_or(valid)) break;
+            uint32_t e = 0, cnt = 0;
+            int si = 0, y0 = 0, y1 = -1;
+            int64_t o = 0;
+            uint64_t low = 0;
+            Ellipse el{};
+            if (valid) {
+                e = kFull ? (uint32_t)r : d.order[r];
+                float4 C = d.rec[3 * (int64_t)e + 2];
+                cnt = __float_as_uint(C.w);
+                o = d.offs[r];
+                valid = cnt != 0 && o + cnt > q0;
+                if (valid) {
+                    float4 A = d.rec[3 * (int64_t)e], B = d.rec[3 * (int64_t)e + 1];
+                    float tau = fmaxf(2.0f * logf(255.0f * B.y), 0.f);
+                    el = make_ellipse(A.x, A.y, A.z, A.w, B.x, tau);
+                    uint32_t rows = __float_as_uint(C.y);
+                    y0 = rows & 0xffff;
+                    y1 = rows >> 16;
+                    si = (int)__float_as_uint(C.z);
+                    if (kFull) low = d.dkey[e];
+                }
+            }
+            if (valid && cnt <= kSmallPairs) {
+                const Seg& s = d.tab.s[si];
+                uint32_t w = 0;
+                for (int yy = y0; yy <= y1 && w < cnt; ++yy) {
+                    int lo, hi;
+                    row_span(el, yy, s.ntx, s.W, s.H, lo, hi);
+                    const uint32_t rowbase = (uint32_t)(s.tile_base + yy * s.ntx);
+                    for (int xx = lo; xx <= hi && w < cnt; ++xx, ++w) {
+                        const int64_t q = o + w;
+                        if (q >= q0 && q < q1) {
+                            const uint32_t t = rowbase + (uint32_t)xx;
+                            skey[q - q0] = kFull ? (Key)(((uint64_t)t << 32) | low) : (Key)t;
+                            sval[q - q0] = e;
+                        }
+                    }
+                }
+            }
+            uint64_t big = __ballot(valid && cnt > kSmallPairs);
+            while (big) {
+                const int src = __ffsll((long long)big) - 1;
+                big &= big - 1ull;
+                const Ellipse eb = shfl_ellipse(el, src);
+                const int by0 = __shfl(y0, src, 64), by1 = __shfl(y1, src, 64), bsi = __shfl(si, src, 64);
+                const uint32_t bcnt = (uint32_t)__shfl((int)cnt, src, 64);
+                const uint32_t be = (uint32_t)__shfl((int)e, src, 64);
+                const int64_t bo = (int64_t)__shfl((long long)o, src, 64);
+                const uint64_t blow = (uint64_t)__shfl((long long)low, src, 64);
+                const Seg& s = d.tab.s[bsi];
+                uint32_t run = 0;
+                for (int chunk = by0; chunk <= by1 && bo + run < q1; chunk += 64) {
+                    int lo = 0, hi = -1;
+                    if (chunk + lane <= by1) row_span(eb, chunk + lane, s.ntx, s.W, s.H, lo, hi);
+                    uint32_t n_row = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot;
+                    uint32_t ex = wave_excl_scan(n_row, tot);
+                    const int nr = min(64, by1 - chunk + 1);
+                    for (int rr = 0; rr < nr; ++rr) {
+                        const int rlo = __shfl(lo, rr, 64), rhi = __shfl(hi, rr, 64);
+                        const uint32_t rex = (uint32_t)__shfl((int)ex, rr, 64);
+                        const int64_t rq = bo + run + rex;  // output position of the row's first pair
+                        if (rq >= q1 || rq + (rhi - rlo + 1) <= q0) continue;
+                        const uint32_t rowbase = (uint32_t)(s.tile_base + (chunk + rr) * s.ntx);
+                        for (int xx = rlo + lane; xx <= rhi; xx += 64) {
+                            const uint32_t w = run + rex + (uint32_t)(xx - rlo);
+                            const int64_t q = bo + w;
+                            if (w < bcnt && q >= q0 && q < q1) {
+                                const uint32_t t = rowbase + (uint32_t)xx;
+                                skey[q - q0] = kFull ? (Key)(((uint64_t)t << 32) | blow) : (Key)t;
+                                sval[q - q0] = be;
+                            }
+                        }
+                    }
+                    run += tot;
+                }
+            }
+        }
+        __syncthreads();
+        const int n = (int)(q1 - q0);
+        for (int i = threadIdx.x; i < n; i += NT) {
+            if (kFull) d.key64[q0 + i] = (uint64_t)skey[i];
+            else d.key32[q0 + i] = (uint32_t)skey[i];
+            d.val[q0 + i] = sval[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -267,14 +491,28 @@ __global__ __launch_bounds__(NT) void k_fill_ranges(int32_t* __restrict__ ranges
     for (int64_t i = gtid(); i < n2; i += gstride()) ranges[i] = 0;
 }
 
+// Each thread scans 8 consecutive sorted keys (plus one neighbour on each
+// side), so every load of a step is issued before any comparison.
 template <typename K>
 __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const int32_t* n_sort, int shift,
-                                               int32_t* __restrict__ ranges) {
+                                               int32_t* __restrict__ ranges, uint32_t n_tiles) {
+    constexpr int R = 8;
     const int64_t n = *n_sort;
-    for (int64_t i = gtid(); i < n; i += gstride()) {
-        uint32_t t = (uint32_t)(keys[i] >> shift);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[2 * (int64_t)t] = (int32_t)i;
-        if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[2 * (int64_t)t + 1] = (int32_t)(i + 1);
+    for (int64_t i0 = gtid() * R; i0 < n; i0 += gstride() * R) {
+        uint32_t t[R + 2];
+#pragma unroll
+        for (int q = 0; q < R + 2; ++q) {
+            int64_t i = i0 - 1 + q;
+            t[q] = (i >= 0 && i < n) ? (uint32_t)(keys[i] >> shift) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int q = 1; q <= R; ++q) {
+            int64_t i = i0 - 1 + q;
+            if (i >= n) break;
+            if (t[q] >= n_tiles) continue;  // never produced by the binning; kept out of bounds-safe reach
+            if (t[q - 1] != t[q]) ranges[2 * (int64_t)t[q]] = (int32_t)i;
+            if (t[q + 1] != t[q]) ranges[2 * (int64_t)t[q] + 1] = (int32_t)(i + 1);
+        }
     }
 }
 
@@ -297,11 +535,11 @@ __global__ __launch_bounds__(NT) void k_seg_pairs(const int32_t* __restrict__ ra
 // One block per global tile; block -> tile mapping keeps runs of adjacent
 // tiles on one XCD (blocks are dealt round-robin over the 8 XCDs) so that
 // Gaussians shared by neighbouring tiles are gathered through one L2.
+// Gaussians are staged in LDS 256 at a time; the block stops as soon as
+// every pixel has reached the transmittance floor.
 __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int32_t* __restrict__ ranges,
                                                           const uint32_t* __restrict__ vals,
-                                                          const float4* __restrict__ recA,
-                                                          const float4* __restrict__ recB,
-                                                          const float* __restrict__ recC) {
+                                                          const float4* __restrict__ rec, uint32_t max_entries) {
     __shared__ float4 sA[kBlendThreads];
     __shared__ float4 sB[kBlendThreads];
     __shared__ float sC[kBlendThreads];
@@ -327,9 +565,11 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         int32_t i = base + (int32_t)threadIdx.x;
         if (i < end) {
             uint32_t e = vals[i];
-            sA[threadIdx.x] = recA[e];
-            sB[threadIdx.x] = recB[e];
-            sC[threadIdx.x] = recC[e];
+            e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
+            const float4* rp = rec + 3 * (int64_t)e;
+            sA[threadIdx.x] = rp[0];
+            sB[threadIdx.x] = rp[1];
+            sC[threadIdx.x] = rp[2].x;
         }
         __syncthreads();
         const int nb = min(kBlendThreads, end - base);
@@ -394,49 +634,50 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
     RasterCounters* rc = r.cnt;
     hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
     PreArgs pa;
-    pa.tab = tab; pa.rc = rc; pa.recA = r.recA; pa.recB = r.recB; pa.recC = r.recC; pa.ntiles = r.ntiles;
-    pa.rect = r.rect; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
+    pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
     hipLaunchKernelGGL(k_preprocess, grid_for(r.max_entries), dim3(NT), 0, st, pa);
     const int tile_bits = bits_for(tab.total_tiles);
     DupArgs da;
-    da.tab = tab; da.rc = rc; da.ntiles = r.ntiles; da.rect = r.rect; da.recA = r.recA; da.recB = r.recB;
-    da.max_pairs = r.max_pairs;
+    da.tab = tab; da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
     hipError_t e;
     if (!full_key_sort) {
+        // low 32 key bits (depth) first, per Gaussian
         int which = 0;
         e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gather_counts, grid_for(r.max_entries), dim3(NT), 0, st, r.dval[which], r.ntiles, rc,
-                           r.dkey[which ^ 1]);
-        e = scan_u32(r.dkey[which ^ 1], r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
+        hipLaunchKernelGGL(k_gather_counts, grid_for(r.max_entries / 4 + 1), dim3(NT), 0, st, r.dval[which], r.ntiles,
+                           rc, r.scnt);
+        e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_duplicate, grid_for(r.max_entries), dim3(NT), 0, st, da);
+        hipLaunchKernelGGL(k_duplicate<false>, dim3(kGridBlocks), dim3(NT), 0, st, da);
+        // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
         e = radix_sort_u32(r.pkey, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_fill_ranges, grid_for(2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
-        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_for(r.max_pairs), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
-                           r.ranges);
+        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_for(r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
+                           r.ranges, (uint32_t)tab.total_tiles);
     } else {
         e = scan_u32(r.ntiles, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_duplicate64, grid_for(r.max_entries), dim3(NT), 0, st, da, r.dkey[0]);
+        hipLaunchKernelGGL(k_duplicate<true>, dim3(kGridBlocks), dim3(NT), 0, st, da);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_fill_ranges, grid_for(2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
-        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_for(r.max_pairs), dim3(NT), 0, st, r.pkey64[pw], r.n_sort, 32,
-                           r.ranges);
+        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_for(r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
+                           32, r.ranges, (uint32_t)tab.total_tiles);
     }
+    r.order = nullptr;
     hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)tab.n), dim3(NT), 0, st, r.ranges, tab, rc);
     hipLaunchKernelGGL(k_blend, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
-                       r.pval[r.sorted_buf], r.recA, r.recB, r.recC);
+                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries);
     return hipGetLastError();
 }
 

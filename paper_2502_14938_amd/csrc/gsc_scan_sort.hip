@@ -145,19 +145,25 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ keys, c
     __syncthreads();
     int64_t b0, b1;
     chunk_of(count_of(n_dev, n_host), SORT_TILE, b0, b1);
-    for (int64_t base = b0; base < b1; base += NT) {
-        int64_t i = base + threadIdx.x;
-        bool valid = i < b1;
-        uint32_t d = valid ? digit(keys[i], shift, mask) : 0u;
-        uint64_t peers = peers_of(d, valid, bits);
-        if (valid) {
-            uint64_t below = peers & ((1ull << lane) - 1ull);
-            if (below == 0ull) atomicAdd(&h[w][d], (uint32_t)__popcll(peers));
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int64_t base = b0; base < b1; base += SORT_TILE) {
+        // issue every load of the step before any ranking work
+        uint32_t d[SORT_IPT];
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            int64_t i = base + r * NT + threadIdx.x;
+            d[r] = i < b1 ? digit(keys[i], shift, mask) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            bool valid = d[r] != 0xffffffffu;
+            uint64_t peers = peers_of(valid ? d[r] : 0u, valid, bits);
+            if (valid && (peers & lt) == 0ull) atomicAdd(&h[w][d[r]], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nbins; d += NT)
-        hist[(int64_t)d * gridDim.x + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+    for (uint32_t q = threadIdx.x; q < nbins; q += NT)
+        hist[(int64_t)q * gridDim.x + blockIdx.x] = h[0][q] + h[1][q] + h[2][q] + h[3][q];
 }
 
 template <typename K>
@@ -183,13 +189,19 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
         __syncthreads();
         K key[SORT_IPT];
         uint32_t val[SORT_IPT], dg[SORT_IPT], lr[SORT_IPT];
+        // issue every load of the sub-tile before any ranking work
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
             int64_t i = base + w * SORT_WSEG + r * 64 + lane;
             bool valid = i < b1;
             key[r] = valid ? kin[i] : (K)0;
             val[r] = valid ? vin[i] : 0u;
-            uint32_t d = valid ? digit(key[r], shift, mask) : 0u;
+            dg[r] = valid ? digit(key[r], shift, mask) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            bool valid = dg[r] != 0xffffffffu;
+            uint32_t d = valid ? dg[r] : 0u;
             uint64_t peers = peers_of(d, valid, bits);
             // every peer reads the wave's running count before the group's
             // first lane advances it (one wave, in-order LDS accesses)
@@ -198,7 +210,6 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
             __builtin_amdgcn_wave_barrier();
             if (valid && rank == 0u) cnt[w][d] = c + (uint32_t)__popcll(peers);
             __builtin_amdgcn_wave_barrier();
-            dg[r] = valid ? d : 0xffffffffu;
             lr[r] = c + rank;
         }
         __syncthreads();

@@ -78,3 +78,17 @@ def test_full_key_sort_gives_same_order(gs):
     b = run(gs, mu, cov, rgb, al, cam, full_key=True)
     assert np.array_equal(a[3], b[3])
     assert np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_large_footprints_match_oracle(gs, seed):
+    # Gaussians 0.3-3 m in front of the camera with metre-scale covariances:
+    # footprints span tens of tiles, many cross the image border, the image
+    # is 200x120 so the last tile column and row are clipped.
+    mu, cov, rgb, al = synth.random_gaussians(400, seed=seed, box=2.5, zc=1.8, s_lo=0.05, s_hi=1.2)
+    cam = synth.look_camera((0, 0, 0), (0, 0, 1), (0, -1, 0), 200, 120, math.radians(90))
+    img, T, nc, pairs, _ = run(gs, mu, cov, rgb, al, cam)
+    ref = oracle.render_gaussians(mu, cov, rgb, al, cam, debug=True)
+    assert ref["n_pairs"] > 20 * 400 * 0.2
+    assert_image(img, ref)
+    assert_pairs(pairs, ref, ref["pre"]["depth"])
