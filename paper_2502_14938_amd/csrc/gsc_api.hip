@@ -160,7 +160,8 @@ hipError_t alloc_raster(gsc_ctx* c, Raster& r, int64_t max_entries, int64_t max_
     r.max_tiles = max_tiles;
     hipError_t e;
 #define A_(p, cnt) if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) return e
-    A_(r.rec, 3 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
+    A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
+    A_(r.big_list, max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
@@ -692,14 +693,14 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
             count = b1 - b0;
             int64_t m = count < cap ? count : cap;
             if (m <= 0) break;
-            std::vector<float4> rr(3 * m);
+            std::vector<float4> rr(4 * m);
             std::vector<uint32_t> nt(m);
-            HIP_OR_FAIL(c, hipMemcpy(rr.data(), R.rec + 3 * b0, m * 48, hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(c, hipMemcpy(rr.data(), R.rec + 4 * b0, m * 64, hipMemcpyDeviceToHost));
             HIP_OR_FAIL(c, hipMemcpy(nt.data(), R.ntiles + b0, m * 4, hipMemcpyDeviceToHost));
             float* o = (float*)dst;
             for (int64_t i = 0; i < m; ++i) {
-                const float4& A = rr[3 * i];
-                const float4& B = rr[3 * i + 1];
+                const float4& A = rr[4 * i];
+                const float4& B = rr[4 * i + 1];
                 float row[8] = {A.x, A.y, A.z, A.w, B.x, B.y, 0.f, (float)nt[i]};
                 std::memcpy(o + 8 * i, row, sizeof(row));
             }

@@ -50,7 +50,8 @@ struct RasterCounters {
     int32_t n_pairs;              // total tile pairs (all segments)
     int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
     int32_t overflow;             // bit0: pair capacity
-    int32_t pad[2];
+    int32_t n_big;                // entries in the large-footprint list
+    int32_t pad;
 };
 
 // One (viewer, eye) image of a raster batch; passed by value in kernel args.
@@ -144,7 +145,8 @@ struct View {
 // Raster batch buffers.
 struct Raster {
     int64_t max_entries = 0, max_pairs = 0, max_tiles = 0;
-    float4* rec = nullptr;      // [3 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count)
+    float4* rec = nullptr;      // [4 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count), spans
+    int32_t* big_list = nullptr;  // entries emitted one wave each
     uint32_t* ntiles = nullptr; // tile count per entry
     uint32_t* scnt = nullptr;   // tile count per depth rank
     int32_t* n_sort = nullptr;  // [1] pairs to sort (clamped to capacity)
@@ -155,7 +157,7 @@ struct Raster {
     uint32_t* pval[2] = {nullptr, nullptr};  // entry id
     uint64_t* pkey64[2] = {nullptr, nullptr};// full-key mode
     int32_t* ranges = nullptr;  // [max_tiles][2]
-    uint32_t* hist = nullptr;   // [256 * kSortBlocks]
+    uint32_t* hist = nullptr;   // [256 * kSortBlocks] radix digit counts per block
     uint32_t* block_sums = nullptr;
     RasterCounters* cnt = nullptr;
     RasterCounters* cnt_host = nullptr;
@@ -172,13 +174,18 @@ struct Raster {
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int64_t n_host, int32_t* total,
                     uint32_t* block_sums, hipStream_t st);
 
-// Stable LSD radix sort of (key, value) pairs over bits [bit0, bit1).
-// Count from *n_dev (device) or n_host.  Returns in *which the buffer index
-// (0/1) holding the result.  hist: [256 * kSortBlocks], block_sums: scan scratch.
+// Stable LSD radix sort of (key, value) pairs over bits [bit0, bit1),
+// 8-bit digits, reduce-then-scan per pass (digit counts per block, a scan of
+// the counts in digit-major order, a scatter through LDS).  Count from
+// *n_dev (device) or n_host.  Returns in *which the buffer index (0/1)
+// holding the result.  hist: [256 * kSortBlocks], block_sums: scan scratch.
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
+
+
+
 
 // Derive stage of one view.
 struct DeriveArgs {

@@ -16,7 +16,6 @@
 // With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
 // key and are sorted after duplication instead; the order is the same.
 #include <cmath>
-#include <type_traits>
 
 #include "gsc_common.h"
 
@@ -54,6 +53,7 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
     }
     rc->entry_base[tab.n] = acc;
     rc->overflow = 0;
+    rc->n_big = 0;
     if (acc > max_entries) {
         rc->overflow |= 2;
         acc = (int32_t)max_entries;
@@ -206,10 +206,13 @@ __device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
 constexpr int kSmallRows = 4;
 constexpr uint32_t kSmallPairs = 32;
 
-// Per-entry record, 3 x float4 (48 B):
+// Per-entry record, 4 x float4 (64 B, one cache line):
 //   A = (mean2d.x, mean2d.y, conic a, conic b)
 //   B = (conic c, alpha, r, g)
 //   C = (b, bits: tile rows y0 | y1 << 16, bits: segment, bits: tile count)
+//   D = bits: exact tile span lo | hi << 16 of each of up to kSmallRows rows
+//       (footprints of at most kSmallRows tile rows; hi < lo: empty row)
+constexpr int kRec = 4;
 struct PreArgs {
     SegTable tab;
     RasterCounters* rc;
@@ -234,6 +237,7 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
         float lb = 0.f;
         Ellipse el{};
         int y0 = 0, y1 = -1;
+        uint32_t spans[kSmallRows] = {0xffffu, 0xffffu, 0xffffu, 0xffffu};
         if (valid) {
             si = seg_of_entry(p.rc, p.tab.n, e);
             const Seg& s = p.tab.s[si];
@@ -286,10 +290,13 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
                 }
             }
             if (y1 - y0 + 1 <= kSmallRows) {
-                for (int yy = y0; yy <= y1; ++yy) {
-                    int lo, hi;
-                    row_span(el, yy, s.ntx, s.W, s.H, lo, hi);
-                    count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+#pragma unroll
+                for (int i = 0; i < kSmallRows; ++i) {
+                    int lo = 0xffff, hi = 0;
+                    if (y0 + i <= y1) row_span(el, y0 + i, s.ntx, s.W, s.H, lo, hi);
+                    if (hi >= lo) count += (uint32_t)(hi - lo + 1);
+                    else lo = 0xffff, hi = 0;
+                    spans[i] = (uint32_t)lo | ((uint32_t)hi << 16);
                 }
             }
         }
@@ -312,10 +319,12 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
         }
         if (valid) {
             rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
-            p.rec[3 * e] = A;
-            p.rec[3 * e + 1] = B;
-            p.rec[3 * e + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
-                                           __uint_as_float(count));
+            p.rec[kRec * e] = A;
+            p.rec[kRec * e + 1] = B;
+            p.rec[kRec * e + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
+                                              __uint_as_float(count));
+            p.rec[kRec * e + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
+                                              __uint_as_float(spans[2]), __uint_as_float(spans[3]));
             p.ntiles[e] = count;
             p.dkey[e] = count ? __float_as_uint(depth) : 0u;
             p.dval[e] = (uint32_t)e;
@@ -354,127 +363,119 @@ struct DupArgs {
     int64_t max_pairs;
 };
 
-// Pair emission, balanced by output: block work item c owns the output
-// slice [c S, (c + 1) S) of the pair list (S = kStage).  It finds the first
-// entry overlapping the slice by binary search over the pair offsets, walks
-// the overlapping entries (in depth-rank order; entry order with full keys),
-// writes each entry's pairs that fall in the slice into LDS, and flushes the
-// slice with coalesced stores.  Entries with more than kSmallPairs pairs are
-// emitted by the whole wave (lanes compute row spans, then stride along each
-// row), so one huge footprint never serialises a lane.
-constexpr int kStage = 4096;
+// Pair emission.  Every entry owns the output range [offs[r], offs[r] +
+// count) (ranks in depth order; entry order with full keys), so entries can
+// be emitted in any order:
+//   k_dup_small  one thread per entry with at most kSmallPairs pairs in at
+//                most kSmallRows rows: tiles straight from the row spans the
+//                preprocess stored; other entries are appended to a list;
+//   k_dup_big    one wave per listed entry: row spans from the record (short
+//                footprints) or recomputed one row per lane (tall ones), and
+//                lanes stride along each row so the stores coalesce.
+template <bool kFull>
+__device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t, uint32_t e, uint64_t low) {
+    if (q >= d.max_pairs) return;
+    if (kFull) d.key64[q] = ((uint64_t)t << 32) | low;
+    else d.key32[q] = t;
+    d.val[q] = e;
+}
 
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_duplicate(DupArgs d) {
-    typedef typename std::conditional<kFull, uint64_t, uint32_t>::type Key;
-    __shared__ Key skey[kStage];
-    __shared__ uint32_t sval[kStage];
-    __shared__ int64_t s_first;
+__global__ __launch_bounds__(NT) void k_dup_small(DupArgs d, int32_t* __restrict__ big_list, int32_t* n_big) {
     const int64_t ne = d.rc->n_entries;
-    const int64_t np = d.rc->n_pairs < d.max_pairs ? d.rc->n_pairs : d.max_pairs;
     const int lane = threadIdx.x & 63;
-    for (int64_t q0 = (int64_t)blockIdx.x * kStage; q0 < np; q0 += (int64_t)gridDim.x * kStage) {
-        const int64_t q1 = q0 + kStage < np ? q0 + kStage : np;
-        if (threadIdx.x == 0) {  // largest rank with offs[rank] <= q0
-            int64_t lo = 0, hi = ne - 1;
-            while (lo < hi) {
-                int64_t mid = (lo + hi + 1) >> 1;
-                if ((int64_t)d.offs[mid] <= q0) lo = mid;
-                else hi = mid - 1;
-            }
-            s_first = lo;
-        }
-        __syncthreads();
-        const int64_t first = s_first;
-        for (int64_t rb = first;; rb += NT) {
-            const int64_t r = rb + threadIdx.x;
-            bool valid = r < ne && (int64_t)d.offs[r] < q1;
-            if (!__syncthreads_or(valid)) break;
-            uint32_t e = 0, cnt = 0;
-            int si = 0, y0 = 0, y1 = -1;
-            int64_t o = 0;
-            uint64_t low = 0;
-            Ellipse el{};
-            if (valid) {
-                e = kFull ? (uint32_t)r : d.order[r];
-                float4 C = d.rec[3 * (int64_t)e + 2];
-                cnt = __float_as_uint(C.w);
-                o = d.offs[r];
-                valid = cnt != 0 && o + cnt > q0;
-                if (valid) {
-                    float4 A = d.rec[3 * (int64_t)e], B = d.rec[3 * (int64_t)e + 1];
-                    float tau = fmaxf(2.0f * logf(255.0f * B.y), 0.f);
-                    el = make_ellipse(A.x, A.y, A.z, A.w, B.x, tau);
-                    uint32_t rows = __float_as_uint(C.y);
-                    y0 = rows & 0xffff;
-                    y1 = rows >> 16;
-                    si = (int)__float_as_uint(C.z);
-                    if (kFull) low = d.dkey[e];
-                }
-            }
-            if (valid && cnt <= kSmallPairs) {
-                const Seg& s = d.tab.s[si];
-                uint32_t w = 0;
-                for (int yy = y0; yy <= y1 && w < cnt; ++yy) {
-                    int lo, hi;
-                    row_span(el, yy, s.ntx, s.W, s.H, lo, hi);
-                    const uint32_t rowbase = (uint32_t)(s.tile_base + yy * s.ntx);
-                    for (int xx = lo; xx <= hi && w < cnt; ++xx, ++w) {
-                        const int64_t q = o + w;
-                        if (q >= q0 && q < q1) {
-                            const uint32_t t = rowbase + (uint32_t)xx;
-                            skey[q - q0] = kFull ? (Key)(((uint64_t)t << 32) | low) : (Key)t;
-                            sval[q - q0] = e;
-                        }
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
+        const int64_t r = base + threadIdx.x;
+        bool is_big = false;
+        if (r < ne) {
+            const uint32_t e = kFull ? (uint32_t)r : d.order[r];
+            const float4* rp = d.rec + kRec * (int64_t)e;
+            const float4 C = rp[2];
+            const uint32_t cnt = __float_as_uint(C.w);
+            if (cnt) {
+                const uint32_t rows = __float_as_uint(C.y);
+                const int y0 = rows & 0xffff, y1 = rows >> 16;
+                if (cnt > kSmallPairs || y1 - y0 + 1 > kSmallRows) {
+                    is_big = true;
+                } else {
+                    const float4 D = rp[3];
+                    const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
+                                                     __float_as_uint(D.w)};
+                    const Seg& s = d.tab.s[__float_as_uint(C.z)];
+                    const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
+                    int64_t q = d.offs[r];
+#pragma unroll
+                    for (int i = 0; i < kSmallRows; ++i) {
+                        const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
+                        const uint32_t rowbase = (uint32_t)(s.tile_base + (y0 + i) * s.ntx);
+                        for (int xx = lo; xx <= hi; ++xx) put_pair<kFull>(d, q++, rowbase + (uint32_t)xx, e, low);
                     }
                 }
             }
-            uint64_t big = __ballot(valid && cnt > kSmallPairs);
-            while (big) {
-                const int src = __ffsll((long long)big) - 1;
-                big &= big - 1ull;
-                const Ellipse eb = shfl_ellipse(el, src);
-                const int by0 = __shfl(y0, src, 64), by1 = __shfl(y1, src, 64), bsi = __shfl(si, src, 64);
-                const uint32_t bcnt = (uint32_t)__shfl((int)cnt, src, 64);
-                const uint32_t be = (uint32_t)__shfl((int)e, src, 64);
-                const int64_t bo = (int64_t)__shfl((long long)o, src, 64);
-                const uint64_t blow = (uint64_t)__shfl((long long)low, src, 64);
-                const Seg& s = d.tab.s[bsi];
-                uint32_t run = 0;
-                for (int chunk = by0; chunk <= by1 && bo + run < q1; chunk += 64) {
-                    int lo = 0, hi = -1;
-                    if (chunk + lane <= by1) row_span(eb, chunk + lane, s.ntx, s.W, s.H, lo, hi);
-                    uint32_t n_row = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot;
-                    uint32_t ex = wave_excl_scan(n_row, tot);
-                    const int nr = min(64, by1 - chunk + 1);
-                    for (int rr = 0; rr < nr; ++rr) {
-                        const int rlo = __shfl(lo, rr, 64), rhi = __shfl(hi, rr, 64);
-                        const uint32_t rex = (uint32_t)__shfl((int)ex, rr, 64);
-                        const int64_t rq = bo + run + rex;  // output position of the row's first pair
-                        if (rq >= q1 || rq + (rhi - rlo + 1) <= q0) continue;
-                        const uint32_t rowbase = (uint32_t)(s.tile_base + (chunk + rr) * s.ntx);
-                        for (int xx = rlo + lane; xx <= rhi; xx += 64) {
-                            const uint32_t w = run + rex + (uint32_t)(xx - rlo);
-                            const int64_t q = bo + w;
-                            if (w < bcnt && q >= q0 && q < q1) {
-                                const uint32_t t = rowbase + (uint32_t)xx;
-                                skey[q - q0] = kFull ? (Key)(((uint64_t)t << 32) | blow) : (Key)t;
-                                sval[q - q0] = be;
-                            }
-                        }
+        }
+        // wave-aggregated append of the large entries (their order is irrelevant)
+        const uint64_t m = __ballot(is_big);
+        if (m) {
+            int32_t at = 0;
+            const int leader = __ffsll((long long)m) - 1;
+            if (lane == leader) at = atomicAdd(n_big, __popcll(m));
+            at = __shfl(at, leader, 64);
+            if (is_big) big_list[at + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)r;
+        }
+    }
+}
+
+template <bool kFull>
+__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ big_list, const int32_t* n_big) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nb = *n_big;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t b = wave; b < nb; b += nwaves) {
+        const int64_t r = big_list[b];
+        const uint32_t e = kFull ? (uint32_t)r : d.order[r];
+        const float4* rp = d.rec + kRec * (int64_t)e;
+        const float4 C = rp[2];
+        const uint32_t cnt = __float_as_uint(C.w);
+        const uint32_t rows = __float_as_uint(C.y);
+        const int y0 = rows & 0xffff, y1 = rows >> 16;
+        const Seg& s = d.tab.s[__float_as_uint(C.z)];
+        const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
+        const int64_t o = d.offs[r];
+        uint32_t run = 0;
+        if (y1 - y0 + 1 <= kSmallRows) {
+            const float4 D = rp[3];
+            const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
+                                             __float_as_uint(D.w)};
+#pragma unroll
+            for (int i = 0; i < kSmallRows; ++i) {
+                const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
+                const uint32_t rowbase = (uint32_t)(s.tile_base + (y0 + i) * s.ntx);
+                for (int xx = lo + lane; xx <= hi; xx += 64)
+                    put_pair<kFull>(d, o + run + (uint32_t)(xx - lo), rowbase + (uint32_t)xx, e, low);
+                run += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+            }
+        } else {
+            const float4 A = rp[0], B = rp[1];
+            const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
+            for (int chunk = y0; chunk <= y1; chunk += 64) {
+                int lo = 0, hi = -1;
+                if (chunk + lane <= y1) row_span(el, chunk + lane, s.ntx, s.W, s.H, lo, hi);
+                uint32_t n_row = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot;
+                const uint32_t ex = wave_excl_scan(n_row, tot);
+                const int nr = min(64, y1 - chunk + 1);
+                for (int rr = 0; rr < nr; ++rr) {
+                    const int rlo = __shfl(lo, rr, 64), rhi = __shfl(hi, rr, 64);
+                    const uint32_t rex = (uint32_t)__shfl((int)ex, rr, 64);
+                    const uint32_t rowbase = (uint32_t)(s.tile_base + (chunk + rr) * s.ntx);
+                    for (int xx = rlo + lane; xx <= rhi; xx += 64) {
+                        const uint32_t w = run + rex + (uint32_t)(xx - rlo);
+                        if (w < cnt) put_pair<kFull>(d, o + w, rowbase + (uint32_t)xx, e, low);
                     }
-                    run += tot;
                 }
+                run += tot;
             }
         }
-        __syncthreads();
-        const int n = (int)(q1 - q0);
-        for (int i = threadIdx.x; i < n; i += NT) {
-            if (kFull) d.key64[q0 + i] = (uint64_t)skey[i];
-            else d.key32[q0 + i] = (uint32_t)skey[i];
-            d.val[q0 + i] = sval[i];
-        }
-        __syncthreads();
     }
 }
 
@@ -566,7 +567,7 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         if (i < end) {
             uint32_t e = vals[i];
             e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
-            const float4* rp = rec + 3 * (int64_t)e;
+            const float4* rp = rec + kRec * (int64_t)e;
             sA[threadIdx.x] = rp[0];
             sB[threadIdx.x] = rp[1];
             sC[threadIdx.x] = rp[2].x;
@@ -651,7 +652,8 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_duplicate<false>, dim3(kGridBlocks), dim3(NT), 0, st, da);
+        hipLaunchKernelGGL(k_dup_small<false>, grid_for(r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_big<false>, dim3(kGridBlocks), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
         e = radix_sort_u32(r.pkey, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st);
@@ -665,7 +667,8 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_duplicate<true>, dim3(kGridBlocks), dim3(NT), 0, st, da);
+        hipLaunchKernelGGL(k_dup_small<true>, grid_for(r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_big<true>, dim3(kGridBlocks), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
