@@ -210,31 +210,50 @@ int gsc_reset_cache(gsc_ctx* ctx);
  * host_dst and writes the full count to *n. */
 int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap, int64_t* n);
 
-/* ---------------- learned reuse predictor (Linear 6-64-64-1, sigmoid) ---- */
+/* ---------------- learned reuse predictor (Linear 6-64-64-1, sigmoid) ----
+ * North-star extension of the reuse decision of Section 4 (Alg. 1): for a
+ * visible anchor whose cache line is still valid, a small MLP reads six
+ * features (view-direction change, distance ratio, age / d_max, level /
+ * l_max, camera travel / distance, log2 projected voxel size) and predicts
+ * whether reusing it would visibly change its Gaussians; with
+ * GSC_FLAG_PREDICTOR set, anchors with p > predictor_threshold are derived
+ * again (the predictor only adds misses).  Inference uses BF16 weights and
+ * activations with FP32 accumulation. */
 #define GSC_PRED_NPARAMS (64 * 6 + 64 + 64 * 64 + 64 + 64 + 1)
-/* Load predictor parameters (host float32, order W1[64,6] b1 W2[64,64] b2
- * W3[1,64] b3). */
+/* Load predictor parameters (host float32 [GSC_PRED_NPARAMS], order W1[64,6]
+ * b1[64] W2[64,64] b2[64] W3[1,64] b3[1], rows = outputs). */
 int gsc_predictor_load(gsc_ctx* ctx, const float* params, int64_t n);
-/* Read the current parameters back (host float32, same order). */
+/* Copy the current parameters to host float32 [GSC_PRED_NPARAMS]. */
 int gsc_predictor_get(gsc_ctx* ctx, float* params, int64_t n);
-/* Train on the device with the library's own forward/backward/Adam
- * kernels: X host float32 [n,6] features, y host uint8 [n] labels.  Mini
- * batches of `batch` rows in a seeded shuffled order for `epochs` epochs;
- * BCE with positive-class weight pos_weight; Adam(lr, 0.9, 0.999, 1e-8).
- * loss_out (host, may be NULL) receives one mean loss per epoch. */
+/* Record the reuse candidates (visible anchors holding a valid line) and
+ * their features during later gsc_derive calls (enable != 0) or stop. */
+int gsc_predictor_collect(gsc_ctx* ctx, int enable);
+/* Training data from the last gsc_derive (collection on, predictor off):
+ * every candidate anchor is derived again with this frame's unified camera
+ * in FP32 and compared with its cached Gaussians.  A Gaussian's drift is
+ * the largest of |d opacity|, opacity * |d colour| (any channel) and
+ * opacity * (max |d cov| / max |cov|) / 2; label 1 (re-derive) iff the
+ * anchor's largest drift times its projected footprint area in pixels,
+ * max(1, size^2) with size = 2^X[5], exceeds 16/255 (one 8-bit level over a
+ * 4x4-pixel patch).  Collect with the predictor off.  Writes up to cap rows:
+ * X_out host float32 [cap, 6], y_out host uint8 [cap], ids_out host int32
+ * [cap] anchor ids (may be NULL); *n = candidate count.  Synchronous. */
+int gsc_predictor_labels(gsc_ctx* ctx, float* X_out, uint8_t* y_out, int32_t* ids_out, int64_t cap, int64_t* n);
+/* Train on the device with the library's own forward, backward and Adam
+ * kernels: X host float32 [n,6], y host uint8 [n].  Mini-batches of `batch`
+ * rows (<= 4096) in a shuffled order seeded by `seed`, for `epochs` epochs;
+ * mean BCE with positive-class weight pos_weight; Adam(lr, 0.9, 0.999,
+ * 1e-8).  loss_out (host, may be NULL) receives each epoch's mean loss.
+ * Synchronous. */
 int gsc_predictor_train(gsc_ctx* ctx, const float* X, const uint8_t* y, int64_t n, int32_t batch,
                         int32_t epochs, float lr, float pos_weight, uint64_t seed, float* loss_out);
-/* One forward/backward pass on device buffers (for gradient checks):
- * X [n,6] float32, y [n] float32 (0/1), device; grads_out host float32
- * [GSC_PRED_NPARAMS]; loss_out host. */
+/* One forward/backward pass over device arrays X [n,6] float32 and y [n]
+ * float32 (0/1), n <= 4096: mean loss and gradients (host float32
+ * [GSC_PRED_NPARAMS]), FP32.  Synchronous. */
 int gsc_predictor_grad(gsc_ctx* ctx, const float* X, const float* y, int64_t n, float pos_weight,
                        float* grads_out, float* loss_out);
-/* Probabilities for X [n,6] (device) into p_out [n] (device), BF16 inference path. */
+/* p(stale) for device X [n,6] into device p_out [n] (BF16 inference path). */
 int gsc_predictor_infer(gsc_ctx* ctx, const float* X, int64_t n, float* p_out);
-/* Features of the current frame's reuse candidates (device float32 out
- * [cap,6], ids int32 [cap] of the anchors); synchronous; *n = count.
- * Valid after gsc_derive. */
-int gsc_predictor_features(gsc_ctx* ctx, float* X_out, int32_t* ids_out, int64_t cap, int64_t* n);
 
 /* ---------------- serving: several viewers, one device ------------------- */
 typedef struct gsc_server gsc_server;

@@ -409,17 +409,30 @@ def reuse_features(scene, anchors, pu_now, pu_then, age, d_max, fx):
     return f
 
 
-def reuse_label(cached: dict, fresh: dict, k: int) -> np.ndarray:
-    """1 (re-derive) iff any of the anchor's k Gaussians changed by more than
-    1/255 in opacity or any colour channel, or its covariance changed by more
-    than 1 % of its largest entry."""
-    da = np.abs(cached["alpha"] - fresh["alpha"]).reshape(-1, k)
-    dc = np.abs(cached["rgb"] - fresh["rgb"]).reshape(-1, k, 3).max(2)
-    app = np.maximum(da, dc).max(1) > 1.0 / 255.0
-    ds = np.abs(cached["cov"] - fresh["cov"]).reshape(-1, k, 6).max(2)
-    sm = np.abs(fresh["cov"]).reshape(-1, k, 6).max(2)
-    geo = (ds / sm).max(1) > 1e-2
-    return (app | geo).astype(np.uint8)
+def reuse_label(cached: dict, fresh: dict, k: int, size_px) -> np.ndarray:
+    """1 (re-derive) iff reusing the anchor would change the image visibly.
+
+    Reading (the reuse decision of Section 4 only says lines are reused while
+    the view changes little): a Gaussian's drift is the largest of its
+    opacity change, its opacity times its largest colour-channel change, and
+    its opacity times half the relative change of its covariance (max |dSigma|
+    over max |Sigma| of the fresh one; half because the footprint radius goes
+    as the square root of Sigma).  The anchor's drift is the largest over its
+    k Gaussians; weighted by its projected footprint area in pixels,
+    max(1, size_px^2) with size_px = s_level f_x / distance (the last
+    feature), it must exceed 16/255, the change of a 4x4-pixel patch by one
+    8-bit level."""
+    a_c = np.asarray(cached["alpha"], np.float64).reshape(-1, k)
+    a_f = np.asarray(fresh["alpha"], np.float64).reshape(-1, k)
+    am = np.maximum(np.abs(a_c), np.abs(a_f))
+    dc = np.abs(np.asarray(cached["rgb"]) - np.asarray(fresh["rgb"])).reshape(-1, k, 3).max(2)
+    ds = np.abs(np.asarray(cached["cov"]) - np.asarray(fresh["cov"])).reshape(-1, k, 6).max(2)
+    sm = np.abs(np.asarray(fresh["cov"])).reshape(-1, k, 6).max(2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        geo = np.where(sm > 0, ds / np.where(sm > 0, sm, 1.0), np.where(ds > 0, np.inf, 0.0))
+    drift = np.maximum(np.abs(a_c - a_f), am * np.maximum(dc, 0.5 * geo)).max(1)
+    area = np.maximum(1.0, np.asarray(size_px, np.float64) ** 2)
+    return (drift * area > 16.0 / 255.0).astype(np.uint8)
 
 
 def pred_init(seed: int = 3, width: int = 64):

@@ -20,7 +20,7 @@ PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT = 1, 2, 4, 8
 GUIDE = {"linear": 0, "fixed": 1}
 DBG = {"visible": 0, "misses": 1, "gauss": 2, "derived": 3, "pairs": 4, "ranges": 5, "preproc": 6, "depth": 7}
-PRED_NPARAMS = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1
+PRED_NPARAMS = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1  # 4673
 
 
 class GscError(RuntimeError):
@@ -92,7 +92,8 @@ SYMBOLS = {
     "gsc_predictor_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p],
                            C.c_int),
     "gsc_predictor_infer": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
-    "gsc_predictor_features": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "gsc_predictor_collect": ([C.c_void_p, C.c_int], C.c_int),
+    "gsc_predictor_labels": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gsc_server_create": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "gsc_server_destroy": ([C.c_void_p], None),
     "gsc_server_admit": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
@@ -285,11 +286,20 @@ class Renderer:
     def predictor_infer(self, X_dev, p_dev):
         self._check(lib().gsc_predictor_infer(self.h, _ptr(X_dev), int(X_dev.shape[0]), _ptr(p_dev)))
 
-    def predictor_features(self, X_dev, ids_dev):
+    def predictor_collect(self, enable=True):
+        self._check(lib().gsc_predictor_collect(self.h, 1 if enable else 0))
+
+    def predictor_labels(self, with_ids=False):
+        """Features and labels of the last frame's reuse candidates (numpy)."""
         n = C.c_int64()
-        self._check(lib().gsc_predictor_features(self.h, _ptr(X_dev), _ptr(ids_dev), int(X_dev.shape[0]),
-                                                 C.byref(n)))
-        return n.value
+        self._check(lib().gsc_predictor_labels(self.h, None, None, None, 0, C.byref(n)))
+        X = np.zeros((n.value, 6), np.float32)
+        y = np.zeros(n.value, np.uint8)
+        ids = np.zeros(n.value, np.int32)
+        if n.value:
+            self._check(lib().gsc_predictor_labels(self.h, X.ctypes.data, y.ctypes.data, ids.ctypes.data, n.value,
+                                                   C.byref(n)))
+        return (X, y, ids) if with_ids else (X, y)
 
 
 def pack_params(params) -> np.ndarray:

@@ -94,17 +94,6 @@ bool valid_camera(const gsc_camera& c) {
 
 namespace gsc {
 
-template <typename T>
-hipError_t dalloc(gsc_ctx* c, size_t& acct, T** p, int64_t count) {
-    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    hipError_t e = hipMalloc((void**)p, bytes);
-    if (e == hipSuccess) {
-        acct += bytes;
-        (c->alloc_list ? c->alloc_list : &c->allocs)->push_back((void*)*p);
-    }
-    return e;
-}
-
 void free_explicit(gsc_ctx* c) {
     if (c->xallocs.empty()) return;
     (void)hipStreamSynchronize(c->stream);

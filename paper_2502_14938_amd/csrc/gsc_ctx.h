@@ -41,19 +41,35 @@ struct gsc_ctx {
     float* pred_v = nullptr;
     float* pred_g = nullptr;      // gradients
     float* pred_loss = nullptr;   // [1]
-    float* pred_X = nullptr;      // training set (device)
-    float* pred_y = nullptr;
-    int32_t* pred_idx = nullptr;  // batch row order
-    int64_t pred_cap = 0;
-    int pred_step = 0;
+    float* pred_work = nullptr;   // per-row activations and gradients of a batch
+    int32_t* pred_idx = nullptr;
+    int pred_step = 0;            // Adam steps taken
     bool pred_loaded = false;
     int collect_features = 0;
+    std::vector<void*> pred_allocs;
+    // label generation: fresh derivations of the reuse candidates
+    float4* lab_L0 = nullptr;
+    float4* lab_L1 = nullptr;
+    float4* lab_L2 = nullptr;
+    float* lab_L3 = nullptr;
+    int32_t* lab_iota = nullptr;
+    uint8_t* lab_y = nullptr;
 };
 
 namespace gsc {
 hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles);
 void free_explicit(gsc_ctx* c);
 void pred_free(gsc_ctx* c);
+
+// Device allocation recorded in the context (in *alloc_list when set).
 template <typename T>
-hipError_t dalloc(gsc_ctx* c, size_t& acct, T** p, int64_t count);
+inline hipError_t dalloc(gsc_ctx* c, size_t& acct, T** p, int64_t count) {
+    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e == hipSuccess) {
+        acct += bytes;
+        (c->alloc_list ? c->alloc_list : &c->allocs)->push_back((void*)*p);
+    }
+    return e;
+}
 }  // namespace gsc

@@ -1,0 +1,216 @@
+"""GPU checks of the learned reuse predictor.
+
+  * gradients of the library's FP32 forward/backward kernels against the
+    oracle's FP64 analytic gradients (themselves pinned by finite
+    differences), relative error <= 1e-4 per tensor;
+  * BF16 inference against the FP64 forward;
+  * training with the library's kernels lowers the loss on a learnable set;
+  * labels and features produced on the GPU against the oracle's label rule
+    evaluated on the same candidates (FP64 derivations at the caching frame
+    and at the current frame);
+  * what the trained predictor gains over the linear depth guide alone, on
+    the trade-off between re-derivations and PSNR against the uncached render.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import paper_2502_14938_amd as gs
+    gs.lib()
+    return gs
+
+
+def rnd_params(seed=3):
+    rng = np.random.default_rng(seed)
+    p = oracle.pred_init(seed=seed)
+    for i in (1, 3, 5):
+        p[i] = rng.uniform(-0.2, 0.2, p[i].shape)
+    return p
+
+
+def test_gradients_match_oracle(gs):
+    r = gs.Renderer(k=10, max_width=64, max_height=64)
+    params = rnd_params()
+    r.predictor_load(gs.pack_params(params))
+    params32 = [p.astype(np.float32).astype(np.float64) for p in params]
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((777, 6)).astype(np.float32)
+    y = (rng.uniform(size=777) < 0.3).astype(np.float32)
+    loss, g = r.predictor_grad(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), pos_weight=2.0)
+    lo, go = oracle.pred_loss_grad(params32, X.astype(np.float64), y, 2.0)
+    assert abs(loss - lo) <= 1e-5 * max(1.0, abs(lo))
+    gpu = gs.unpack_params(g)
+    for a, b in zip(gpu, go):
+        rel = np.abs(a - b).max() / max(np.abs(b).max(), 1e-12)
+        assert rel <= 1e-4, rel
+
+
+def test_bf16_inference_close_to_fp64(gs):
+    r = gs.Renderer(k=10, max_width=64, max_height=64)
+    params = rnd_params(5)
+    r.predictor_load(gs.pack_params(params))
+    X = np.random.default_rng(2).standard_normal((2000, 6)).astype(np.float32)
+    p = torch.zeros(2000, device="cuda")
+    r.predictor_infer(torch.from_numpy(X).cuda(), p)
+    torch.cuda.synchronize()
+    logit, _ = oracle.pred_forward([q.astype(np.float32).astype(np.float64) for q in params], X.astype(np.float64))
+    pref = 1 / (1 + np.exp(-logit))
+    assert np.abs(p.cpu().numpy() - pref).max() < 2e-2
+
+
+def test_training_lowers_loss(gs):
+    r = gs.Renderer(k=10, max_width=64, max_height=64)
+    r.predictor_load(gs.pack_params(oracle.pred_init(seed=3)))
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((4096, 6)).astype(np.float32)
+    y = (X[:, 0] + 0.5 * X[:, 1] > 0.2).astype(np.uint8)
+    losses = r.predictor_train(X, y, batch=512, epochs=30, lr=3e-3, pos_weight=1.0, seed=0)
+    assert losses[-1] < 0.5 * losses[0], losses
+    p = torch.zeros(4096, device="cuda")
+    r.predictor_infer(torch.from_numpy(X).cuda(), p)
+    torch.cuda.synchronize()
+    acc = ((p.cpu().numpy() > 0.5) == (y == 1)).mean()
+    assert acc > 0.95, acc
+
+
+def walk(n, step=0.25, turn=0.02, seed=0):
+    rng = np.random.default_rng(seed)
+    out, pos, ang = [], np.array([0.0, 0.0, -15.0]), 0.0
+    for i in range(n):
+        out.append(synth.stereo_pair(pos.copy(), (math.sin(ang), 0.0, math.cos(ang)), (0, -1, 0), 128, 96,
+                                     math.radians(60), math.radians(50)))
+        pos = pos + np.array([step * rng.uniform(0.5, 1.5), 0.0, 0.3 * step])
+        ang += turn * rng.uniform(-1, 1)
+    return out
+
+
+def run_collect(gs, r, traj):
+    """Render a trajectory; returns per-frame (X, y, ids) of reuse candidates."""
+    r.predictor_collect(True)
+    oL = torch.zeros(3, 96, 128, device="cuda"); oR = torch.zeros(3, 96, 128, device="cuda")
+    out = []
+    for L, R in traj:
+        r.frame(L, R, oL, oR)
+        torch.cuda.synchronize()
+        out.append(r.predictor_labels(with_ids=True))
+    r.predictor_collect(False)
+    return out
+
+
+def test_labels_match_oracle_rule(gs, tiny):
+    d_max = 10
+    traj = walk(8)
+    r = gs.Renderer(k=tiny.k, reuse=True, d_max=d_max, guide="fixed", max_width=128, max_height=96)
+    r.load(tiny)
+    frames = run_collect(gs, r, traj)
+    pus = [oracle.unified_camera(L, R)["pos"] for L, R in traj]
+    fx = 128 / (2 * math.tan(math.radians(30)))
+    agree = total = 0
+    for t, (X, y, ids) in enumerate(frames):
+        if t == 0:
+            assert len(ids) == 0  # nothing cached yet
+            continue
+        assert len(ids) > 0
+        age = np.rint(X[:, 2] * d_max).astype(int)
+        assert np.all((age >= 1) & (age <= min(t, d_max)))
+        tau = t - age
+        feats = oracle.reuse_features(tiny, ids, pus[t], np.stack([pus[q] for q in tau]), age, d_max, fx)
+        assert np.allclose(X, feats, rtol=2e-3, atol=2e-5)
+        for q in np.unique(tau):
+            sel = tau == q
+            a = oracle.derive(tiny, ids[sel], pus[q])
+            b = oracle.derive(tiny, ids[sel], pus[t])
+            lab = oracle.reuse_label(a, b, tiny.k, 2.0 ** feats[sel, 5])
+            agree += int((lab == y[sel]).sum())
+            total += int(sel.sum())
+    assert agree >= 0.995 * total, (agree, total)
+
+
+def play(gs, scene, traj, ref=None, **kw):
+    """Render a trajectory with a fresh renderer; returns (re-derivations,
+    per-eye images), or with `ref` (uncached images of the same trajectory)
+    (re-derivations, per-eye mean squared errors against them)."""
+    params = kw.pop("params", None)
+    r = gs.Renderer(k=scene.k, max_width=128, max_height=96, **kw)
+    r.load(scene)
+    if params is not None:
+        r.predictor_load(params)
+    misses, imgs = 0, []
+    for L, R in traj:
+        oL = torch.zeros(3, 96, 128, device="cuda"); oR = torch.zeros(3, 96, 128, device="cuda")
+        r.frame(L, R, oL, oR)
+        torch.cuda.synchronize()
+        misses += r.stats()["n_miss"]
+        imgs += [oL.cpu().numpy().astype(np.float64), oR.cpu().numpy().astype(np.float64)]
+    if ref is None:
+        return misses, imgs
+    return misses, np.array([np.mean((a - b) ** 2) for a, b in zip(imgs, ref)])
+
+
+def quality(mse):
+    """(pooled PSNR over all eye images, worst eye-image PSNR)."""
+    return -10 * np.log10(max(mse.mean(), 1e-30)), -10 * np.log10(max(mse.max(), 1e-30))
+
+
+def test_learned_reuse_gain(gs, tiny):
+    """What the trained predictor gains over the linear depth guide alone.
+
+    The predictor runs on top of the guide and only adds re-derivations, so it
+    is judged on the trade-off between re-derivations and image error against
+    the uncached render. Shortening the guide's maximum depth is the
+    heuristic's own way to buy quality with re-derivations; its settings
+    D = 10..1 trace a curve. At each decision threshold the predictor must sit
+    above that curve (linearly interpolated at the same number of
+    re-derivations) by at least 2 dB, both in pooled PSNR and in the worst
+    eye image's PSNR. Training labels come from one walk, the comparison from
+    another."""
+    d_max = 10
+    train = walk(40, seed=1)
+    test = walk(30, seed=2)
+    col = gs.Renderer(k=tiny.k, reuse=True, d_max=d_max, guide="linear", max_width=128, max_height=96)
+    col.load(tiny)
+    frames = run_collect(gs, col, train)
+    X = np.concatenate([f[0] for f in frames]); y = np.concatenate([f[1] for f in frames])
+    assert 0.05 < y.mean() < 0.95, y.mean()
+    pw = float((y == 0).sum()) / max(1, int((y == 1).sum()))
+    trainer = gs.Renderer(k=tiny.k, max_width=64, max_height=64)
+    trainer.predictor_load(gs.pack_params(oracle.pred_init(seed=3)))
+    losses = trainer.predictor_train(X, y, batch=1024, epochs=20, lr=1e-3, pos_weight=pw, seed=11)
+    assert losses[-1] < losses[0]
+    params = trainer.predictor_get()
+
+    _, ref = play(gs, tiny, test)
+    curve = []
+    for d in (10, 8, 6, 5, 4, 3, 2, 1):
+        m, mse = play(gs, tiny, test, ref, reuse=True, d_max=d, guide="linear")
+        curve.append((m,) + quality(mse))
+    curve.sort()
+    learned = {}
+    for thr in (0.5, 0.9, 0.99):
+        m, mse = play(gs, tiny, test, ref, reuse=True, d_max=d_max, guide="linear", predictor=True,
+                      predictor_threshold=thr, params=params)
+        learned[thr] = (m,) + quality(mse)
+    print("\nlinear guide, D = 10..1 (re-derivations, pooled PSNR, worst PSNR):", curve)
+    print("with predictor, by threshold:", learned)
+    cm = np.array([c[0] for c in curve], np.float64)
+    assert min(c[2] for c in curve) >= 40.0 and min(v[2] for v in learned.values()) >= 40.0
+    compared = 0
+    for thr, (m, pooled, worst) in learned.items():
+        assert m > curve[0][0]  # it did add work
+        if m > cm[-1]:
+            continue  # costlier than re-deriving on every other frame: off the curve
+        compared += 1
+        h_pooled = np.interp(m, cm, [c[1] for c in curve])
+        h_worst = np.interp(m, cm, [c[2] for c in curve])
+        assert pooled >= h_pooled + 2.0 and worst >= h_worst + 2.0, (thr, learned[thr], h_pooled, h_worst)
+    assert compared >= 2

@@ -57,3 +57,36 @@ def test_features_geometry():
     assert abs(f2[0, 1] - 0.0) < 1e-12
     assert abs(f2[0, 4] - np.sqrt(200.0) / 10.0) < 1e-12
     assert abs(f2[0, 5] - np.log2(0.5 * 100.0 / 10.0)) < 1e-12
+
+
+def _gauss(alpha, rgb, cov):
+    return {"alpha": np.array(alpha, np.float64), "rgb": np.array(rgb, np.float64),
+            "cov": np.array(cov, np.float64)}
+
+
+def test_reuse_label_hand_worked():
+    """Two Gaussians per anchor; each row changes one quantity by a hand-picked
+    amount, so the drift and the 16/255 (~0.0627) bound are read off by eye."""
+    eye = [1, 0, 0, 1, 0, 1]
+    base_rgb = [[0.2, 0.4, 0.6], [0.1, 0.1, 0.1]]
+    # anchor 0: nothing changes
+    # anchor 1: opacity 0.30 -> 0.31 (drift 0.01)
+    # anchor 2: red 0.2 -> 0.4 at opacity 0.5 (drift 0.1); its twin at 0.2 (drift 0.04)
+    # anchor 3: Sigma_xx 1.0 -> 1.1 at opacity 1 (relative 0.1, drift 0.05)
+    cached = _gauss([0.5, 0.5, 0.30, 0.5, 0.5, 0.5, 1.0, 0.5],
+                    base_rgb * 4,
+                    [eye] * 8)
+    fresh = _gauss([0.5, 0.5, 0.31, 0.5, 0.5, 0.5, 1.0, 0.5],
+                   base_rgb * 4,
+                   [eye] * 8)
+    fresh["rgb"][4, 0] = 0.4
+    cached["cov"][6, 0] = 1.1
+    lab = oracle.reuse_label(cached, fresh, 2, size_px=[1.0, 1.0, 1.0, 1.0])
+    assert lab.tolist() == [0, 0, 1, 0]
+    # footprint 3x3 px: 0.01 * 9 = 0.09 > 0.0627; 2x2 px: 0.05 * 4 = 0.2
+    lab = oracle.reuse_label(cached, fresh, 2, size_px=[5.0, 3.0, 0.5, 2.0])
+    assert lab.tolist() == [0, 1, 1, 1]
+    # below one pixel the area counts as one: 0.04 stays below the bound
+    cached["alpha"][4] = fresh["alpha"][4] = 0.2
+    assert oracle.reuse_label(cached, fresh, 2, size_px=[1.0, 0.1, 0.1, 0.1]).tolist() == [0, 0, 0, 0]
+    assert oracle.reuse_label(cached, fresh, 2, size_px=[1.0, 1.0, 1.3, 1.0]).tolist() == [0, 0, 1, 0]
