@@ -255,32 +255,54 @@ int gsc_predictor_grad(gsc_ctx* ctx, const float* X, const float* y, int64_t n, 
 /* p(stale) for device X [n,6] into device p_out [n] (BF16 inference path). */
 int gsc_predictor_infer(gsc_ctx* ctx, const float* X, int64_t n, float* p_out);
 
-/* ---------------- serving: several viewers, one device ------------------- */
+/* ---------------- serving: several viewers, one device -------------------
+ * North-star extension around the per-frame path of Section 4 (the paper's
+ * own scheduler, Section 5, is multi-GPU and not this): continuous batching
+ * of stereo frame requests from several viewers of uneven resolution, each
+ * with its own device cache, over one shared scene.  Every call on a server
+ * comes from one host thread; calls on one server never overlap. */
 typedef struct gsc_server gsc_server;
-/* A server shares the scene of `scene_ctx` (which must stay alive) among
- * viewers.  budget_bytes caps the device memory of all admitted viewers. */
+/* A server shares the scene (and predictor) of `scene_ctx`, which must stay
+ * alive, be loaded with de-redundancy on, and not be rendered with while the
+ * server runs.  budget_bytes caps the device memory of all admitted viewers
+ * (their caches, per-frame buffers and batch-raster shares).  All work goes
+ * on `stream` (NULL = the default stream). */
 int gsc_server_create(gsc_ctx* scene_ctx, int64_t budget_bytes, void* stream, gsc_server** out);
+/* Waits for outstanding batches, then frees everything. */
 void gsc_server_destroy(gsc_server* s);
-/* Admit a viewer whose eyes are at most max_width x max_height: returns a
- * viewer id >= 0, or GSC_E_BUDGET if its buffers do not fit the budget
- * now (the caller retries after a viewer leaves). */
-int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height);
-/* Bytes a viewer of this size would take (for admission planning). */
+const char* gsc_server_last_error(const gsc_server* s);
+/* Device bytes a viewer of at most max_width x max_height per eye takes:
+ * cache lines (capacity of the scene context's config, or one per anchor),
+ * slot map, per-frame lists, and its share of the batch raster (entries for
+ * two eyes of a full cache, tile pairs: max_pairs of the config, else
+ * 16 per pixel of both eyes within [2^22, min(24 per entry, 2^27)]). */
 int64_t gsc_server_viewer_bytes(gsc_server* s, int32_t max_width, int32_t max_height);
-/* Queue one stereo frame for a viewer: cameras are copied; outputs are
- * caller device buffers [3,H,W] float32 per eye that stay valid until the
- * frame completes.  Returns a request id >= 0. */
+/* Admit a viewer: returns a viewer id >= 0, or GSC_E_BUDGET when its bytes
+ * do not fit the budget beside the viewers already admitted (retry after
+ * one leaves).  Waits for outstanding batches (the batch raster is resized). */
+int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height);
+/* Queue one stereo frame for a viewer: cameras are copied (eyes share
+ * intrinsics, at most the admitted size); outputs are caller device buffers
+ * float32 [3,H,W] per eye that must stay valid until the request completes.
+ * t_arrival is carried for FIFO order.  Returns a request id >= 0. */
 int64_t gsc_server_submit(gsc_server* s, int32_t viewer, const gsc_camera* left, const gsc_camera* right,
                           double t_arrival, float* out_left, float* out_right);
-/* Launch every queued request of every viewer as one batch: per viewer the
- * derive stage, then one persistent blend launch over all (viewer, eye,
- * tile) work items.  Returns the number of requests launched (asynchronous). */
+/* Form one batch from the oldest queued request of each of up to 8 viewers
+ * (oldest arrival first) and enqueue it: per viewer the derive stage on its
+ * own cache, then one raster batch over all (viewer, eye) images ending in
+ * one persistent blend launch.  Asynchronous; returns the number of
+ * requests launched (0 when nothing is queued). */
 int gsc_server_step(gsc_server* s);
 /* Completed requests since the last poll (non-blocking): writes up to cap
- * request ids and their completion times (seconds, host monotonic clock,
- * taken when the device finished) and returns the count. */
-int gsc_server_poll(gsc_server* s, int64_t* ids, double* t_done, int32_t cap);
-/* Remove a viewer and free its buffers (after its requests complete). */
+ * request ids, completion times (seconds on the host monotonic clock, taken
+ * when the device finished the batch) and statuses (GSC_OK, or
+ * GSC_E_CAPACITY when the batch ran out of cache lines or tile pairs; status
+ * may be NULL); returns the count. */
+int gsc_server_poll(gsc_server* s, int64_t* ids, double* t_done, int32_t* status, int32_t cap);
+/* Requests queued or in flight. */
+int gsc_server_pending(gsc_server* s);
+/* Remove a viewer with no queued requests and free its buffers (waits for
+ * outstanding batches). */
 int gsc_server_leave(gsc_server* s, int32_t viewer);
 
 #ifdef __cplusplus

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgscache.so")
 
 GSC_OK = 0
+GSC_E_INVALID_ARG, GSC_E_NOT_LOADED, GSC_E_OOM, GSC_E_CAPACITY, GSC_E_BUDGET, GSC_E_HIP = -1, -2, -3, -4, -5, -6
 ERRORS = {-1: "GSC_E_INVALID_ARG", -2: "GSC_E_NOT_LOADED", -3: "GSC_E_OOM", -4: "GSC_E_CAPACITY",
           -5: "GSC_E_BUDGET", -6: "GSC_E_HIP"}
 PREC = {"f32": 0, "bf16": 1, "fp8": 2}
@@ -101,7 +102,9 @@ SYMBOLS = {
     "gsc_server_submit": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p],
                           C.c_int64),
     "gsc_server_step": ([C.c_void_p], C.c_int),
-    "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "gsc_server_pending": ([C.c_void_p], C.c_int),
+    "gsc_server_last_error": ([C.c_void_p], C.c_char_p),
     "gsc_server_leave": ([C.c_void_p, C.c_int32], C.c_int),
 }
 
@@ -316,3 +319,73 @@ def unpack_params(flat) -> list:
         out.append(flat[o:o + m].reshape(s))
         o += m
     return out
+
+
+class Server:
+    """Continuous-batching server over the scene of a loaded Renderer
+    (gsc_server_*): viewers with their own device caches, admitted against a
+    device-memory budget; frame requests batched across viewers."""
+
+    def __init__(self, renderer: Renderer, budget_bytes: int, stream=None):
+        h = C.c_void_p()
+        st = stream if stream is not None else _current_stream()
+        rc = lib().gsc_server_create(renderer.h, int(budget_bytes), st, C.byref(h))
+        if rc != GSC_OK:
+            raise GscError(rc, "gsc_server_create failed (scene loaded with de-redundancy? predictor loaded?)")
+        self.h = h
+        self.renderer = renderer  # keeps the scene alive
+        self._outs = {}
+
+    def _check(self, rc):
+        if rc is not None and rc < 0:
+            raise GscError(rc, (lib().gsc_server_last_error(self.h) or b"").decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gsc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def viewer_bytes(self, width, height) -> int:
+        return self._check(lib().gsc_server_viewer_bytes(self.h, width, height))
+
+    def admit(self, width, height):
+        """Viewer id, or None when the budget does not allow it now."""
+        rc = lib().gsc_server_admit(self.h, width, height)
+        if rc == GSC_E_BUDGET:
+            return None
+        return self._check(rc)
+
+    def submit(self, viewer, left: dict, right: dict, t_arrival, out_left, out_right) -> int:
+        l, r = camera(left), camera(right)
+        rid = self._check(lib().gsc_server_submit(self.h, viewer, C.byref(l), C.byref(r), float(t_arrival),
+                                                  _ptr(out_left), _ptr(out_right)))
+        self._outs[rid] = (out_left, out_right)  # keep the buffers alive until completion
+        return rid
+
+    def step(self) -> int:
+        return self._check(lib().gsc_server_step(self.h))
+
+    def poll(self, cap=256):
+        """[(request id, completion time, status)] finished since the last poll."""
+        ids = np.zeros(cap, np.int64)
+        t = np.zeros(cap, np.float64)
+        stt = np.zeros(cap, np.int32)
+        n = self._check(lib().gsc_server_poll(self.h, ids.ctypes.data, t.ctypes.data, stt.ctypes.data, cap))
+        out = []
+        for i in range(n):
+            self._outs.pop(int(ids[i]), None)
+            out.append((int(ids[i]), float(t[i]), int(stt[i])))
+        return out
+
+    def pending(self) -> int:
+        return self._check(lib().gsc_server_pending(self.h))
+
+    def leave(self, viewer):
+        self._check(lib().gsc_server_leave(self.h, viewer))

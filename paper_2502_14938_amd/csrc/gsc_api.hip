@@ -33,6 +33,10 @@ int hip_fail(gsc_ctx* c, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(c, e_, #x);   \
     } while (0)
 
+}  // namespace
+
+namespace gsc {
+
 // --------------------------------------------------------- unified camera
 // Binocular stereo de-redundancy (Section 4, eqs. 5-6), in double precision.
 
@@ -61,7 +65,7 @@ void unified_camera(const gsc_camera& l, const gsc_camera& r, gsc_camera& u) {
 }
 
 // Frustum planes of a camera in world space, inward: n.x + w >= -radius.
-DeriveCam derive_cam(const gsc_camera& c, double d_ref) {
+DeriveCam derive_cam(const gsc_camera& c, float d_ref) {
     DeriveCam dc;
     double tx = std::tan(0.5 * c.fovx), ty = std::tan(0.5 * c.fovy);
     double nx = std::sqrt(1.0 + tx * tx), ny = std::sqrt(1.0 + ty * ty);
@@ -90,30 +94,33 @@ bool valid_camera(const gsc_camera& c) {
            c.znear > 0 && std::isfinite(c.pos[0]) && std::isfinite(c.pos[1]) && std::isfinite(c.pos[2]);
 }
 
-}  // namespace
-
-namespace gsc {
 
 void free_explicit(gsc_ctx* c) {
-    if (c->xallocs.empty()) return;
+    if (c->xmem.empty()) return;
     (void)hipStreamSynchronize(c->stream);
-    for (void* p : c->xallocs) (void)hipFree(p);
-    c->xallocs.clear();
-    for (void* p : c->xhost_allocs) (void)hipHostFree(p);
-    c->xhost_allocs.clear();
+    c->xmem.release();
+    c->xraster = Raster();
     c->xg = {};
     c->xg_cap = 0;
     c->xg_bytes = 0;
-    c->xraster = Raster();
+}
+
+void free_labels(gsc_ctx* c) {
+    if (c->lmem.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->lmem.release();
+    c->lab_L0 = c->lab_L1 = c->lab_L2 = nullptr;
+    c->lab_L3 = nullptr;
+    c->lab_iota = nullptr;
+    c->lab_y = nullptr;
+    c->lab_entries = 0;
 }
 
 void free_all(gsc_ctx* c) {
-    if (c->allocs.empty()) return;
+    free_labels(c);
+    if (c->mem.empty()) return;
     (void)hipStreamSynchronize(c->stream);
-    for (void* p : c->allocs) (void)hipFree(p);
-    c->allocs.clear();
-    for (void* p : c->host_allocs) (void)hipHostFree(p);
-    c->host_allocs.clear();
+    c->mem.release();
     c->scene = Scene();
     c->view[0] = View();
     c->view[1] = View();
@@ -121,34 +128,29 @@ void free_all(gsc_ctx* c) {
     c->loaded = false;
 }
 
-hipError_t alloc_view(gsc_ctx* c, View& v, int64_t n, int64_t C, int k) {
-    size_t& b = v.bytes;
-    v.C = C;
-    v.max_gauss = C * k;
-    int64_t m = n > C ? n : C;
+// Buffers of one view (viewer): cache lines, slot map, per-frame lists and
+// scratch.  A(p, count) allocates or only counts.
+template <class Fn>
+hipError_t view_layout(View& v, int64_t n, int64_t C, int k, Fn&& A) {
+    const int64_t m = n > C ? n : C;
     hipError_t e;
-#define A_(p, cnt) if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) return e
+#define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
     A_(v.slot_of, n); A_(v.line_anchor, C); A_(v.line_tau, C); A_(v.line_last, C);
     A_(v.L0, C * k); A_(v.L1, C * k); A_(v.L2, C * k); A_(v.L3, C * k);
     A_(v.pu_hist, 64 * 4); A_(v.visible, n); A_(v.vslot, n);
     A_(v.tmp_a, m); A_(v.tmp_b, m); A_(v.tmp_c, m); A_(v.tmp_d, m);
     A_(v.evict_hist, 64); A_(v.evict_scan_n, 1);
-    A_(v.misses, n); A_(v.free_list, C); A_(v.G, v.max_gauss); A_(v.block_sums, kScanBlocks);
+    A_(v.misses, n); A_(v.free_list, C); A_(v.G, C * k); A_(v.block_sums, kScanBlocks);
     A_(v.cand_feat, n * kPredIn); A_(v.cand_id, n); A_(v.cnt, 1);
 #undef A_
-    if ((e = hipHostMalloc((void**)&v.cnt_host, sizeof(Counters))) != hipSuccess) return e;
-    c->host_allocs.push_back(v.cnt_host);
     return hipSuccess;
 }
 
-hipError_t alloc_raster(gsc_ctx* c, Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles,
-                        bool full_key) {
-    size_t& b = r.bytes;
-    r.max_entries = max_entries;
-    r.max_pairs = max_pairs;
-    r.max_tiles = max_tiles;
+// Buffers of one raster batch.
+template <class Fn>
+hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key, Fn&& A) {
     hipError_t e;
-#define A_(p, cnt) if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) return e
+#define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
     A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
     A_(r.big_list, max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
@@ -158,9 +160,49 @@ hipError_t alloc_raster(gsc_ctx* c, Raster& r, int64_t max_entries, int64_t max_
     A_(r.ranges, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks); A_(r.block_sums, kScanBlocks);
     A_(r.n_sort, 1); A_(r.cnt, 1);
 #undef A_
-    if ((e = hipHostMalloc((void**)&r.cnt_host, sizeof(RasterCounters))) != hipSuccess) return e;
-    (c->alloc_list ? &c->xhost_allocs : &c->host_allocs)->push_back(r.cnt_host);
     return hipSuccess;
+}
+
+struct ByteCounter {
+    size_t bytes = 0;
+    template <typename T>
+    hipError_t operator()(T*&, int64_t count) {
+        bytes += (size_t)(count > 0 ? count : 1) * sizeof(T);
+        return hipSuccess;
+    }
+};
+
+size_t view_bytes(int64_t n, int64_t C, int k) {
+    View v;
+    ByteCounter bc;
+    (void)view_layout(v, n, C, k, bc);
+    return bc.bytes;
+}
+
+size_t raster_bytes(int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key) {
+    Raster r;
+    ByteCounter bc;
+    (void)raster_layout(r, max_entries, max_pairs, max_tiles, full_key, bc);
+    return bc.bytes;
+}
+
+hipError_t alloc_view(AllocSet& set, View& v, int64_t n, int64_t C, int k) {
+    v.C = C;
+    v.max_gauss = C * k;
+    hipError_t e = view_layout(v, n, C, k, [&](auto*& p, int64_t cnt) { return dalloc(set, v.bytes, &p, cnt); });
+    if (e != hipSuccess) return e;
+    return halloc(set, &v.cnt_host, 1);
+}
+
+hipError_t alloc_raster(AllocSet& set, Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles,
+                        bool full_key) {
+    r.max_entries = max_entries;
+    r.max_pairs = max_pairs;
+    r.max_tiles = max_tiles;
+    hipError_t e = raster_layout(r, max_entries, max_pairs, max_tiles, full_key,
+                                 [&](auto*& p, int64_t cnt) { return dalloc(set, r.bytes, &p, cnt); });
+    if (e != hipSuccess) return e;
+    return halloc(set, &r.cnt_host, 1);
 }
 
 __global__ void k_reset_view(int32_t* slot_of, int64_t n, int32_t* line_anchor, int32_t* line_tau, int32_t* line_last,
@@ -180,8 +222,8 @@ __global__ void k_reset_view(int32_t* slot_of, int64_t n, int32_t* line_anchor, 
     }
 }
 
-hipError_t reset_view(gsc_ctx* c, View& v, int64_t n, int dmax) {
-    hipLaunchKernelGGL(k_reset_view, dim3(1024), dim3(256), 0, c->stream, v.slot_of, n, v.line_anchor, v.line_tau,
+hipError_t reset_view(View& v, int64_t n, int dmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_view, dim3(1024), dim3(256), 0, st, v.slot_of, n, v.line_anchor, v.line_tau,
                        v.line_last, v.C, v.cnt, dmax);
     v.t = 0;
     return hipGetLastError();
@@ -208,14 +250,12 @@ hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles
         int64_t pairs = c->cfg.max_pairs > 0 ? c->cfg.max_pairs : 64 * cap;
         if (pairs > (1ll << 31) - 1) pairs = (1ll << 31) - 1;
         int64_t tiles = ntiles > 1 ? ntiles : 1;
-        c->alloc_list = &c->xallocs;
         hipError_t e = hipSuccess;
-        if ((e = dalloc(c, c->xg_bytes, &c->xg.L0, cap)) == hipSuccess &&
-            (e = dalloc(c, c->xg_bytes, &c->xg.L1, cap)) == hipSuccess &&
-            (e = dalloc(c, c->xg_bytes, &c->xg.L2, cap)) == hipSuccess &&
-            (e = dalloc(c, c->xg_bytes, &c->xg.L3, cap)) == hipSuccess)
-            e = alloc_raster(c, c->xraster, cap, pairs, tiles, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
-        c->alloc_list = nullptr;
+        if ((e = dalloc(c->xmem, c->xg_bytes, &c->xg.L0, cap)) == hipSuccess &&
+            (e = dalloc(c->xmem, c->xg_bytes, &c->xg.L1, cap)) == hipSuccess &&
+            (e = dalloc(c->xmem, c->xg_bytes, &c->xg.L2, cap)) == hipSuccess &&
+            (e = dalloc(c->xmem, c->xg_bytes, &c->xg.L3, cap)) == hipSuccess)
+            e = alloc_raster(c->xmem, c->xraster, cap, pairs, tiles, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
         if (e != hipSuccess) {
             free_explicit(c);
             return e;
@@ -335,7 +375,7 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
     size_t& b = sc.bytes;
     hipError_t e;
 #define A_(p, cnt)                                                         \
-    if ((e = dalloc(c, b, &p, cnt)) != hipSuccess) {                       \
+    if ((e = dalloc(c->mem, b, &p, cnt)) != hipSuccess) {                       \
         free_all(c);                                                       \
         return fail(c, GSC_E_OOM, "gsc_load_anchors: device allocation"); \
     }
@@ -348,11 +388,11 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
     sc.n_at = hf.n_at; sc.n_ct = hf.n_ct; sc.n_vt = hf.n_vt;
 #undef A_
     for (int vi = 0; vi < nviews; ++vi)
-        if (alloc_view(c, c->view[vi], n, C, k) != hipSuccess) {
+        if (alloc_view(c->mem, c->view[vi], n, C, k) != hipSuccess) {
             free_all(c);
             return fail(c, GSC_E_OOM, "gsc_load_anchors: view allocation");
         }
-    if (alloc_raster(c, c->raster, max_entries, max_pairs, 2 * ntx * nty,
+    if (alloc_raster(c->mem, c->raster, max_entries, max_pairs, 2 * ntx * nty,
                      (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0) != hipSuccess) {
         free_all(c);
         return fail(c, GSC_E_OOM, "gsc_load_anchors: raster allocation");
@@ -376,7 +416,7 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
     HIP_OR_FAIL(c, up(sc.fr_b2, hf.b2.data(), hf.b2.size() * 4));
     HIP_OR_FAIL(c, up(sc.fr_s1, hf.s1.data(), hf.s1.size() * 4));
     HIP_OR_FAIL(c, up(sc.fr_s2, hf.s2.data(), hf.s2.size() * 4));
-    for (int vi = 0; vi < nviews; ++vi) HIP_OR_FAIL(c, reset_view(c, c->view[vi], n, c->cfg.d_max));
+    for (int vi = 0; vi < nviews; ++vi) HIP_OR_FAIL(c, reset_view(c->view[vi], n, c->cfg.d_max, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(st));
     c->nviews = nviews;
     c->loaded = true;
@@ -535,7 +575,7 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
 int gsc_reset_cache(gsc_ctx* c) {
     if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_reset_cache: null context");
     if (!c->loaded) return fail(c, GSC_E_NOT_LOADED, "gsc_reset_cache: no scene loaded");
-    for (int vi = 0; vi < c->nviews; ++vi) HIP_OR_FAIL(c, reset_view(c, c->view[vi], c->scene.n, c->cfg.d_max));
+    for (int vi = 0; vi < c->nviews; ++vi) HIP_OR_FAIL(c, reset_view(c->view[vi], c->scene.n, c->cfg.d_max, c->stream));
     c->derived = false;
     return GSC_OK;
 }

@@ -51,6 +51,7 @@ struct RasterCounters {
     int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
     int32_t overflow;             // bit0: pair capacity
     int32_t n_big;                // entries in the large-footprint list
+    int32_t blend_next[8];        // persistent blend: next tile of each XCD's share
     int32_t pad;
 };
 

@@ -5,16 +5,62 @@
 
 #include "gsc_common.h"
 
+namespace gsc {
+// Device and pinned host allocations owned together (freed together).
+struct AllocSet {
+    std::vector<void*> dev, host;
+    size_t bytes = 0;  // device bytes
+    void release() {
+        for (void* p : dev) (void)hipFree(p);
+        for (void* p : host) (void)hipHostFree(p);
+        dev.clear();
+        host.clear();
+        bytes = 0;
+    }
+    bool empty() const { return dev.empty() && host.empty(); }
+};
+
+// Device allocation of count elements recorded in `set`; acct also counts it.
+template <typename T>
+inline hipError_t dalloc(AllocSet& set, size_t& acct, T** p, int64_t count) {
+    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e == hipSuccess) {
+        acct += bytes;
+        set.bytes += bytes;
+        set.dev.push_back((void*)*p);
+    }
+    return e;
+}
+
+template <typename T>
+inline hipError_t halloc(AllocSet& set, T** p, int64_t count) {
+    hipError_t e = hipHostMalloc((void**)p, (size_t)(count > 0 ? count : 1) * sizeof(T));
+    if (e == hipSuccess) set.host.push_back((void*)*p);
+    return e;
+}
+
+// Exact device bytes alloc_view / alloc_raster will take (admission planning).
+size_t view_bytes(int64_t n, int64_t C, int k);
+size_t raster_bytes(int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key);
+hipError_t alloc_view(AllocSet& set, View& v, int64_t n, int64_t C, int k);
+hipError_t alloc_raster(AllocSet& set, Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles,
+                        bool full_key);
+hipError_t reset_view(View& v, int64_t n, int dmax, hipStream_t st);
+DeriveCam derive_cam(const gsc_camera& c, float d_ref);
+void unified_camera(const gsc_camera& l, const gsc_camera& r, gsc_camera& u);
+bool valid_camera(const gsc_camera& c);
+}  // namespace gsc
+
 struct gsc_ctx {
     gsc_config cfg{};
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
-    std::vector<void*> allocs;       // device allocations owned by the context
-    std::vector<void*> host_allocs;  // pinned host allocations
-    std::vector<void*> xallocs;      // buffers of the raster-only entry
-    std::vector<void*> xhost_allocs;
-    std::vector<void*>* alloc_list = nullptr;  // where dalloc records (nullptr = allocs)
+    gsc::AllocSet mem;               // scene, views and raster of the stereo path
+    gsc::AllocSet xmem;              // buffers of the raster-only entry
+    gsc::AllocSet pmem;              // reuse predictor parameters and training buffers
+    gsc::AllocSet lmem;              // label scratch, sized for the loaded scene
     gsc::Scene scene;
     gsc::View view[2];               // view[1] only without de-redundancy (per-eye derive)
     gsc::Raster raster;
@@ -46,7 +92,6 @@ struct gsc_ctx {
     int pred_step = 0;            // Adam steps taken
     bool pred_loaded = false;
     int collect_features = 0;
-    std::vector<void*> pred_allocs;
     // label generation: fresh derivations of the reuse candidates
     float4* lab_L0 = nullptr;
     float4* lab_L1 = nullptr;
@@ -54,22 +99,12 @@ struct gsc_ctx {
     float* lab_L3 = nullptr;
     int32_t* lab_iota = nullptr;
     uint8_t* lab_y = nullptr;
+    int64_t lab_entries = 0;      // anchors * k the label scratch holds
 };
 
 namespace gsc {
 hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles);
 void free_explicit(gsc_ctx* c);
+void free_labels(gsc_ctx* c);
 void pred_free(gsc_ctx* c);
-
-// Device allocation recorded in the context (in *alloc_list when set).
-template <typename T>
-inline hipError_t dalloc(gsc_ctx* c, size_t& acct, T** p, int64_t count) {
-    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    hipError_t e = hipMalloc((void**)p, bytes);
-    if (e == hipSuccess) {
-        acct += bytes;
-        (c->alloc_list ? c->alloc_list : &c->allocs)->push_back((void*)*p);
-    }
-    return e;
-}
 }  // namespace gsc

@@ -255,19 +255,15 @@ int fail(gsc_ctx* c, int code, const char* msg) {
 
 hipError_t ensure_pred(gsc_ctx* c) {
     if (c->pred_w) return hipSuccess;
-    std::vector<void*>* keep = c->alloc_list;
-    c->alloc_list = &c->pred_allocs;
     size_t b = 0;
     hipError_t e;
-    if ((e = dalloc(c, b, &c->pred_w, P)) != hipSuccess || (e = dalloc(c, b, &c->pred_wbf, P)) != hipSuccess ||
-        (e = dalloc(c, b, &c->pred_m, P)) != hipSuccess || (e = dalloc(c, b, &c->pred_v, P)) != hipSuccess ||
-        (e = dalloc(c, b, &c->pred_g, P + 1)) != hipSuccess || (e = dalloc(c, b, &c->pred_loss, 1)) != hipSuccess ||
-        (e = dalloc(c, b, &c->pred_work, (size_t)kMaxRows * (kPredIn + 4 * kPredW + 2))) != hipSuccess ||
-        (e = dalloc(c, b, &c->pred_idx, kMaxRows)) != hipSuccess) {
-        c->alloc_list = keep;
+    if ((e = dalloc(c->pmem, b, &c->pred_w, P)) != hipSuccess || (e = dalloc(c->pmem, b, &c->pred_wbf, P)) != hipSuccess ||
+        (e = dalloc(c->pmem, b, &c->pred_m, P)) != hipSuccess || (e = dalloc(c->pmem, b, &c->pred_v, P)) != hipSuccess ||
+        (e = dalloc(c->pmem, b, &c->pred_g, P + 1)) != hipSuccess || (e = dalloc(c->pmem, b, &c->pred_loss, 1)) != hipSuccess ||
+        (e = dalloc(c->pmem, b, &c->pred_work, (size_t)kMaxRows * (kPredIn + 4 * kPredW + 2))) != hipSuccess ||
+        (e = dalloc(c->pmem, b, &c->pred_idx, kMaxRows)) != hipSuccess) {
         return e;
     }
-    c->alloc_list = keep;
     return hipSuccess;
 }
 
@@ -289,12 +285,14 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, st
 }  // namespace
 
 void pred_free(gsc_ctx* c) {
-    if (c->pred_allocs.empty()) return;
+    free_labels(c);
+    if (c->pmem.empty()) return;
     (void)hipStreamSynchronize(c->stream);
-    for (void* p : c->pred_allocs) (void)hipFree(p);
-    c->pred_allocs.clear();
+    c->pmem.release();
     c->pred_w = nullptr;
     c->pred_wbf = nullptr;
+    c->pred_m = c->pred_v = c->pred_g = c->pred_loss = c->pred_work = nullptr;
+    c->pred_idx = nullptr;
     c->pred_loaded = false;
 }
 
@@ -345,19 +343,18 @@ int gsc_predictor_labels(gsc_ctx* c, float* X_out, uint8_t* y_out, int32_t* ids_
     View& v = c->view[0];
     const Scene& sc = c->scene;
     hipStream_t st = c->stream;
-    if (!c->lab_L0) {  // scratch lines for fresh derivations of the candidates
-        std::vector<void*>* keep = c->alloc_list;
-        c->alloc_list = &c->pred_allocs;
+    const int64_t E = sc.n * sc.k;
+    if (c->lab_entries < E) {  // scratch lines for fresh derivations of the candidates
+        free_labels(c);
         size_t b = 0;
-        const int64_t E = sc.n * sc.k;
         hipError_t e;
-        if ((e = dalloc(c, b, &c->lab_L0, E)) != hipSuccess || (e = dalloc(c, b, &c->lab_L1, E)) != hipSuccess ||
-            (e = dalloc(c, b, &c->lab_L2, E)) != hipSuccess || (e = dalloc(c, b, &c->lab_L3, E)) != hipSuccess ||
-            (e = dalloc(c, b, &c->lab_iota, sc.n)) != hipSuccess || (e = dalloc(c, b, &c->lab_y, sc.n)) != hipSuccess) {
-            c->alloc_list = keep;
+        if ((e = dalloc(c->lmem, b, &c->lab_L0, E)) != hipSuccess || (e = dalloc(c->lmem, b, &c->lab_L1, E)) != hipSuccess ||
+            (e = dalloc(c->lmem, b, &c->lab_L2, E)) != hipSuccess || (e = dalloc(c->lmem, b, &c->lab_L3, E)) != hipSuccess ||
+            (e = dalloc(c->lmem, b, &c->lab_iota, sc.n)) != hipSuccess || (e = dalloc(c->lmem, b, &c->lab_y, sc.n)) != hipSuccess) {
+            free_labels(c);
             return fail(c, GSC_E_OOM, "gsc_predictor_labels: device allocation");
         }
-        c->alloc_list = keep;
+        c->lab_entries = E;
         hipLaunchKernelGGL(k_iota, dim3(blocks_for(sc.n)), dim3(NT), 0, st, c->lab_iota, sc.n);
     }
     // derive every candidate again with this frame's unified camera, FP32

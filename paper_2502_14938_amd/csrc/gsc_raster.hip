@@ -11,7 +11,10 @@
 //                      emitted in depth order (LDS-staged, coalesced)
 //   tile radix pass    stable sort of pairs by global tile id (the high bits)
 //   k_ranges           [start, end) of every tile's run
-//   k_blend            front-to-back compositing, one block per tile,
+//   k_blend            front-to-back compositing, persistent: a grid that
+//                      fills the chip takes tiles from per-XCD queues (each
+//                      XCD's contiguous share of the batch's tiles first,
+//                      then the others'), 16x16 pixels per block,
 //                      LDS-staged Gaussian batches, block-wide early exit
 // With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
 // key and are sorted after duplication instead; the order is the same.
@@ -54,6 +57,7 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
     rc->entry_base[tab.n] = acc;
     rc->overflow = 0;
     rc->n_big = 0;
+    for (int x = 0; x < 8; ++x) rc->blend_next[x] = 0;
     if (acc > max_entries) {
         rc->overflow |= 2;
         acc = (int32_t)max_entries;
@@ -538,72 +542,119 @@ __global__ __launch_bounds__(NT) void k_seg_pairs(const int32_t* __restrict__ ra
 // Gaussians shared by neighbouring tiles are gathered through one L2.
 // Gaussians are staged in LDS 256 at a time; the block stops as soon as
 // every pixel has reached the transmittance floor.
+// Next tile for a block on XCD `xcd`: its own XCD's contiguous share of the
+// batch's tiles first, then the other XCDs' shares.  `qi` counts the queues
+// found empty (kept by the calling thread).  -1 when all are drained.
+__device__ __forceinline__ int next_tile(int32_t* q, int xcd, int q8, int r8, int& qi) {
+    while (qi < 8) {
+        const int x = (xcd + qi) & 7;
+        const int len = q8 + (x < r8 ? 1 : 0);
+        const int j = atomicAdd(&q[x], 1);
+        if (j < len) return x * q8 + min(x, r8) + j;
+        ++qi;
+    }
+    return -1;
+}
+
 __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int32_t* __restrict__ ranges,
                                                           const uint32_t* __restrict__ vals,
-                                                          const float4* __restrict__ rec, uint32_t max_entries) {
+                                                          const float4* __restrict__ rec, uint32_t max_entries,
+                                                          RasterCounters* rc) {
     __shared__ float4 sA[kBlendThreads];
     __shared__ float4 sB[kBlendThreads];
     __shared__ float sC[kBlendThreads];
+    __shared__ int s_tile;
     const int total = tab.total_tiles;
     const int q8 = total >> 3, r8 = total & 7;
-    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int gt = xcd * q8 + min(xcd, r8) + j;
-    int si = 0;
-    while (si + 1 < tab.n && gt >= tab.s[si + 1].tile_base) ++si;
-    const Seg& s = tab.s[si];
-    const int lt = gt - s.tile_base;
-    const int tx = lt % s.ntx, ty = lt / s.ntx;
-    const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-    const int py = ty * kTile + (threadIdx.x / kTile);
-    const bool inside = px < s.W && py < s.H;
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    int32_t nc = 0;
-    bool done = !inside;
-    for (int32_t base = start; base < end; base += kBlendThreads) {
-        if (__syncthreads_count(done) == kBlendThreads) break;
-        int32_t i = base + (int32_t)threadIdx.x;
-        if (i < end) {
-            uint32_t e = vals[i];
-            e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
-            const float4* rp = rec + kRec * (int64_t)e;
-            sA[threadIdx.x] = rp[0];
-            sB[threadIdx.x] = rp[1];
-            sC[threadIdx.x] = rp[2].x;
-        }
-        __syncthreads();
-        const int nb = min(kBlendThreads, end - base);
-        if (!done) {
-            for (int k = 0; k < nb; ++k) {
-                float4 A = sA[k];
-                float4 B = sB[k];
-                float dx = fx - A.x, dy = fy - A.y;
-                float q = A.z * dx * dx + 2.0f * A.w * dx * dy + B.x * dy * dy;
-                float al = fminf(0.99f, B.y * __expf(-0.5f * q));
-                if (al < kMinAlpha) continue;
-                float tn = T * (1.0f - al);
-                if (tn < kTStop) {
-                    done = true;
-                    break;
+    const int xcd = blockIdx.x & 7;  // workgroups are dealt to the 8 XCDs round-robin
+    int qi = 0;
+    if (threadIdx.x == 0) s_tile = next_tile(rc->blend_next, xcd, q8, r8, qi);
+    __syncthreads();
+    int gt = s_tile;
+    while (gt >= 0) {
+        // claim the following tile now; it is only read after this one
+        int nxt = -1;
+        if (threadIdx.x == 0) nxt = next_tile(rc->blend_next, xcd, q8, r8, qi);
+        int si = 0;
+        while (si + 1 < tab.n && gt >= tab.s[si + 1].tile_base) ++si;
+        const Seg& s = tab.s[si];
+        const int lt = gt - s.tile_base;
+        const int tx = lt % s.ntx, ty = lt / s.ntx;
+        const int px = tx * kTile + (threadIdx.x & (kTile - 1));
+        const int py = ty * kTile + (threadIdx.x / kTile);
+        const bool inside = px < s.W && py < s.H;
+        const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+        const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+        float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+        int32_t nc = 0;
+        bool done = !inside;
+        for (int32_t base = start; base < end; base += kBlendThreads) {
+            if (__syncthreads_count(done) == kBlendThreads) break;
+            int32_t i = base + (int32_t)threadIdx.x;
+            if (i < end) {
+                uint32_t e = vals[i];
+                e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
+                const float4* rp = rec + kRec * (int64_t)e;
+                sA[threadIdx.x] = rp[0];
+                sB[threadIdx.x] = rp[1];
+                sC[threadIdx.x] = rp[2].x;
+            }
+            __syncthreads();
+            const int nb = min(kBlendThreads, end - base);
+            if (!done) {
+                for (int k = 0; k < nb; ++k) {
+                    float4 A = sA[k];
+                    float4 B = sB[k];
+                    float dx = fx - A.x, dy = fy - A.y;
+                    float q = A.z * dx * dx + 2.0f * A.w * dx * dy + B.x * dy * dy;
+                    float al = fminf(0.99f, B.y * __expf(-0.5f * q));
+                    if (al < kMinAlpha) continue;
+                    float tn = T * (1.0f - al);
+                    if (tn < kTStop) {
+                        done = true;
+                        break;
+                    }
+                    float w = al * T;
+                    c0 += B.z * w;
+                    c1 += B.w * w;
+                    c2 += sC[k] * w;
+                    T = tn;
+                    ++nc;
                 }
-                float w = al * T;
-                c0 += B.z * w;
-                c1 += B.w * w;
-                c2 += sC[k] * w;
-                T = tn;
-                ++nc;
             }
         }
+        if (inside) {
+            const int64_t p = (int64_t)py * s.W + px, np = (int64_t)s.W * s.H;
+            s.out_rgb[p] = c0;
+            s.out_rgb[np + p] = c1;
+            s.out_rgb[2 * np + p] = c2;
+            if (s.out_T) s.out_T[p] = T;
+            if (s.out_nc) s.out_nc[p] = nc;
+        }
+        __syncthreads();  // LDS batches and s_tile are free again
+        if (threadIdx.x == 0) s_tile = nxt;
+        __syncthreads();
+        gt = s_tile;
     }
-    if (inside) {
-        const int64_t p = (int64_t)py * s.W + px, np = (int64_t)s.W * s.H;
-        s.out_rgb[p] = c0;
-        s.out_rgb[np + p] = c1;
-        s.out_rgb[2 * np + p] = c2;
-        if (s.out_T) s.out_T[p] = T;
-        if (s.out_nc) s.out_nc[p] = nc;
+}
+
+// Resident blend blocks that fill the device (a multiple of 8, one share per
+// XCD), capped by the tile count rounded up to 8.
+unsigned blend_grid(int total_tiles) {
+    static int resident[64] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int& g = resident[dev & 63];
+    if (g == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_blend, kBlendThreads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 8;
+        g = ((per_cu * cus + 7) / 8) * 8;
     }
+    const int want = ((total_tiles + 7) / 8) * 8;
+    return (unsigned)(want < g ? (want > 8 ? want : 8) : g);
 }
 
 int bits_for(int64_t v) {
@@ -679,8 +730,8 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
     }
     r.order = nullptr;
     hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)tab.n), dim3(NT), 0, st, r.ranges, tab, rc);
-    hipLaunchKernelGGL(k_blend, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
-                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries);
+    hipLaunchKernelGGL(k_blend, dim3(blend_grid(tab.total_tiles)), dim3(kBlendThreads), 0, st, tab, r.ranges,
+                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, rc);
     return hipGetLastError();
 }
 

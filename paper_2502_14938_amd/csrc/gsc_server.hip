@@ -1,14 +1,437 @@
-// Multi-viewer serving loop.
+// Multi-viewer serving on one device: continuous batching of stereo frame
+// requests from several viewers (uneven resolutions, one device cache each)
+// over the shared scene of a context.
+//
+//   admit    a viewer is admitted when its cache, per-frame buffers and its
+//            share of the batch raster fit the device-memory budget
+//   submit   a frame request is queued on its viewer (cameras copied, the
+//            unified camera of eqs. 5-6 computed on the host)
+//   step     the oldest queued request of up to kMaxSeg/2 viewers (oldest
+//            first) form one batch: each viewer's derive stage (selection,
+//            cache schedule, derivation of misses, compose) on its own cache,
+//            then ONE raster batch over all (viewer, eye) images ending in
+//            one persistent blend launch; the host returns at once and the
+//            next step can be queued behind this one
+//   poll     completions, timestamped on the host monotonic clock by a host
+//            function the stream runs when the batch's kernels are done
+#include <algorithm>
+#include <cstring>
+#include <ctime>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
 #include "gsc_common.h"
 #include "gsc_ctx.h"
 
-extern "C" {
-int gsc_server_create(gsc_ctx*, int64_t, void*, gsc_server** out) { if (out) *out = nullptr; return GSC_E_INVALID_ARG; }
-void gsc_server_destroy(gsc_server*) {}
-int gsc_server_admit(gsc_server*, int32_t, int32_t) { return GSC_E_INVALID_ARG; }
-int64_t gsc_server_viewer_bytes(gsc_server*, int32_t, int32_t) { return 0; }
-int64_t gsc_server_submit(gsc_server*, int32_t, const gsc_camera*, const gsc_camera*, double, float*, float*) { return GSC_E_INVALID_ARG; }
-int gsc_server_step(gsc_server*) { return GSC_E_INVALID_ARG; }
-int gsc_server_poll(gsc_server*, int64_t*, double*, int32_t) { return 0; }
-int gsc_server_leave(gsc_server*, int32_t) { return GSC_E_INVALID_ARG; }
+using namespace gsc;
+
+namespace {
+
+constexpr int kMaxBatchViewers = kMaxSeg / 2;
+constexpr int64_t kPairCapPerViewer = (int64_t)1 << 27;
+
+double now_monotonic() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
+
+struct Request {
+    int64_t id;
+    gsc_camera eye[2];
+    gsc_camera unified;
+    double t_arrival;
+    float* out[2];
+};
+
+struct Viewer {
+    int32_t max_w = 0, max_h = 0;
+    View v;
+    AllocSet mem;
+    int64_t entries = 0, pairs = 0, tiles = 0;  // share of the batch raster
+    size_t bytes = 0;                           // view + raster share (upper bound)
+    std::deque<Request> queue;
+};
+
+// Counters a finished batch reports to the host (pinned, one per batch).
+struct BatchReport {
+    RasterCounters rc;
+    Counters vc[kMaxBatchViewers];
+};
+
+struct Batch;
+
+}  // namespace
+
+struct gsc_server {
+    gsc_ctx* ctx = nullptr;
+    hipStream_t st = nullptr;
+    int64_t budget = 0;
+    size_t used = 0;
+    std::vector<std::unique_ptr<Viewer>> viewers;
+    AllocSet rmem;
+    Raster raster;
+    int64_t r_entries = 0, r_pairs = 0, r_tiles = 0;
+    int64_t next_id = 0;
+    std::string err;
+    std::mutex mu;  // guards the fields below (host functions run on a runtime thread)
+    struct Done {
+        int64_t id;
+        double t;
+        int32_t status;
+    };
+    std::vector<Done> done;
+    std::vector<BatchReport*> free_reports;
+    std::vector<BatchReport*> all_reports;
+    int64_t in_flight = 0;
+};
+
+namespace {
+
+struct Batch {
+    gsc_server* s;
+    BatchReport* rep;
+    int nviewers;
+    std::vector<int64_t> ids;
+    std::vector<int> viewer_of;  // batch-local viewer index of each request
+};
+
+int sfail(gsc_server* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+void on_batch_done(void* p) {
+    Batch* b = (Batch*)p;
+    const double t = now_monotonic();
+    gsc_server* s = b->s;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const bool pairs_over = (b->rep->rc.overflow & 3) != 0;
+        for (size_t i = 0; i < b->ids.size(); ++i) {
+            const bool cache_over = (b->rep->vc[b->viewer_of[i]].overflow & 2) != 0;
+            s->done.push_back({b->ids[i], t, (pairs_over || cache_over) ? GSC_E_CAPACITY : GSC_OK});
+        }
+        s->free_reports.push_back(b->rep);
+        s->in_flight -= 1;
+    }
+    delete b;
+}
+
+int64_t viewer_cache_lines(const gsc_ctx* c) {
+    const int64_t n = c->scene.n;
+    int64_t C = c->cfg.cache_capacity > 0 ? c->cfg.cache_capacity : n;
+    if (!(c->cfg.flags & GSC_FLAG_REUSE) && C < n) C = n;  // no-cache schedule: line i = visible i
+    return C;
+}
+
+void viewer_share(const gsc_ctx* c, int32_t W, int32_t H, int64_t& entries, int64_t& pairs, int64_t& tiles) {
+    const int64_t C = viewer_cache_lines(c);
+    entries = 2 * C * c->scene.k;
+    const int64_t ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
+    tiles = 2 * ntx * nty;
+    if (c->cfg.max_pairs > 0) {
+        pairs = c->cfg.max_pairs;
+    } else {
+        pairs = std::max<int64_t>((int64_t)1 << 22, (int64_t)16 * 2 * W * H);
+        pairs = std::min(pairs, std::min<int64_t>(24 * entries, kPairCapPerViewer));
+    }
+}
+
+size_t viewer_bytes_of(const gsc_ctx* c, int32_t W, int32_t H) {
+    int64_t e, p, t;
+    viewer_share(c, W, H, e, p, t);
+    return view_bytes(c->scene.n, viewer_cache_lines(c), c->scene.k) + sizeof(Counters) +
+           raster_bytes(e, p, t, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
+}
+
+// Size the batch raster for the admitted viewers (stream must be idle).
+hipError_t resize_raster(gsc_server* s) {
+    int64_t e = 0, p = 0, t = 0;
+    for (auto& v : s->viewers)
+        if (v) {
+            e += v->entries;
+            p += v->pairs;
+            t += v->tiles;
+        }
+    e = std::min<int64_t>(e, ((int64_t)1 << 31) - 1);
+    p = std::min<int64_t>(p, ((int64_t)1 << 31) - 1);
+    if (e == s->r_entries && p == s->r_pairs && t == s->r_tiles) return hipSuccess;
+    s->rmem.release();
+    s->raster = Raster();
+    s->r_entries = s->r_pairs = s->r_tiles = 0;
+    if (e == 0) return hipSuccess;
+    hipError_t err = alloc_raster(s->rmem, s->raster, e, p, t, (s->ctx->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
+    if (err != hipSuccess) {
+        s->rmem.release();
+        s->raster = Raster();
+        return err;
+    }
+    s->r_entries = e;
+    s->r_pairs = p;
+    s->r_tiles = t;
+    return hipSuccess;
+}
+
+Viewer* viewer_at(gsc_server* s, int32_t id) {
+    if (id < 0 || id >= (int32_t)s->viewers.size()) return nullptr;
+    return s->viewers[id].get();
+}
+
+}  // namespace
+
+extern "C" {
+
+int gsc_server_create(gsc_ctx* ctx, int64_t budget_bytes, void* stream, gsc_server** out) {
+    if (!out) return GSC_E_INVALID_ARG;
+    *out = nullptr;
+    if (!ctx || budget_bytes <= 0) return GSC_E_INVALID_ARG;
+    if (!ctx->loaded) return GSC_E_NOT_LOADED;
+    if (ctx->nviews != 1) return GSC_E_INVALID_ARG;  // needs binocular de-redundancy (one view per viewer)
+    if ((ctx->cfg.flags & GSC_FLAG_PREDICTOR) && !ctx->pred_loaded) return GSC_E_NOT_LOADED;
+    gsc_server* s = new (std::nothrow) gsc_server();
+    if (!s) return GSC_E_OOM;
+    s->ctx = ctx;
+    s->st = (hipStream_t)stream;
+    s->budget = budget_bytes;
+    *out = s;
+    return GSC_OK;
+}
+
+void gsc_server_destroy(gsc_server* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->st);
+    // completion host functions may still be returning on the runtime's thread
+    for (int spin = 0; spin < 100000; ++spin) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->in_flight == 0) break;
+        }
+        timespec ts{0, 100000};
+        nanosleep(&ts, nullptr);
+    }
+    for (auto& v : s->viewers)
+        if (v) v->mem.release();
+    s->rmem.release();
+    for (BatchReport* r : s->all_reports) (void)hipHostFree(r);
+    delete s;
+}
+
+const char* gsc_server_last_error(const gsc_server* s) { return s ? s->err.c_str() : "null server"; }
+
+int64_t gsc_server_viewer_bytes(gsc_server* s, int32_t max_width, int32_t max_height) {
+    if (!s || max_width < 1 || max_height < 1 || max_width > 16384 || max_height > 16384) return GSC_E_INVALID_ARG;
+    return (int64_t)viewer_bytes_of(s->ctx, max_width, max_height);
+}
+
+int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height) {
+    if (!s) return GSC_E_INVALID_ARG;
+    if (max_width < 1 || max_height < 1 || max_width > 16384 || max_height > 16384)
+        return sfail(s, GSC_E_INVALID_ARG, "gsc_server_admit: image size out of range");
+    const size_t bytes = viewer_bytes_of(s->ctx, max_width, max_height);
+    if (s->used + bytes > (size_t)s->budget)
+        return sfail(s, GSC_E_BUDGET, "gsc_server_admit: viewer does not fit the device-memory budget now");
+    int32_t id = -1;
+    for (size_t i = 0; i < s->viewers.size(); ++i)
+        if (!s->viewers[i]) {
+            id = (int32_t)i;
+            break;
+        }
+    if (id < 0) {
+        id = (int32_t)s->viewers.size();
+        s->viewers.emplace_back();
+    }
+    std::unique_ptr<Viewer> v(new (std::nothrow) Viewer());
+    if (!v) return sfail(s, GSC_E_OOM, "gsc_server_admit: out of host memory");
+    v->max_w = max_width;
+    v->max_h = max_height;
+    v->bytes = bytes;
+    viewer_share(s->ctx, max_width, max_height, v->entries, v->pairs, v->tiles);
+    const gsc_ctx* c = s->ctx;
+    if (hipStreamSynchronize(s->st) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_admit: stream failed");
+    if (alloc_view(v->mem, v->v, c->scene.n, viewer_cache_lines(c), c->scene.k) != hipSuccess) {
+        v->mem.release();
+        return sfail(s, GSC_E_OOM, "gsc_server_admit: device allocation");
+    }
+    if (reset_view(v->v, c->scene.n, c->cfg.d_max, s->st) != hipSuccess) {
+        v->mem.release();
+        return sfail(s, GSC_E_HIP, "gsc_server_admit: cache reset failed");
+    }
+    s->viewers[id] = std::move(v);
+    if (resize_raster(s) != hipSuccess) {
+        s->viewers[id]->mem.release();
+        s->viewers[id].reset();
+        (void)resize_raster(s);
+        return sfail(s, GSC_E_OOM, "gsc_server_admit: raster allocation");
+    }
+    s->used += bytes;
+    return id;
+}
+
+int64_t gsc_server_submit(gsc_server* s, int32_t viewer, const gsc_camera* left, const gsc_camera* right,
+                          double t_arrival, float* out_left, float* out_right) {
+    if (!s) return GSC_E_INVALID_ARG;
+    Viewer* v = viewer_at(s, viewer);
+    if (!v) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_submit: no such viewer");
+    if (!left || !right || !out_left || !out_right) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_submit: null argument");
+    if (!valid_camera(*left) || !valid_camera(*right))
+        return sfail(s, GSC_E_INVALID_ARG, "gsc_server_submit: invalid camera");
+    if (left->width != right->width || left->height != right->height || left->fovx != right->fovx ||
+        left->fovy != right->fovy || left->znear != right->znear)
+        return sfail(s, GSC_E_INVALID_ARG, "gsc_server_submit: eyes must share intrinsics");
+    if (left->width > v->max_w || left->height > v->max_h)
+        return sfail(s, GSC_E_INVALID_ARG, "gsc_server_submit: image larger than the viewer's admitted size");
+    Request r;
+    r.id = s->next_id++;
+    r.eye[0] = *left;
+    r.eye[1] = *right;
+    unified_camera(*left, *right, r.unified);
+    r.t_arrival = t_arrival;
+    r.out[0] = out_left;
+    r.out[1] = out_right;
+    v->queue.push_back(r);
+    return r.id;
+}
+
+int gsc_server_step(gsc_server* s) {
+    if (!s) return GSC_E_INVALID_ARG;
+    gsc_ctx* c = s->ctx;
+    // oldest head request first, one request per viewer per batch
+    std::vector<int32_t> pick;
+    for (int32_t i = 0; i < (int32_t)s->viewers.size(); ++i)
+        if (s->viewers[i] && !s->viewers[i]->queue.empty()) pick.push_back(i);
+    if (pick.empty()) return 0;
+    std::stable_sort(pick.begin(), pick.end(), [&](int32_t a, int32_t b) {
+        return s->viewers[a]->queue.front().t_arrival < s->viewers[b]->queue.front().t_arrival;
+    });
+    if ((int)pick.size() > kMaxBatchViewers) pick.resize(kMaxBatchViewers);
+
+    BatchReport* rep = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->free_reports.empty()) {
+            rep = s->free_reports.back();
+            s->free_reports.pop_back();
+        }
+    }
+    if (!rep) {
+        if (hipHostMalloc((void**)&rep, sizeof(BatchReport)) != hipSuccess)
+            return sfail(s, GSC_E_OOM, "gsc_server_step: pinned allocation");
+        s->all_reports.push_back(rep);
+    }
+    Batch* b = new (std::nothrow) Batch();
+    if (!b) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->free_reports.push_back(rep);
+        return sfail(s, GSC_E_OOM, "gsc_server_step: out of host memory");
+    }
+    b->s = s;
+    b->rep = rep;
+    b->nviewers = (int)pick.size();
+
+    SegTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    int tiles = 0;
+    for (int i = 0; i < (int)pick.size(); ++i) {
+        Viewer& v = *s->viewers[pick[i]];
+        Request r = v.queue.front();
+        v.queue.pop_front();
+        DeriveArgs a;
+        a.sc = &c->scene;
+        a.v = &v.v;
+        a.cam = derive_cam(r.unified, c->scene.d_ref);
+        a.precision = c->cfg.precision;
+        a.flags = c->cfg.flags;
+        a.d_max = c->cfg.d_max;
+        a.guide = c->cfg.guide;
+        a.pred_thr = c->cfg.predictor_threshold;
+        a.pred_w = c->pred_w;
+        a.pred_wbf = c->pred_wbf;
+        a.collect = 0;
+        hipError_t e = derive_frame(a, s->st);
+        if (e != hipSuccess) {
+            delete b;
+            return sfail(s, GSC_E_HIP, std::string("gsc_server_step: derive: ") + hipGetErrorString(e));
+        }
+        v.v.t += 1;
+        for (int eye = 0; eye < 2; ++eye) {
+            Seg& sg = tab.s[tab.n++];
+            sg.L0 = v.v.L0; sg.L1 = v.v.L1; sg.L2 = v.v.L2; sg.L3 = v.v.L3;
+            sg.G = v.v.G; sg.nG = &v.v.cnt->n_gauss; sg.nG_host = 0;
+            seg_camera(sg, r.eye[eye]);
+            sg.tile_base = tiles;
+            tiles += sg.ntx * sg.nty;
+            sg.out_rgb = r.out[eye];
+            sg.out_T = nullptr;
+            sg.out_nc = nullptr;
+        }
+        b->ids.push_back(r.id);
+        b->viewer_of.push_back(i);
+        if (hipMemcpyAsync(&rep->vc[i], v.v.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s->st) != hipSuccess) {
+            delete b;
+            return sfail(s, GSC_E_HIP, "gsc_server_step: counter copy");
+        }
+    }
+    tab.total_tiles = tiles;
+    hipError_t e = raster_batch(tab, s->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, s->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&rep->rc, s->raster.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost, s->st);
+    if (e != hipSuccess) {
+        delete b;
+        return sfail(s, GSC_E_HIP, std::string("gsc_server_step: raster: ") + hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->in_flight += 1;
+    }
+    const int launched = (int)b->ids.size();
+    e = hipLaunchHostFunc(s->st, on_batch_done, b);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->in_flight -= 1;
+        delete b;
+        return sfail(s, GSC_E_HIP, "gsc_server_step: completion callback");
+    }
+    return launched;
+}
+
+int gsc_server_poll(gsc_server* s, int64_t* ids, double* t_done, int32_t* status, int32_t cap) {
+    if (!s || cap < 0 || (cap > 0 && (!ids || !t_done))) return GSC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int32_t m = (int32_t)std::min<size_t>((size_t)cap, s->done.size());
+    for (int32_t i = 0; i < m; ++i) {
+        ids[i] = s->done[i].id;
+        t_done[i] = s->done[i].t;
+        if (status) status[i] = s->done[i].status;
+    }
+    s->done.erase(s->done.begin(), s->done.begin() + m);
+    return m;
+}
+
+int gsc_server_pending(gsc_server* s) {
+    if (!s) return GSC_E_INVALID_ARG;
+    int64_t q = 0;
+    for (auto& v : s->viewers)
+        if (v) q += (int64_t)v->queue.size();
+    std::lock_guard<std::mutex> lk(s->mu);
+    return (int)std::min<int64_t>(q + s->in_flight, 1 << 30);
+}
+
+int gsc_server_leave(gsc_server* s, int32_t viewer) {
+    if (!s) return GSC_E_INVALID_ARG;
+    Viewer* v = viewer_at(s, viewer);
+    if (!v) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_leave: no such viewer");
+    if (!v->queue.empty()) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_leave: viewer has queued requests");
+    if (hipStreamSynchronize(s->st) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_leave: stream failed");
+    s->used -= v->bytes;
+    v->mem.release();
+    s->viewers[viewer].reset();
+    if (resize_raster(s) != hipSuccess) return sfail(s, GSC_E_OOM, "gsc_server_leave: raster allocation");
+    return GSC_OK;
+}
+
+}  // extern "C"
