@@ -210,6 +210,33 @@ int gsc_reset_cache(gsc_ctx* ctx);
  * host_dst and writes the full count to *n. */
 int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap, int64_t* n);
 
+/* ---------------- stage timing -------------------------------------------
+ * With timing on, every frame (gsc_derive + gsc_render_stereo) records HIP
+ * events on the context's stream at its stage boundaries; gsc_timing_read
+ * synchronises and returns the summed device milliseconds per stage over the
+ * frames issued since timing was switched on or last read.  Stages: */
+#define GSC_STAGE_SCHEDULE 0    /* unified-camera selection, cache schedule */
+#define GSC_STAGE_DERIVE 1      /* MLP derivation of the misses (MFMA) */
+#define GSC_STAGE_COMPOSE 2     /* depth update, render buffer */
+#define GSC_STAGE_PREPROCESS 3  /* projection, conic, extent, tile counts (both eyes) */
+#define GSC_STAGE_DEPTH_SORT 4  /* per-Gaussian depth radix pass */
+#define GSC_STAGE_PAIR_SCAN 5   /* pair offsets in depth order */
+#define GSC_STAGE_DUP_SMALL 6   /* pair emission, small footprints */
+#define GSC_STAGE_DUP_BIG 7     /* pair emission, large footprints */
+#define GSC_STAGE_TILE_SORT 8   /* tile-id radix passes over the pairs */
+#define GSC_STAGE_RANGES 9      /* per-tile ranges */
+#define GSC_STAGE_BLEND 10      /* persistent blend */
+#define GSC_NUM_STAGES 11
+/* Switch timing on (enable != 0) or off; clears what was recorded.  Waits
+ * for the stream. */
+int gsc_timing(gsc_ctx* ctx, int enable);
+/* ms_out host [n] (n <= GSC_NUM_STAGES): summed ms per stage; frame_ms host
+ * [frame_cap] (may be NULL when frame_cap is 0): each recorded frame's device
+ * time from the start of its derive stage to the end of its blend (-1 when
+ * the frame did not run both); *frames = frames recorded.  The events skip
+ * the system-scope fence (no cache writeback per mark).  Clears the record. */
+int gsc_timing_read(gsc_ctx* ctx, double* ms_out, int32_t n, double* frame_ms, int64_t frame_cap, int64_t* frames);
+
 /* ---------------- learned reuse predictor (Linear 6-64-64-1, sigmoid) ----
  * North-star extension of the reuse decision of Section 4 (Alg. 1): for a
  * visible anchor whose cache line is still valid, a small MLP reads six

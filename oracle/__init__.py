@@ -48,6 +48,7 @@ def _load():
             _b.build()
         lib = C.CDLL(_LIB_PATH)
         P = C.c_void_p
+        lib.orc_threads.restype = C.c_int
         lib.orc_unified_camera.argtypes = [P, P, P]
         lib.orc_select.argtypes = [C.c_int64, P, P, P, P, C.c_double, P, P]
         lib.orc_select.restype = C.c_int64
@@ -92,6 +93,11 @@ def to_orc(cam: dict) -> OrcCamera:
 def from_orc(c: OrcCamera) -> dict:
     return {"R": np.array(c.R[:], np.float64).reshape(3, 3), "pos": np.array(c.pos[:], np.float64),
             "fovx": c.fovx, "fovy": c.fovy, "width": c.width, "height": c.height, "znear": c.znear}
+
+
+def threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(_load().orc_threads())
 
 
 def round_bf16(x: float) -> float:
@@ -433,19 +439,6 @@ def reuse_label(cached: dict, fresh: dict, k: int, size_px) -> np.ndarray:
     drift = np.maximum(np.abs(a_c - a_f), am * np.maximum(dc, 0.5 * geo)).max(1)
     area = np.maximum(1.0, np.asarray(size_px, np.float64) ** 2)
     return (drift * area > 16.0 / 255.0).astype(np.uint8)
-
-
-def pred_init(seed: int = 3, width: int = 64):
-    """Predictor weights Linear(6,64)-ReLU-Linear(64,64)-ReLU-Linear(64,1):
-    Glorot-uniform weights, zero biases, PCG64(seed) in layer order."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    dims = [(width, PRED_FEATURES), (width, width), (1, width)]
-    params = []
-    for o, i in dims:
-        lim = math.sqrt(6.0 / (o + i))
-        params.append(rng.uniform(-lim, lim, size=(o, i)))
-        params.append(np.zeros(o))
-    return params
 
 
 def pred_forward(params, X):

@@ -30,6 +30,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_TILE 16
 
@@ -516,4 +519,13 @@ void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end,
             n_contrib[p] = nc;
             pix_band[p] = bnd;
         }
+}
+
+/* Threads the parallel loops above run on (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -104,6 +104,8 @@ SYMBOLS = {
     "gsc_server_step": ([C.c_void_p], C.c_int),
     "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "gsc_server_pending": ([C.c_void_p], C.c_int),
+    "gsc_timing": ([C.c_void_p, C.c_int], C.c_int),
+    "gsc_timing_read": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gsc_server_last_error": ([C.c_void_p], C.c_char_p),
     "gsc_server_leave": ([C.c_void_p, C.c_int32], C.c_int),
 }
@@ -144,6 +146,10 @@ def _ptr(t):
 def _current_stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+STAGES = ("schedule", "derive", "compose", "preprocess", "depth_sort", "pair_scan", "dup_small", "dup_big",
+          "tile_sort", "ranges", "blend")
 
 
 class Renderer:
@@ -261,6 +267,20 @@ class Renderer:
         return out
 
     # ---------------------------------------------------------- predictor
+    def timing(self, enable=True):
+        """Record device time per stage of every frame from now on (or stop)."""
+        self._check(lib().gsc_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self, max_frames=4096):
+        """(summed device ms per stage, per-frame device ms, frames recorded)
+        since timing was switched on or last read."""
+        ms = np.zeros(len(STAGES), np.float64)
+        fr = np.zeros(max_frames, np.float64)
+        n = C.c_int64()
+        self._check(lib().gsc_timing_read(self.h, ms.ctypes.data, len(STAGES), fr.ctypes.data, max_frames,
+                                          C.byref(n)))
+        return dict(zip(STAGES, ms.tolist())), fr[:min(n.value, max_frames)], n.value
+
     def predictor_load(self, params: np.ndarray):
         p = np.ascontiguousarray(params, np.float32)
         assert p.size == PRED_NPARAMS

@@ -271,6 +271,29 @@ hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles
     return hipGetLastError();
 }
 
+// Event set of the frame being issued (nullptr when timing is off).
+Marks* frame_marks(gsc_ctx* c) {
+    if (!c->timing) return nullptr;
+    if (c->marks_used == c->marks.size()) {
+        Marks m{};
+        for (int i = 0; i <= kNumStages; ++i)
+            // timing-only events: no system-scope fence (no cache writeback per mark)
+            if (hipEventCreateWithFlags(&m.ev[i], hipEventDisableSystemFence) != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipEventDestroy(m.ev[j]);
+                return nullptr;
+            }
+        c->marks.push_back(m);
+    }
+    return &c->marks[c->marks_used];
+}
+
+void free_marks(gsc_ctx* c) {
+    for (Marks& m : c->marks)
+        for (int i = 0; i <= kNumStages; ++i) (void)hipEventDestroy(m.ev[i]);
+    c->marks.clear();
+    c->marks_used = 0;
+}
+
 }  // namespace gsc
 
 // ====================================================================== ABI
@@ -305,6 +328,8 @@ int gsc_create(const gsc_config* cfg, void* stream, gsc_ctx** out) {
 
 void gsc_destroy(gsc_ctx* c) {
     if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    gsc::free_marks(c);
     gsc::pred_free(c);
     gsc::free_explicit(c);
     gsc::free_all(c);
@@ -463,7 +488,7 @@ int gsc_derive(gsc_ctx* c) {
         a.pred_w = c->pred_w;
         a.pred_wbf = c->pred_wbf;
         a.collect = c->collect_features;
-        hipError_t e = derive_frame(a, c->stream);
+        hipError_t e = derive_frame(a, c->stream, vi == 0 ? frame_marks(c) : nullptr);
         if (e != hipSuccess) return hip_fail(c, e, "gsc_derive");
         c->view[vi].t += 1;
     }
@@ -494,8 +519,10 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
         s.out_nc = nullptr;
     }
     tab.total_tiles = tiles;
-    hipError_t e = raster_batch(tab, c->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->stream);
+    Marks* mk = frame_marks(c);
+    hipError_t e = raster_batch(tab, c->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->stream, mk);
     if (e != hipSuccess) return hip_fail(c, e, "gsc_render_stereo");
+    if (mk) c->marks_used += 1;
     c->last_tab = tab;
     c->rendered = true;
     c->explicit_render = false;
@@ -569,6 +596,41 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->overflow = (r.overflow & 1) | (k.overflow & 2);
     size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;
+    return GSC_OK;
+}
+
+int gsc_timing(gsc_ctx* c, int enable) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_timing: null context");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->timing = enable != 0;
+    c->marks_used = 0;
+    for (Marks& m : c->marks) m.recorded = 0;
+    return GSC_OK;
+}
+
+int gsc_timing_read(gsc_ctx* c, double* ms, int32_t n, double* frame_ms, int64_t frame_cap, int64_t* frames) {
+    if (!c || !ms || n < 0 || frame_cap < 0 || (frame_cap > 0 && !frame_ms))
+        return fail(c, GSC_E_INVALID_ARG, "gsc_timing_read: bad argument");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    for (int32_t i = 0; i < n; ++i) ms[i] = 0.0;
+    for (size_t f = 0; f < c->marks_used; ++f) {
+        Marks& m = c->marks[f];
+        for (int i = 0; i < kNumStages && i < n; ++i) {
+            const uint32_t need = (1u << i) | (1u << (i + 1));
+            if ((m.recorded & need) != need) continue;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, m.ev[i], m.ev[i + 1]) == hipSuccess) ms[i] += t;
+        }
+        if ((int64_t)f < frame_cap) {
+            const uint32_t ends = 1u | (1u << kNumStages);
+            float t = -1.f;
+            if ((m.recorded & ends) == ends) (void)hipEventElapsedTime(&t, m.ev[0], m.ev[kNumStages]);
+            frame_ms[f] = t;
+        }
+        m.recorded = 0;
+    }
+    if (frames) *frames = (int64_t)c->marks_used;
+    c->marks_used = 0;
     return GSC_OK;
 }
 

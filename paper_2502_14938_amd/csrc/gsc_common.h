@@ -51,7 +51,6 @@ struct RasterCounters {
     int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
     int32_t overflow;             // bit0: pair capacity
     int32_t n_big;                // entries in the large-footprint list
-    int32_t blend_next[8];        // persistent blend: next tile of each XCD's share
     int32_t pad;
 };
 
@@ -202,10 +201,21 @@ struct DeriveArgs {
     const uint16_t* pred_wbf; // bf16 copy for inference
     int collect;              // store reuse-candidate features for label collection
 };
-hipError_t derive_frame(const DeriveArgs& a, hipStream_t st);
+// Optional stage timing: HIP events recorded on the stream at the stage
+// boundaries of one frame (GSC_STAGE_* order of the public header).
+constexpr int kNumStages = 11;
+struct Marks {
+    hipEvent_t ev[kNumStages + 1];
+    uint32_t recorded;  // bit i: ev[i] recorded this frame
+};
+inline void mark(Marks* m, int i, hipStream_t st) {
+    if (m && hipEventRecord(m->ev[i], st) == hipSuccess) m->recorded |= 1u << i;
+}
+
+hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr);
 
 // Raster stage of a batch of segments.
-hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st);
+hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st, Marks* mk = nullptr);
 
 // Fill a segment's camera fields from a public camera.
 void seg_camera(Seg& s, const gsc_camera& c);

@@ -100,6 +100,10 @@ struct gsc_ctx {
     int32_t* lab_iota = nullptr;
     uint8_t* lab_y = nullptr;
     int64_t lab_entries = 0;      // anchors * k the label scratch holds
+    // stage timing (gsc_timing): one event set per frame since the last read
+    bool timing = false;
+    std::vector<gsc::Marks> marks;
+    size_t marks_used = 0;
 };
 
 namespace gsc {
@@ -107,4 +111,6 @@ hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles
 void free_explicit(gsc_ctx* c);
 void free_labels(gsc_ctx* c);
 void pred_free(gsc_ctx* c);
+Marks* frame_marks(gsc_ctx* c);
+void free_marks(gsc_ctx* c);
 }  // namespace gsc

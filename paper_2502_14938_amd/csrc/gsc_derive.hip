@@ -11,6 +11,7 @@
 
 #include "gsc_common.h"
 #include "gsc_derive_mfma.h"
+#include "gsc_pred_bf16.h"
 
 namespace gsc {
 
@@ -86,40 +87,6 @@ __device__ __forceinline__ void reuse_features(float4 p, int lvl, int lmax, cons
     f[5] = log2f(smax * fx / dn);
 }
 
-__device__ __forceinline__ float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
-}
-__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-// p(stale) with BF16 weights and activations, FP32 accumulation.
-__device__ float pred_prob_bf16(const uint16_t* __restrict__ wb, const float* __restrict__ w32, const float* f) {
-    // layout: W1[64*6] b1[64] W2[64*64] b2[64] W3[64] b3[1]
-    const int oW1 = 0, ob1 = 64 * 6, oW2 = ob1 + 64, ob2 = oW2 + 64 * 64, oW3 = ob2 + 64, ob3 = oW3 + 64;
-    float x[kPredIn];
-#pragma unroll
-    for (int i = 0; i < kPredIn; ++i) x[i] = bf16_round(f[i]);
-    float h1[kPredW];
-#pragma unroll
-    for (int r = 0; r < kPredW; ++r) {
-        float acc = 0.f;
-#pragma unroll
-        for (int c = 0; c < kPredIn; ++c) acc = fmaf(bf16_to_f(wb[oW1 + r * kPredIn + c]), x[c], acc);
-        acc += w32[ob1 + r];
-        h1[r] = bf16_round(fmaxf(acc, 0.f));
-    }
-    float logit = w32[ob3];
-    for (int r = 0; r < kPredW; ++r) {
-        float acc = 0.f;
-#pragma unroll
-        for (int c = 0; c < kPredW; ++c) acc = fmaf(bf16_to_f(wb[oW2 + r * kPredW + c]), h1[c], acc);
-        acc += w32[ob2 + r];
-        float h2 = bf16_round(fmaxf(acc, 0.f));
-        logit = fmaf(bf16_to_f(wb[oW3 + r]), h2, logit);
-    }
-    return 1.0f / (1.0f + expf(-logit));
-}
 
 struct LookupArgs {
     const int32_t* visible;
@@ -287,6 +254,29 @@ __global__ __launch_bounds__(NT) void k_assign(const int32_t* __restrict__ misse
     }
 }
 
+// Direct-mapped lines, used when there is a line for every anchor: anchor a
+// owns line a.  Free lines can then never run short, so there is no free
+// list and no eviction, and the hit/miss decisions are the same as with any
+// other choice of free line.  Misses (re)take their line at frame t; every
+// visible anchor's buffer position points at its own line.
+__global__ __launch_bounds__(NT) void k_direct_assign(const int32_t* __restrict__ misses,
+                                                      const int32_t* __restrict__ visible, int32_t* __restrict__ slot_of,
+                                                      int32_t* __restrict__ line_anchor, int32_t* __restrict__ line_tau,
+                                                      int32_t* __restrict__ line_last, int32_t* __restrict__ vslot,
+                                                      int32_t t, Counters* cnt) {
+    const int32_t nm = cnt->n_miss, nv = cnt->n_visible;
+    for (int64_t j = gtid(); j < nm; j += gstride()) {
+        const int32_t aid = visible[misses[j]];
+        if (slot_of[aid] < 0) {
+            slot_of[aid] = aid;
+            line_anchor[aid] = aid;
+            line_last[aid] = t;
+        }
+        line_tau[aid] = t;
+    }
+    for (int64_t i = gtid(); i < nv; i += gstride()) vslot[i] = visible[i];
+}
+
 __global__ __launch_bounds__(NT) void k_vslot(const int32_t* __restrict__ visible, const int32_t* __restrict__ slot_of,
                                               int32_t* __restrict__ vslot, Counters* cnt) {
     int32_t nv = cnt->n_visible;
@@ -387,12 +377,13 @@ inline dim3 grid_for(int64_t n) {
         if (e_ != hipSuccess) return e_;        \
     } while (0)
 
-hipError_t derive_frame(const DeriveArgs& a, hipStream_t st) {
+hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     const Scene& sc = *a.sc;
     View& v = *a.v;
     const int64_t n = sc.n;
     const int32_t t = (int32_t)v.t;
     Counters* cnt = v.cnt;
+    mark(mk, 0, st);
     hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(1), 0, st, cnt);
     hipLaunchKernelGGL(k_store_pu, dim3(1), dim3(64), 0, st, v.pu_hist, t, a.cam);
     // anchor indexing and filtering -> X_t ascending
@@ -419,37 +410,43 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st) {
         GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_miss, v.block_sums, st));
         hipLaunchKernelGGL(k_compact_ids, grid_for(n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, 0, &cnt->n_visible,
                            v.misses);
-        // misses that need a line, and their ranks
-        uint32_t* need = v.tmp_a;
-        uint32_t* need_rank = v.tmp_b;
-        hipLaunchKernelGGL(k_need_flags, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, cnt, need);
-        GSC_TRY(scan_u32(need, need_rank, &cnt->n_miss, 0, &cnt->n_need, v.block_sums, st));
-        // free lines, ascending
-        uint32_t* fflag = reinterpret_cast<uint32_t*>(v.tmp_c);
-        uint32_t* fpos = reinterpret_cast<uint32_t*>(v.tmp_d);
-        hipLaunchKernelGGL(k_free_flags, grid_for(C), dim3(NT), 0, st, v.line_anchor, C, fflag);
-        GSC_TRY(scan_u32(fflag, fpos, nullptr, C, &cnt->n_free, v.block_sums, st));
-        hipLaunchKernelGGL(k_compact_ids, grid_for(C), dim3(NT), 0, st, fflag, fpos, C, nullptr, v.free_list);
-        // eviction of outdated lines when free lines are short
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, v.evict_hist, 64);
-        hipLaunchKernelGGL(k_evict_hist, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_last, C, t, a.d_max,
-                           cnt, v.evict_hist);
-        hipLaunchKernelGGL(k_evict_plan, dim3(1), dim3(1), 0, st, v.evict_hist, t, a.d_max, cnt, v.evict_scan_n, n);
-        hipLaunchKernelGGL(k_evict_thr_flags, grid_for(n), dim3(NT), 0, st, v.slot_of, v.line_last, v.evict_scan_n,
-                           cnt, fflag);
-        GSC_TRY(scan_u32(fflag, fpos, v.evict_scan_n, 0, nullptr, v.block_sums, st));
-        hipLaunchKernelGGL(k_evict_apply, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_last, v.slot_of, fpos,
-                           C, t, cnt);
-        // free list again if anything was evicted (count 0 otherwise)
-        hipLaunchKernelGGL(k_evict_freescan_n, dim3(1), dim3(1), 0, st, cnt, v.evict_scan_n, C);
-        hipLaunchKernelGGL(k_free_flags_n, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.evict_scan_n, fflag);
-        GSC_TRY(scan_u32(fflag, fpos, v.evict_scan_n, 0, nullptr, v.block_sums, st));
-        hipLaunchKernelGGL(k_compact_ids, grid_for(C), dim3(NT), 0, st, fflag, fpos, 0, v.evict_scan_n, v.free_list);
-        hipLaunchKernelGGL(k_assign, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, v.line_anchor,
-                           v.line_tau, v.line_last, need, need_rank, v.free_list, t, C, cnt);
-        hipLaunchKernelGGL(k_vslot, grid_for(n), dim3(NT), 0, st, v.visible, v.slot_of, v.vslot, cnt);
+        if (C >= n) {
+            hipLaunchKernelGGL(k_direct_assign, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of,
+                               v.line_anchor, v.line_tau, v.line_last, v.vslot, t, cnt);
+        } else {
+            // misses that need a line, and their ranks
+            uint32_t* need = v.tmp_a;
+            uint32_t* need_rank = v.tmp_b;
+            hipLaunchKernelGGL(k_need_flags, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, cnt, need);
+            GSC_TRY(scan_u32(need, need_rank, &cnt->n_miss, 0, &cnt->n_need, v.block_sums, st));
+            // free lines, ascending
+            uint32_t* fflag = reinterpret_cast<uint32_t*>(v.tmp_c);
+            uint32_t* fpos = reinterpret_cast<uint32_t*>(v.tmp_d);
+            hipLaunchKernelGGL(k_free_flags, grid_for(C), dim3(NT), 0, st, v.line_anchor, C, fflag);
+            GSC_TRY(scan_u32(fflag, fpos, nullptr, C, &cnt->n_free, v.block_sums, st));
+            hipLaunchKernelGGL(k_compact_ids, grid_for(C), dim3(NT), 0, st, fflag, fpos, C, nullptr, v.free_list);
+            // eviction of outdated lines when free lines are short
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, v.evict_hist, 64);
+            hipLaunchKernelGGL(k_evict_hist, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_last, C, t, a.d_max,
+                               cnt, v.evict_hist);
+            hipLaunchKernelGGL(k_evict_plan, dim3(1), dim3(1), 0, st, v.evict_hist, t, a.d_max, cnt, v.evict_scan_n, n);
+            hipLaunchKernelGGL(k_evict_thr_flags, grid_for(n), dim3(NT), 0, st, v.slot_of, v.line_last, v.evict_scan_n,
+                               cnt, fflag);
+            GSC_TRY(scan_u32(fflag, fpos, v.evict_scan_n, 0, nullptr, v.block_sums, st));
+            hipLaunchKernelGGL(k_evict_apply, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_last, v.slot_of, fpos,
+                               C, t, cnt);
+            // free list again if anything was evicted (count 0 otherwise)
+            hipLaunchKernelGGL(k_evict_freescan_n, dim3(1), dim3(1), 0, st, cnt, v.evict_scan_n, C);
+            hipLaunchKernelGGL(k_free_flags_n, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.evict_scan_n, fflag);
+            GSC_TRY(scan_u32(fflag, fpos, v.evict_scan_n, 0, nullptr, v.block_sums, st));
+            hipLaunchKernelGGL(k_compact_ids, grid_for(C), dim3(NT), 0, st, fflag, fpos, 0, v.evict_scan_n, v.free_list);
+            hipLaunchKernelGGL(k_assign, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, v.line_anchor,
+                               v.line_tau, v.line_last, need, need_rank, v.free_list, t, C, cnt);
+            hipLaunchKernelGGL(k_vslot, grid_for(n), dim3(NT), 0, st, v.visible, v.slot_of, v.vslot, cnt);
+        }
     }
     // decode the misses on the matrix cores
+    mark(mk, 1, st);
     {
         MfmaDeriveArgs m;
         m.posr = sc.posr; m.feat = sc.feat; m.scale = sc.scale; m.offsets = sc.offsets; m.k = sc.k;
@@ -462,11 +459,13 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st) {
         m.fr.n_at = sc.n_at; m.fr.n_ct = sc.n_ct; m.fr.n_vt = sc.n_vt;
         GSC_TRY(derive_mfma(m, n, st));
     }
+    mark(mk, 2, st);
     hipLaunchKernelGGL(k_depth_update, dim3(1), dim3(1), 0, st, cnt, a.d_max, a.guide);
     // compose the render buffer
     hipLaunchKernelGGL(k_compose_count, grid_for(n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_a);
     GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_gauss, v.block_sums, st));
     hipLaunchKernelGGL(k_compose_write, grid_for(n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_b, v.G);
+    mark(mk, 3, st);
     return hipGetLastError();
 }
 

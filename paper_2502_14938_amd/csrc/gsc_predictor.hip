@@ -24,6 +24,7 @@
 #include "gsc_common.h"
 #include "gsc_ctx.h"
 #include "gsc_derive_mfma.h"
+#include "gsc_pred_bf16.h"
 
 namespace gsc {
 
@@ -163,35 +164,14 @@ __global__ __launch_bounds__(NT) void k_pred_to_bf16(const float* __restrict__ w
     if (p < P) wbf[p] = to_bf16(w[p]);
 }
 
-__device__ __forceinline__ float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
-}
-__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 __global__ __launch_bounds__(NT) void k_pred_infer(const uint16_t* __restrict__ wb, const float* __restrict__ w32,
                                                    const float* __restrict__ X, int64_t n, float* __restrict__ out) {
     for (int64_t r = gtid(); r < n; r += gstride()) {
         float x[kPredIn];
 #pragma unroll
-        for (int i = 0; i < kPredIn; ++i) x[i] = bf16_round(X[r * kPredIn + i]);
-        float h1[kPredW];
-#pragma unroll
-        for (int j = 0; j < kPredW; ++j) {
-            float a = 0.f;
-#pragma unroll
-            for (int i = 0; i < kPredIn; ++i) a = fmaf(bf16_val(wb[oW1 + j * kPredIn + i]), x[i], a);
-            h1[j] = bf16_round(fmaxf(a + w32[ob1 + j], 0.f));
-        }
-        float logit = w32[ob3];
-        for (int j = 0; j < kPredW; ++j) {
-            float a = 0.f;
-#pragma unroll
-            for (int i = 0; i < kPredW; ++i) a = fmaf(bf16_val(wb[oW2 + j * kPredW + i]), h1[i], a);
-            logit = fmaf(bf16_val(wb[oW3 + j]), bf16_round(fmaxf(a + w32[ob2 + j], 0.f)), logit);
-        }
-        out[r] = 1.0f / (1.0f + expf(-logit));
+        for (int i = 0; i < kPredIn; ++i) x[i] = X[r * kPredIn + i];
+        out[r] = pred_prob_bf16(wb, w32, x);
     }
 }
 

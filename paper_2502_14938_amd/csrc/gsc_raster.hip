@@ -11,11 +11,10 @@
 //                      emitted in depth order (LDS-staged, coalesced)
 //   tile radix pass    stable sort of pairs by global tile id (the high bits)
 //   k_ranges           [start, end) of every tile's run
-//   k_blend            front-to-back compositing, persistent: a grid that
-//                      fills the chip takes tiles from per-XCD queues (each
-//                      XCD's contiguous share of the batch's tiles first,
-//                      then the others'), 16x16 pixels per block,
-//                      LDS-staged Gaussian batches, block-wide early exit
+//   k_blend            front-to-back compositing, one launch over every
+//                      (segment, tile) of the batch, one block per 16x16
+//                      tile (XCD-aware tile order), LDS-staged Gaussian
+//                      batches, block-wide early exit
 // With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
 // key and are sorted after duplication instead; the order is the same.
 #include <cmath>
@@ -57,7 +56,6 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
     rc->entry_base[tab.n] = acc;
     rc->overflow = 0;
     rc->n_big = 0;
-    for (int x = 0; x < 8; ++x) rc->blend_next[x] = 0;
     if (acc > max_entries) {
         rc->overflow |= 2;
         acc = (int32_t)max_entries;
@@ -542,119 +540,72 @@ __global__ __launch_bounds__(NT) void k_seg_pairs(const int32_t* __restrict__ ra
 // Gaussians shared by neighbouring tiles are gathered through one L2.
 // Gaussians are staged in LDS 256 at a time; the block stops as soon as
 // every pixel has reached the transmittance floor.
-// Next tile for a block on XCD `xcd`: its own XCD's contiguous share of the
-// batch's tiles first, then the other XCDs' shares.  `qi` counts the queues
-// found empty (kept by the calling thread).  -1 when all are drained.
-__device__ __forceinline__ int next_tile(int32_t* q, int xcd, int q8, int r8, int& qi) {
-    while (qi < 8) {
-        const int x = (xcd + qi) & 7;
-        const int len = q8 + (x < r8 ? 1 : 0);
-        const int j = atomicAdd(&q[x], 1);
-        if (j < len) return x * q8 + min(x, r8) + j;
-        ++qi;
-    }
-    return -1;
-}
-
 __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int32_t* __restrict__ ranges,
                                                           const uint32_t* __restrict__ vals,
-                                                          const float4* __restrict__ rec, uint32_t max_entries,
-                                                          RasterCounters* rc) {
+                                                          const float4* __restrict__ rec, uint32_t max_entries) {
     __shared__ float4 sA[kBlendThreads];
     __shared__ float4 sB[kBlendThreads];
     __shared__ float sC[kBlendThreads];
-    __shared__ int s_tile;
     const int total = tab.total_tiles;
     const int q8 = total >> 3, r8 = total & 7;
-    const int xcd = blockIdx.x & 7;  // workgroups are dealt to the 8 XCDs round-robin
-    int qi = 0;
-    if (threadIdx.x == 0) s_tile = next_tile(rc->blend_next, xcd, q8, r8, qi);
-    __syncthreads();
-    int gt = s_tile;
-    while (gt >= 0) {
-        // claim the following tile now; it is only read after this one
-        int nxt = -1;
-        if (threadIdx.x == 0) nxt = next_tile(rc->blend_next, xcd, q8, r8, qi);
-        int si = 0;
-        while (si + 1 < tab.n && gt >= tab.s[si + 1].tile_base) ++si;
-        const Seg& s = tab.s[si];
-        const int lt = gt - s.tile_base;
-        const int tx = lt % s.ntx, ty = lt / s.ntx;
-        const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-        const int py = ty * kTile + (threadIdx.x / kTile);
-        const bool inside = px < s.W && py < s.H;
-        const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-        const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-        float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-        int32_t nc = 0;
-        bool done = !inside;
-        for (int32_t base = start; base < end; base += kBlendThreads) {
-            if (__syncthreads_count(done) == kBlendThreads) break;
-            int32_t i = base + (int32_t)threadIdx.x;
-            if (i < end) {
-                uint32_t e = vals[i];
-                e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
-                const float4* rp = rec + kRec * (int64_t)e;
-                sA[threadIdx.x] = rp[0];
-                sB[threadIdx.x] = rp[1];
-                sC[threadIdx.x] = rp[2].x;
-            }
-            __syncthreads();
-            const int nb = min(kBlendThreads, end - base);
-            if (!done) {
-                for (int k = 0; k < nb; ++k) {
-                    float4 A = sA[k];
-                    float4 B = sB[k];
-                    float dx = fx - A.x, dy = fy - A.y;
-                    float q = A.z * dx * dx + 2.0f * A.w * dx * dy + B.x * dy * dy;
-                    float al = fminf(0.99f, B.y * __expf(-0.5f * q));
-                    if (al < kMinAlpha) continue;
-                    float tn = T * (1.0f - al);
-                    if (tn < kTStop) {
-                        done = true;
-                        break;
-                    }
-                    float w = al * T;
-                    c0 += B.z * w;
-                    c1 += B.w * w;
-                    c2 += sC[k] * w;
-                    T = tn;
-                    ++nc;
-                }
-            }
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int gt = xcd * q8 + min(xcd, r8) + j;
+    int si = 0;
+    while (si + 1 < tab.n && gt >= tab.s[si + 1].tile_base) ++si;
+    const Seg& s = tab.s[si];
+    const int lt = gt - s.tile_base;
+    const int tx = lt % s.ntx, ty = lt / s.ntx;
+    const int px = tx * kTile + (threadIdx.x & (kTile - 1));
+    const int py = ty * kTile + (threadIdx.x / kTile);
+    const bool inside = px < s.W && py < s.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    int32_t nc = 0;
+    bool done = !inside;
+    for (int32_t base = start; base < end; base += kBlendThreads) {
+        if (__syncthreads_count(done) == kBlendThreads) break;
+        int32_t i = base + (int32_t)threadIdx.x;
+        if (i < end) {
+            uint32_t e = vals[i];
+            e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
+            const float4* rp = rec + kRec * (int64_t)e;
+            sA[threadIdx.x] = rp[0];
+            sB[threadIdx.x] = rp[1];
+            sC[threadIdx.x] = rp[2].x;
         }
-        if (inside) {
-            const int64_t p = (int64_t)py * s.W + px, np = (int64_t)s.W * s.H;
-            s.out_rgb[p] = c0;
-            s.out_rgb[np + p] = c1;
-            s.out_rgb[2 * np + p] = c2;
-            if (s.out_T) s.out_T[p] = T;
-            if (s.out_nc) s.out_nc[p] = nc;
-        }
-        __syncthreads();  // LDS batches and s_tile are free again
-        if (threadIdx.x == 0) s_tile = nxt;
         __syncthreads();
-        gt = s_tile;
+        const int nb = min(kBlendThreads, end - base);
+        if (!done) {
+            for (int k = 0; k < nb; ++k) {
+                float4 A = sA[k];
+                float4 B = sB[k];
+                float dx = fx - A.x, dy = fy - A.y;
+                float q = A.z * dx * dx + 2.0f * A.w * dx * dy + B.x * dy * dy;
+                float al = fminf(0.99f, B.y * __expf(-0.5f * q));
+                if (al < kMinAlpha) continue;
+                float tn = T * (1.0f - al);
+                if (tn < kTStop) {
+                    done = true;
+                    break;
+                }
+                float w = al * T;
+                c0 += B.z * w;
+                c1 += B.w * w;
+                c2 += sC[k] * w;
+                T = tn;
+                ++nc;
+            }
+        }
     }
-}
-
-// Resident blend blocks that fill the device (a multiple of 8, one share per
-// XCD), capped by the tile count rounded up to 8.
-unsigned blend_grid(int total_tiles) {
-    static int resident[64] = {};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    int& g = resident[dev & 63];
-    if (g == 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_blend, kBlendThreads, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 8;
-        g = ((per_cu * cus + 7) / 8) * 8;
+    if (inside) {
+        const int64_t p = (int64_t)py * s.W + px, np = (int64_t)s.W * s.H;
+        s.out_rgb[p] = c0;
+        s.out_rgb[np + p] = c1;
+        s.out_rgb[2 * np + p] = c2;
+        if (s.out_T) s.out_T[p] = T;
+        if (s.out_nc) s.out_nc[p] = nc;
     }
-    const int want = ((total_tiles + 7) / 8) * 8;
-    return (unsigned)(want < g ? (want > 8 ? want : 8) : g);
 }
 
 int bits_for(int64_t v) {
@@ -682,12 +633,14 @@ void seg_camera(Seg& s, const gsc_camera& c) {
     s.nty = (c.height + kTile - 1) / kTile;
 }
 
-hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st) {
+hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st, Marks* mk) {
     RasterCounters* rc = r.cnt;
+    mark(mk, 3, st);
     hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
     PreArgs pa;
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
     hipLaunchKernelGGL(k_preprocess, grid_for(r.max_entries), dim3(NT), 0, st, pa);
+    mark(mk, 4, st);
     const int tile_bits = bits_for(tab.total_tiles);
     DupArgs da;
     da.tab = tab; da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
@@ -697,32 +650,42 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         int which = 0;
         e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st);
         if (e != hipSuccess) return e;
+        mark(mk, 5, st);
         hipLaunchKernelGGL(k_gather_counts, grid_for(r.max_entries / 4 + 1), dim3(NT), 0, st, r.dval[which], r.ntiles,
                            rc, r.scnt);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
+        mark(mk, 6, st);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
         hipLaunchKernelGGL(k_dup_small<false>, grid_for(r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        mark(mk, 7, st);
         hipLaunchKernelGGL(k_dup_big<false>, dim3(kGridBlocks), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        mark(mk, 8, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
         e = radix_sort_u32(r.pkey, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
+        mark(mk, 9, st);
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_fill_ranges, grid_for(2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
         hipLaunchKernelGGL(k_ranges<uint32_t>, grid_for(r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
                            r.ranges, (uint32_t)tab.total_tiles);
     } else {
+        mark(mk, 5, st);  // no per-Gaussian depth pass in this mode
         e = scan_u32(r.ntiles, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
+        mark(mk, 6, st);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
         hipLaunchKernelGGL(k_dup_small<true>, grid_for(r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        mark(mk, 7, st);
         hipLaunchKernelGGL(k_dup_big<true>, dim3(kGridBlocks), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        mark(mk, 8, st);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
+        mark(mk, 9, st);
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_fill_ranges, grid_for(2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
         hipLaunchKernelGGL(k_ranges<uint64_t>, grid_for(r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
@@ -730,8 +693,10 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
     }
     r.order = nullptr;
     hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)tab.n), dim3(NT), 0, st, r.ranges, tab, rc);
-    hipLaunchKernelGGL(k_blend, dim3(blend_grid(tab.total_tiles)), dim3(kBlendThreads), 0, st, tab, r.ranges,
-                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, rc);
+    mark(mk, 10, st);
+    hipLaunchKernelGGL(k_blend, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
+                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries);
+    mark(mk, 11, st);
     return hipGetLastError();
 }
 

@@ -302,6 +302,19 @@ def serving_workload(viewers: int = 8, frames: int = 600, rate_hz: float = 72.0,
     return out
 
 
+def predictor_init(seed: int = 3, width: int = 64, n_in: int = 6):
+    """Initial reuse-predictor weights Linear(n_in,64)-ReLU-Linear(64,64)-
+    ReLU-Linear(64,1) (rows = outputs): Glorot-uniform weights, zero biases,
+    drawn from PCG64(seed) in layer order (W1, W2, W3)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = []
+    for o, i in ((width, n_in), (width, width), (1, width)):
+        lim = math.sqrt(6.0 / (o + i))
+        params.append(rng.uniform(-lim, lim, size=(o, i)))
+        params.append(np.zeros(o))
+    return params
+
+
 def random_gaussians(n: int, seed: int = 0, box: float = 4.0, zc: float = 0.0, s_lo=0.05, s_hi=0.6):
     """Explicit anisotropic Gaussians (raster-only inputs): means in a box,
     a random symmetric positive-definite covariance, rgb in (0,1), opacity in

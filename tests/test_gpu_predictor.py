@@ -32,7 +32,7 @@ def gs():
 
 def rnd_params(seed=3):
     rng = np.random.default_rng(seed)
-    p = oracle.pred_init(seed=seed)
+    p = synth.predictor_init(seed=seed)
     for i in (1, 3, 5):
         p[i] = rng.uniform(-0.2, 0.2, p[i].shape)
     return p
@@ -70,7 +70,7 @@ def test_bf16_inference_close_to_fp64(gs):
 
 def test_training_lowers_loss(gs):
     r = gs.Renderer(k=10, max_width=64, max_height=64)
-    r.predictor_load(gs.pack_params(oracle.pred_init(seed=3)))
+    r.predictor_load(gs.pack_params(synth.predictor_init(seed=3)))
     rng = np.random.default_rng(4)
     X = rng.standard_normal((4096, 6)).astype(np.float32)
     y = (X[:, 0] + 0.5 * X[:, 1] > 0.2).astype(np.uint8)
@@ -184,7 +184,7 @@ def test_learned_reuse_gain(gs, tiny):
     assert 0.05 < y.mean() < 0.95, y.mean()
     pw = float((y == 0).sum()) / max(1, int((y == 1).sum()))
     trainer = gs.Renderer(k=tiny.k, max_width=64, max_height=64)
-    trainer.predictor_load(gs.pack_params(oracle.pred_init(seed=3)))
+    trainer.predictor_load(gs.pack_params(synth.predictor_init(seed=3)))
     losses = trainer.predictor_train(X, y, batch=1024, epochs=20, lr=1e-3, pos_weight=pw, seed=11)
     assert losses[-1] < losses[0]
     params = trainer.predictor_get()

@@ -13,7 +13,7 @@ import synth
 
 def test_gradients_match_finite_differences():
     rng = np.random.default_rng(0)
-    params = oracle.pred_init(seed=3)
+    params = synth.predictor_init(seed=3)
     for i in range(1, 6, 2):
         params[i] = rng.uniform(-0.1, 0.1, params[i].shape)  # non-zero biases
     X = rng.standard_normal((64, oracle.PRED_FEATURES))
