@@ -32,8 +32,16 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
-MFMA_BF16_PEAK_TFS = 2500.0  # dense
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+MFMA_BF16_PEAK_TFS = 2500.0   # dense
+# FP32 vector ALU without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz.  (157.3 TFLOP/s counts packed FP32, which is not used.)
+VALU_FP32_PEAK_TFS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Blend work per (pixel, Gaussian) visit, from its definition: offset (2),
+# conic quadratic (9), exponent scale, exp, opacity product, clamp and the
+# 1/255 test (5) = 16 flops; a composited visit adds 1 - alpha, the new
+# transmittance, the stop test, the weight and 3 colour FMAs (10).
+BLEND_FLOP_VISIT, BLEND_FLOP_CONTRIB = 16, 10
 WORKLOAD = ("synthetic city, 1M anchors (32-dim features, k=10, octree LOD 0-10), 300-frame fly-through "
             "rising 2->300 m, stereo 2048x1080 per eye, IPD 64 mm")
 FORMS = {
@@ -71,6 +79,34 @@ def parse():
 
 
 # --------------------------------------------------------------------------- helpers
+
+class _Roctx:
+    """ROCTx ranges around the timed passes (recorded by rocprofv3
+    --marker-trace, so kernel statistics can be restricted to them); no-op
+    when the library is absent."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "/opt/rocm/lib/librocprofiler-sdk-roctx.so.1"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                break
+            except OSError:
+                continue
+
+    def push(self, name):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
+
+
+ROCTX = _Roctx()
+
 
 def psnr_dev(torch, a, b):
     mse = torch.mean((a - b) ** 2).item()
@@ -128,7 +164,7 @@ def make_renderer(gs, scene, form, W, H, args, params=None):
     return r
 
 
-def timed_pass(torch, r, traj, steps, warmup, W, H):
+def timed_pass(torch, r, traj, steps, warmup, W, H, tag="timed"):
     """Warm up, reset the cache, then time `steps` frames along the
     trajectory (frame i % len).  Returns (wall seconds, per-frame device ms,
     summed stage ms, frames) - device times from the library's own events."""
@@ -142,12 +178,14 @@ def timed_pass(torch, r, traj, steps, warmup, W, H):
     r.reset_cache()
     r.timing(True)
     torch.cuda.synchronize()
+    ROCTX.push(tag)
     t0 = time.perf_counter()
     for i in range(steps):
         L, R = traj[i % n]
         r.frame(L, R, oL, oR)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ROCTX.pop()
     stages, lat, frames = r.timing_read(max_frames=steps)
     r.timing(False)
     r.sync()  # raises if a capacity was exceeded
@@ -175,7 +213,8 @@ def stage_bytes(counts, W, H, frames):
     """Algorithmic bytes (and MFMA flops) per stage kernel summed over the
     timed frames (frame i uses the counters of trajectory frame i % len)."""
     n = len(counts)
-    tot = {"derive": 0.0, "derive_flop": 0.0, "preprocess": 0.0, "duplicate": 0.0, "blend": 0.0}
+    tot = {"derive": 0.0, "derive_flop": 0.0, "preprocess": 0.0, "duplicate": 0.0, "blend": 0.0,
+           "blend_flop": 0.0}
     for i in range(frames):
         c = counts[i % n]
         g, m = float(c["n_gauss"]), float(c["n_miss"])
@@ -185,6 +224,8 @@ def stage_bytes(counts, W, H, frames):
         tot["preprocess"] += 2 * g * (4 + 52 + 76)          # index + entry in; record, count, depth key out
         tot["duplicate"] += 2 * g * 44 + pairs * 8          # per-Gaussian binning inputs; (tile, id) pairs out
         tot["blend"] += pairs * 40 + 2 * W * H * 12         # pair id + 36 B record per pair; RGB out
+        tot["blend_flop"] += (BLEND_FLOP_VISIT * float(sum(c["n_eval"])) +
+                              BLEND_FLOP_CONTRIB * float(sum(c["n_contrib"])))
     return tot
 
 
@@ -242,13 +283,13 @@ def run_frames(args):
     form = args.form
     params = train_predictor(gs, torch, synth, scene, W, H, log) if FORMS[form].get("predictor") else None
     r = make_renderer(gs, scene, form, W, H, args, params)
-    total_s, lat, stages, frames = timed_pass(torch, r, traj, args.steps, args.warmup, W, H)
+    total_s, lat, stages, frames = timed_pass(torch, r, traj, args.steps, args.warmup, W, H, "timed:" + form)
     fps = args.steps / total_s
     plain = None
     plain_out = None
     if form != "plain" and not args.no_plain:
         plain = make_renderer(gs, scene, "plain", W, H, args)
-        p_s, p_lat, p_stages, _ = timed_pass(torch, plain, traj, args.steps, args.warmup, W, H)
+        p_s, p_lat, p_stages, _ = timed_pass(torch, plain, traj, args.steps, args.warmup, W, H, "timed:plain")
         plain_out = {"fps": round(args.steps / p_s, 2), "p50_ms": round(float(np.percentile(p_lat, 50)), 4),
                      "p99_ms": round(float(np.percentile(p_lat, 99)), 4)}
     quality = None
@@ -274,19 +315,36 @@ def run_frames(args):
 
     # roofline of the stage kernel with the largest total time
     tb = stage_bytes(counts, W, H, frames)
+    # the single kernel with the largest total time; the two emission kernels
+    # share their algorithmic bytes (reported together, as "duplicate")
+    kernels = {"derive": stages["derive"], "preprocess": stages["preprocess"], "blend": stages["blend"],
+               "dup_rows": stages["dup_rows"], "dup_big": stages["dup_big"]}
+    top = max(kernels, key=kernels.get)
     single = {"derive": stages["derive"], "preprocess": stages["preprocess"], "blend": stages["blend"],
-              "duplicate": stages["dup_small"] + stages["dup_big"]}
-    dom = max(single, key=single.get)
+              "duplicate": stages["dup_rows"] + stages["dup_big"]}
+    dom = "duplicate" if top.startswith("dup_") else top
     launches = frames * (2 if dom == "duplicate" else 1)
     ms = single[dom]
-    achieved = (tb[dom] / launches) / (ms / launches * 1e-3) / 1e9 if ms > 0 else 0.0
+    sec = ms * 1e-3
     traffic = traffic_for(dom, "city_flythrough_2k")
-    roofline = {"kernel": {"derive": "k_derive_mfma", "preprocess": "k_preprocess", "blend": "k_blend",
-                           "duplicate": "k_dup_small + k_dup_big"}[dom],
-                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "avg_launch_us": round(1e3 * ms / launches, 2),
-                "algorithmic_bytes_per_launch": round(tb[dom] / launches)}
+    names = {"derive": "k_derive_mfma", "preprocess": "k_preprocess", "blend": "k_blend",
+             "duplicate": "k_dup_rows + k_dup_big"}
+    if dom == "blend":
+        # per-pixel compositing is issue-bound on the vector ALU: ~16-26 flops
+        # per visit against ~40 B per tile pair shared by 256 pixels
+        achieved = tb["blend_flop"] / sec / 1e12 if sec > 0 else 0.0
+        roofline = {"kernel": names[dom], "bound": "alu", "achieved": round(achieved, 2),
+                    "peak": round(VALU_FP32_PEAK_TFS, 1), "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_FP32_PEAK_TFS, 4), "traffic": traffic,
+                    "avg_launch_us": round(1e3 * ms / launches, 2),
+                    "algorithmic_flop_per_launch": round(tb["blend_flop"] / launches),
+                    "algorithmic_bytes_per_launch": round(tb["blend"] / launches)}
+    else:
+        achieved = (tb[dom] / launches) / (sec / launches) / 1e9 if sec > 0 else 0.0
+        roofline = {"kernel": names[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "avg_launch_us": round(1e3 * ms / launches, 2),
+                    "algorithmic_bytes_per_launch": round(tb[dom] / launches)}
     others = {}
     for k in single:
         if single[k] > 0:
@@ -295,6 +353,8 @@ def run_frames(args):
                          "gbs": round(tb[k] / (single[k] * 1e-3) / 1e9, 1)}
     if single["derive"] > 0:
         others["derive"]["mfma_tflops"] = round(tb["derive_flop"] / (single["derive"] * 1e-3) / 1e12, 2)
+    if single["blend"] > 0:
+        others["blend"]["alu_tflops"] = round(tb["blend_flop"] / (single["blend"] * 1e-3) / 1e12, 2)
 
     mean = lambda key: float(np.mean([c[key] for c in counts])) if counts else 0.0  # noqa: E731
     out = {"metric": "binocular 2K frames/sec and p99 frame latency at PSNR>=40dB vs plain FP32",
@@ -313,6 +373,8 @@ def run_frames(args):
            "stage_ms_per_frame": {k: round(v / max(1, frames), 4) for k, v in stages.items()},
            "counts_mean": {"visible": round(mean("n_visible")), "misses": round(mean("n_miss")),
                            "gaussians": round(mean("n_gauss")),
+                           "blend_visits": round(float(np.mean([sum(c["n_eval"]) for c in counts])) if counts else 0),
+                           "blend_contrib": round(float(np.mean([sum(c["n_contrib"]) for c in counts])) if counts else 0),
                            "pairs_per_eye": round(float(np.mean([sum(c["n_pairs"]) / 2 for c in counts])) if counts else 0)},
            "roofline": roofline, "roofline_stages": others}
     out.update(log)

@@ -145,6 +145,10 @@ typedef struct gsc_frame_stats {
     int32_t overflow;       /* bit0 pair capacity, bit1 cache capacity */
     int32_t pad;
     int64_t device_bytes;   /* device memory owned by the context */
+    int64_t n_eval[2];      /* (pixel, Gaussian) visits of the blend per eye: per
+                               pixel, the Gaussians visited front to back until
+                               its transmittance ran out or its list ended */
+    int64_t n_contrib[2];   /* of those, the visits that were composited */
 } gsc_frame_stats;
 
 typedef struct gsc_ctx gsc_ctx;
@@ -221,8 +225,8 @@ int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap,
 #define GSC_STAGE_PREPROCESS 3  /* projection, conic, extent, tile counts (both eyes) */
 #define GSC_STAGE_DEPTH_SORT 4  /* per-Gaussian depth radix pass */
 #define GSC_STAGE_PAIR_SCAN 5   /* pair offsets in depth order */
-#define GSC_STAGE_DUP_SMALL 6   /* pair emission, small footprints */
-#define GSC_STAGE_DUP_BIG 7     /* pair emission, large footprints */
+#define GSC_STAGE_DUP_ROWS 6    /* pair emission, footprints of up to 4 tile rows */
+#define GSC_STAGE_DUP_BIG 7     /* pair emission, taller footprints */
 #define GSC_STAGE_TILE_SORT 8   /* tile-id radix passes over the pairs */
 #define GSC_STAGE_RANGES 9      /* per-tile ranges */
 #define GSC_STAGE_BLEND 10      /* persistent blend */

@@ -481,7 +481,8 @@ void orc_sort_pairs(int64_t n, const int32_t* tile, const int32_t* g, const doub
  * so their order is not fixed by float32 keys). */
 void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end, const int32_t* sorted_g,
                const double* mean2d, const double* conic, const double* alpha, const double* rgb,
-               const double* depth, double* out_rgb, double* out_T, int32_t* n_contrib, uint8_t* pix_band) {
+               const double* depth, double* out_rgb, double* out_T, int32_t* n_contrib, uint8_t* pix_band,
+               int32_t* n_eval) {
     int ntx = (W + ORC_TILE - 1) / ORC_TILE;
     int64_t npx = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -490,11 +491,12 @@ void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end,
             int tile = (v / ORC_TILE) * ntx + (u / ORC_TILE);
             double px = u + 0.5, py = v + 0.5;
             double T = 1.0, C[3] = {0.0, 0.0, 0.0};
-            int32_t nc = 0;
+            int32_t nc = 0, ne = 0;
             uint8_t bnd = 0;
             double prev_depth = -1.0;
             for (int64_t i = tile_start[tile]; i < tile_end[tile]; ++i) {
                 int32_t g = sorted_g[i];
+                ++ne; /* visited, whether it contributes, is skipped or ends the pixel */
                 double dx = px - mean2d[2 * g], dy = py - mean2d[2 * g + 1];
                 const double* cn = conic + 3 * g;
                 double q = cn[0] * dx * dx + 2.0 * cn[1] * dx * dy + cn[2] * dy * dy;
@@ -518,6 +520,7 @@ void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end,
             out_T[p] = T;
             n_contrib[p] = nc;
             pix_band[p] = bnd;
+            n_eval[p] = ne;
         }
 }
 

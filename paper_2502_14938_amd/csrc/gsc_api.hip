@@ -157,7 +157,8 @@ hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int6
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
     if (full_key) { A_(r.pkey64[0], max_pairs); A_(r.pkey64[1], max_pairs); }
-    A_(r.ranges, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks); A_(r.block_sums, kScanBlocks);
+    A_(r.ranges, 2 * max_tiles); A_(r.tile_eval, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks);
+    A_(r.block_sums, kScanBlocks);
     A_(r.n_sort, 1); A_(r.cnt, 1);
 #undef A_
     return hipSuccess;
@@ -596,6 +597,20 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->overflow = (r.overflow & 1) | (k.overflow & 2);
     size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;
+    if (c->rendered && !c->explicit_render && c->last_tab.total_tiles > 0) {
+        std::vector<int32_t> te(2 * (size_t)c->last_tab.total_tiles);
+        HIP_OR_FAIL(c, hipMemcpy(te.data(), c->raster.tile_eval, te.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int sg = 0; sg < c->last_tab.n && sg < 2; ++sg) {
+            const Seg& g = c->last_tab.s[sg];
+            int64_t ev = 0, co = 0;
+            for (int t = 0; t < g.ntx * g.nty; ++t) {
+                ev += te[2 * (size_t)(g.tile_base + t)];
+                co += te[2 * (size_t)(g.tile_base + t) + 1];
+            }
+            st->n_eval[sg] = ev;
+            st->n_contrib[sg] = co;
+        }
+    }
     return GSC_OK;
 }
 

@@ -13,7 +13,8 @@
 namespace gsc {
 
 constexpr int kTile = 16;             // 16x16 pixel tiles
-constexpr int kBlendThreads = 256;    // one thread per pixel of a tile
+constexpr int kBlendThreads = 128;    // two pixels of a 16x16 tile per thread (rows y, y + 8)
+constexpr int kBlendBatch = 256;      // Gaussians staged in LDS per step
 constexpr int kMaxSeg = 16;           // (viewer, eye) images per raster batch
 constexpr int kGridBlocks = 2048;     // fixed grid of the grid-stride kernels
 constexpr int kScanBlocks = 1024;     // blocks of the device-wide scan
@@ -153,6 +154,7 @@ struct Raster {
     uint32_t* dkey[2] = {nullptr, nullptr};  // depth keys (double buffer)
     uint32_t* dval[2] = {nullptr, nullptr};  // entry ids
     uint32_t* offs = nullptr;   // pair offset per depth rank
+    int32_t* tile_eval = nullptr;  // [max_tiles][2] blend visits and contributions of each tile
     uint32_t* pkey[2] = {nullptr, nullptr};  // global tile id
     uint32_t* pval[2] = {nullptr, nullptr};  // entry id
     uint64_t* pkey64[2] = {nullptr, nullptr};// full-key mode
@@ -216,6 +218,21 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr
 
 // Raster stage of a batch of segments.
 hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st, Marks* mk = nullptr);
+
+// Blocks of `threads` threads of `kernel` the whole device holds at once
+// (occupancy x compute units; cached per kernel and device).  Grid-stride
+// kernels launch at most this many, so that no block waits for a second
+// round while the rest of the chip idles.
+int resident_blocks(const void* kernel, int threads);
+
+// Grid of a grid-stride kernel over n items, one item per thread per step.
+template <typename K>
+inline dim3 grid_fit(K* kernel, int64_t n, int threads = 256) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    const int64_t cap = resident_blocks((const void*)kernel, threads);
+    return dim3((unsigned)(b < cap ? b : cap));
+}
 
 // Fill a segment's camera fields from a public camera.
 void seg_camera(Seg& s, const gsc_camera& c);

@@ -362,12 +362,6 @@ __global__ __launch_bounds__(NT) void k_compose_write(const int32_t* __restrict_
     }
 }
 
-inline dim3 grid_for(int64_t n) {
-    int64_t b = (n + NT - 1) / NT;
-    if (b < 1) b = 1;
-    if (b > kGridBlocks) b = kGridBlocks;
-    return dim3((unsigned)b);
-}
 
 }  // namespace
 
@@ -387,16 +381,16 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(1), 0, st, cnt);
     hipLaunchKernelGGL(k_store_pu, dim3(1), dim3(64), 0, st, v.pu_hist, t, a.cam);
     // anchor indexing and filtering -> X_t ascending
-    hipLaunchKernelGGL(k_select_flags, grid_for(n), dim3(NT), 0, st, sc.posr, sc.level, n, a.cam, v.tmp_a);
+    hipLaunchKernelGGL(k_select_flags, grid_fit(k_select_flags, n), dim3(NT), 0, st, sc.posr, sc.level, n, a.cam, v.tmp_a);
     GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, nullptr, n, &cnt->n_visible, v.block_sums, st));
-    hipLaunchKernelGGL(k_compact_ids, grid_for(n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, n, nullptr, v.visible);
+    hipLaunchKernelGGL(k_compact_ids, grid_fit(k_compact_ids, n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, n, nullptr, v.visible);
 
     const bool reuse = (a.flags & GSC_FLAG_REUSE) != 0;
     if (!reuse) {
-        hipLaunchKernelGGL(k_nocache, grid_for(n), dim3(NT), 0, st, v.misses, v.vslot, cnt);
+        hipLaunchKernelGGL(k_nocache, grid_fit(k_nocache, n), dim3(NT), 0, st, v.misses, v.vslot, cnt);
     } else {
         const int64_t C = v.C;
-        hipLaunchKernelGGL(k_cache_invalidate, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_tau, v.slot_of, C,
+        hipLaunchKernelGGL(k_cache_invalidate, grid_fit(k_cache_invalidate, C), dim3(NT), 0, st, v.line_anchor, v.line_tau, v.slot_of, C,
                            t, cnt);
         LookupArgs la;
         la.visible = v.visible; la.slot_of = v.slot_of; la.line_last = v.line_last; la.line_tau = v.line_tau;
@@ -405,44 +399,44 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
         la.thr = a.pred_thr; la.posr = sc.posr; la.level = sc.level; la.scale = sc.scale; la.pu_hist = v.pu_hist;
         la.lmax = sc.l_max; la.dmax = a.d_max; la.cam = a.cam; la.pred_wbf = a.pred_wbf; la.pred_w32 = a.pred_w;
         la.cand_feat = a.collect ? v.cand_feat : nullptr; la.cand_id = v.cand_id; la.cnt = cnt;
-        hipLaunchKernelGGL(k_cache_lookup, grid_for(n), dim3(NT), 0, st, la);
+        hipLaunchKernelGGL(k_cache_lookup, grid_fit(k_cache_lookup, n), dim3(NT), 0, st, la);
         // misses, ascending visible position (= ascending anchor id)
         GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_miss, v.block_sums, st));
-        hipLaunchKernelGGL(k_compact_ids, grid_for(n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, 0, &cnt->n_visible,
+        hipLaunchKernelGGL(k_compact_ids, grid_fit(k_compact_ids, n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, 0, &cnt->n_visible,
                            v.misses);
         if (C >= n) {
-            hipLaunchKernelGGL(k_direct_assign, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of,
+            hipLaunchKernelGGL(k_direct_assign, grid_fit(k_direct_assign, n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of,
                                v.line_anchor, v.line_tau, v.line_last, v.vslot, t, cnt);
         } else {
             // misses that need a line, and their ranks
             uint32_t* need = v.tmp_a;
             uint32_t* need_rank = v.tmp_b;
-            hipLaunchKernelGGL(k_need_flags, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, cnt, need);
+            hipLaunchKernelGGL(k_need_flags, grid_fit(k_need_flags, n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, cnt, need);
             GSC_TRY(scan_u32(need, need_rank, &cnt->n_miss, 0, &cnt->n_need, v.block_sums, st));
             // free lines, ascending
             uint32_t* fflag = reinterpret_cast<uint32_t*>(v.tmp_c);
             uint32_t* fpos = reinterpret_cast<uint32_t*>(v.tmp_d);
-            hipLaunchKernelGGL(k_free_flags, grid_for(C), dim3(NT), 0, st, v.line_anchor, C, fflag);
+            hipLaunchKernelGGL(k_free_flags, grid_fit(k_free_flags, C), dim3(NT), 0, st, v.line_anchor, C, fflag);
             GSC_TRY(scan_u32(fflag, fpos, nullptr, C, &cnt->n_free, v.block_sums, st));
-            hipLaunchKernelGGL(k_compact_ids, grid_for(C), dim3(NT), 0, st, fflag, fpos, C, nullptr, v.free_list);
+            hipLaunchKernelGGL(k_compact_ids, grid_fit(k_compact_ids, C), dim3(NT), 0, st, fflag, fpos, C, nullptr, v.free_list);
             // eviction of outdated lines when free lines are short
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, v.evict_hist, 64);
-            hipLaunchKernelGGL(k_evict_hist, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_last, C, t, a.d_max,
+            hipLaunchKernelGGL(k_evict_hist, grid_fit(k_evict_hist, C), dim3(NT), 0, st, v.line_anchor, v.line_last, C, t, a.d_max,
                                cnt, v.evict_hist);
             hipLaunchKernelGGL(k_evict_plan, dim3(1), dim3(1), 0, st, v.evict_hist, t, a.d_max, cnt, v.evict_scan_n, n);
-            hipLaunchKernelGGL(k_evict_thr_flags, grid_for(n), dim3(NT), 0, st, v.slot_of, v.line_last, v.evict_scan_n,
+            hipLaunchKernelGGL(k_evict_thr_flags, grid_fit(k_evict_thr_flags, n), dim3(NT), 0, st, v.slot_of, v.line_last, v.evict_scan_n,
                                cnt, fflag);
             GSC_TRY(scan_u32(fflag, fpos, v.evict_scan_n, 0, nullptr, v.block_sums, st));
-            hipLaunchKernelGGL(k_evict_apply, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.line_last, v.slot_of, fpos,
+            hipLaunchKernelGGL(k_evict_apply, grid_fit(k_evict_apply, C), dim3(NT), 0, st, v.line_anchor, v.line_last, v.slot_of, fpos,
                                C, t, cnt);
             // free list again if anything was evicted (count 0 otherwise)
             hipLaunchKernelGGL(k_evict_freescan_n, dim3(1), dim3(1), 0, st, cnt, v.evict_scan_n, C);
-            hipLaunchKernelGGL(k_free_flags_n, grid_for(C), dim3(NT), 0, st, v.line_anchor, v.evict_scan_n, fflag);
+            hipLaunchKernelGGL(k_free_flags_n, grid_fit(k_free_flags_n, C), dim3(NT), 0, st, v.line_anchor, v.evict_scan_n, fflag);
             GSC_TRY(scan_u32(fflag, fpos, v.evict_scan_n, 0, nullptr, v.block_sums, st));
-            hipLaunchKernelGGL(k_compact_ids, grid_for(C), dim3(NT), 0, st, fflag, fpos, 0, v.evict_scan_n, v.free_list);
-            hipLaunchKernelGGL(k_assign, grid_for(n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, v.line_anchor,
+            hipLaunchKernelGGL(k_compact_ids, grid_fit(k_compact_ids, C), dim3(NT), 0, st, fflag, fpos, 0, v.evict_scan_n, v.free_list);
+            hipLaunchKernelGGL(k_assign, grid_fit(k_assign, n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of, v.line_anchor,
                                v.line_tau, v.line_last, need, need_rank, v.free_list, t, C, cnt);
-            hipLaunchKernelGGL(k_vslot, grid_for(n), dim3(NT), 0, st, v.visible, v.slot_of, v.vslot, cnt);
+            hipLaunchKernelGGL(k_vslot, grid_fit(k_vslot, n), dim3(NT), 0, st, v.visible, v.slot_of, v.vslot, cnt);
         }
     }
     // decode the misses on the matrix cores
@@ -462,9 +456,9 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     mark(mk, 2, st);
     hipLaunchKernelGGL(k_depth_update, dim3(1), dim3(1), 0, st, cnt, a.d_max, a.guide);
     // compose the render buffer
-    hipLaunchKernelGGL(k_compose_count, grid_for(n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_a);
+    hipLaunchKernelGGL(k_compose_count, grid_fit(k_compose_count, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_a);
     GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_gauss, v.block_sums, st));
-    hipLaunchKernelGGL(k_compose_write, grid_for(n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_b, v.G);
+    hipLaunchKernelGGL(k_compose_write, grid_fit(k_compose_write, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_b, v.G);
     mark(mk, 3, st);
     return hipGetLastError();
 }

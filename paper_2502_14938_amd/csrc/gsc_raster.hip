@@ -32,12 +32,6 @@ constexpr float kTStop = 1e-4f;
 __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
-inline dim3 grid_for(int64_t n) {
-    int64_t b = (n + NT - 1) / NT;
-    if (b < 1) b = 1;
-    if (b > kGridBlocks) b = kGridBlocks;
-    return dim3((unsigned)b);
-}
 
 __device__ __forceinline__ int seg_of_entry(const RasterCounters* rc, int nseg, int64_t e) {
     int s = 0;
@@ -203,10 +197,9 @@ __device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
 }
 
 // Footprints taller than this many tile rows are counted by the whole wave
-// (lanes split the rows); entries with more pairs than kSmallPairs are
-// emitted by the whole wave (lanes split each row's tiles).
+// (lanes split the rows) and emitted one wave per entry; shorter ones keep
+// their row spans in the record and are emitted from them.
 constexpr int kSmallRows = 4;
-constexpr uint32_t kSmallPairs = 32;
 
 // Per-entry record, 4 x float4 (64 B, one cache line):
 //   A = (mean2d.x, mean2d.y, conic a, conic b)
@@ -368,12 +361,14 @@ struct DupArgs {
 // Pair emission.  Every entry owns the output range [offs[r], offs[r] +
 // count) (ranks in depth order; entry order with full keys), so entries can
 // be emitted in any order:
-//   k_dup_small  one thread per entry with at most kSmallPairs pairs in at
-//                most kSmallRows rows: tiles straight from the row spans the
-//                preprocess stored; other entries are appended to a list;
-//   k_dup_big    one wave per listed entry: row spans from the record (short
-//                footprints) or recomputed one row per lane (tall ones), and
-//                lanes stride along each row so the stores coalesce.
+//   k_dup_rows   entries of at most kSmallRows tile rows: the row spans the
+//                preprocess stored give each pair's tile; a wave writes its 64
+//                entries' pairs together, lane j taking pairs j, j + 64, ...
+//                of their concatenation (consecutive lanes, consecutive
+//                slots), so the stores coalesce; taller entries are appended
+//                to a list;
+//   k_dup_big    one wave per listed entry: row spans recomputed one row per
+//                lane, and lanes stride along each row so the stores coalesce.
 template <bool kFull>
 __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t, uint32_t e, uint64_t low) {
     if (q >= d.max_pairs) return;
@@ -383,12 +378,21 @@ __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t
 }
 
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_dup_small(DupArgs d, int32_t* __restrict__ big_list, int32_t* n_big) {
+__global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict__ big_list, int32_t* n_big) {
+    // per thread (entry): pairs before each row's end, first tile id of each row
+    __shared__ uint32_t s_cum[kSmallRows][NT];
+    __shared__ uint32_t s_first[kSmallRows][NT];
+    __shared__ uint32_t s_start[NT];  // exclusive prefix of the wave's pair counts
+    __shared__ uint32_t s_out[NT];    // output offset of the entry
+    __shared__ uint32_t s_e[NT];      // entry id
+    __shared__ uint32_t s_low[NT];    // depth bits (full-key mode)
     const int64_t ne = d.rc->n_entries;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
         const int64_t r = base + threadIdx.x;
         bool is_big = false;
+        uint32_t n_here = 0;
+        uint32_t cum[kSmallRows] = {0u, 0u, 0u, 0u}, first[kSmallRows] = {0u, 0u, 0u, 0u};
         if (r < ne) {
             const uint32_t e = kFull ? (uint32_t)r : d.order[r];
             const float4* rp = d.rec + kRec * (int64_t)e;
@@ -397,25 +401,36 @@ __global__ __launch_bounds__(NT) void k_dup_small(DupArgs d, int32_t* __restrict
             if (cnt) {
                 const uint32_t rows = __float_as_uint(C.y);
                 const int y0 = rows & 0xffff, y1 = rows >> 16;
-                if (cnt > kSmallPairs || y1 - y0 + 1 > kSmallRows) {
+                if (y1 - y0 + 1 > kSmallRows) {
                     is_big = true;
                 } else {
                     const float4 D = rp[3];
                     const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
                                                      __float_as_uint(D.w)};
-                    const Seg& s = d.tab.s[__float_as_uint(C.z)];
-                    const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
-                    int64_t q = d.offs[r];
+                    const Seg& sg = d.tab.s[__float_as_uint(C.z)];
+                    uint32_t acc = 0;
 #pragma unroll
                     for (int i = 0; i < kSmallRows; ++i) {
                         const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
-                        const uint32_t rowbase = (uint32_t)(s.tile_base + (y0 + i) * s.ntx);
-                        for (int xx = lo; xx <= hi; ++xx) put_pair<kFull>(d, q++, rowbase + (uint32_t)xx, e, low);
+                        acc += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+                        cum[i] = acc;
+                        first[i] = (uint32_t)(sg.tile_base + (y0 + i) * sg.ntx + lo);
                     }
+                    n_here = acc;  // equals cnt: the spans are what was counted
+                    s_out[threadIdx.x] = d.offs[r];
+                    s_e[threadIdx.x] = e;
+                    s_low[threadIdx.x] = kFull ? d.dkey[e] : 0u;
                 }
             }
         }
-        // wave-aggregated append of the large entries (their order is irrelevant)
+#pragma unroll
+        for (int i = 0; i < kSmallRows; ++i) {
+            s_cum[i][threadIdx.x] = cum[i];
+            s_first[i][threadIdx.x] = first[i];
+        }
+        uint32_t tot;
+        s_start[threadIdx.x] = wave_excl_scan(n_here, tot);
+        // wave-aggregated append of the tall entries (their order is irrelevant)
         const uint64_t m = __ballot(is_big);
         if (m) {
             int32_t at = 0;
@@ -424,6 +439,25 @@ __global__ __launch_bounds__(NT) void k_dup_small(DupArgs d, int32_t* __restrict
             at = __shfl(at, leader, 64);
             if (is_big) big_list[at + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)r;
         }
+        __syncthreads();
+        // the wave's pairs in rank order, lane j taking pairs j, j + 64, ...:
+        // consecutive lanes write consecutive slots of one entry's range
+        for (uint32_t j = lane; j < tot; j += 64) {
+            int lo = 0, hi = 63;  // last entry of the wave whose range starts at or before j
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_start[w0 + mid] <= j) lo = mid;
+                else hi = mid - 1;
+            }
+            const int t = w0 + lo;
+            const uint32_t k = j - s_start[t];
+            int row = 0;
+#pragma unroll
+            for (int i = 0; i < kSmallRows - 1; ++i) row += k >= s_cum[i][t] ? 1 : 0;
+            const uint32_t before = row ? s_cum[row - 1][t] : 0u;
+            put_pair<kFull>(d, (int64_t)s_out[t] + k, s_first[row][t] + (k - before), s_e[t], s_low[t]);
+        }
+        __syncthreads();  // LDS is rewritten by the next step
     }
 }
 
@@ -540,12 +574,29 @@ __global__ __launch_bounds__(NT) void k_seg_pairs(const int32_t* __restrict__ ra
 // Gaussians shared by neighbouring tiles are gathered through one L2.
 // Gaussians are staged in LDS 256 at a time; the block stops as soon as
 // every pixel has reached the transmittance floor.
+// One 16x16 tile per block of 128 threads; thread t owns the pixels
+// (t & 15, t >> 4) and (t & 15, (t >> 4) + 8) of the tile, which share their
+// column offset dx.  Gaussians of the tile's depth-sorted list are staged in
+// LDS, 256 at a time, with the conic pre-scaled so that the exponent is
+// base 2 and the log2 of the opacity folded in:
+//   alpha = min(0.99, 2^(a' dx^2 + b' dx dy + c' dy^2 + log2 o)),
+//   a' = -log2(e)/2 a, b' = -log2(e) b, c' = -log2(e)/2 c,
+// equal to min(0.99, o exp(-q/2)) of the conic quadratic q (the hardware
+// exp2 flushes results below 2^-126 to zero, far below the 1/255 cut-off).
+// Per pixel: skip
+// alpha < 1/255; stop before a Gaussian that would take T(1 - alpha) below
+// 1e-4; otherwise composite.  The composite step is predicated (no branches);
+// a wave leaves a batch early once all its pixels are done, the block once
+// every pixel is.
 __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int32_t* __restrict__ ranges,
                                                           const uint32_t* __restrict__ vals,
-                                                          const float4* __restrict__ rec, uint32_t max_entries) {
-    __shared__ float4 sA[kBlendThreads];
-    __shared__ float4 sB[kBlendThreads];
-    __shared__ float sC[kBlendThreads];
+                                                          const float4* __restrict__ rec, uint32_t max_entries,
+                                                          int32_t* __restrict__ tile_eval) {
+    __shared__ float4 sA[kBlendBatch];  // mx, my, a', b'
+    __shared__ float4 sB[kBlendBatch];  // c', log2 o, r, g
+    __shared__ float sC[kBlendBatch];   // b
+    __shared__ int32_t sEval[2 * (kBlendThreads / 64)];
+    constexpr float kL2e = 1.4426950408889634f;
     const int total = tab.total_tiles;
     const int q8 = total >> 3, r8 = total & 7;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
@@ -556,55 +607,100 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
     const int lt = gt - s.tile_base;
     const int tx = lt % s.ntx, ty = lt / s.ntx;
     const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-    const int py = ty * kTile + (threadIdx.x / kTile);
-    const bool inside = px < s.W && py < s.H;
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int py0 = ty * kTile + (threadIdx.x / kTile), py1 = py0 + kTile / 2;
+    const bool in0 = px < s.W && py0 < s.H, in1 = px < s.W && py1 < s.H;
+    const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f, fy1 = (float)py1 + 0.5f;
     const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    int32_t nc = 0;
-    bool done = !inside;
-    for (int32_t base = start; base < end; base += kBlendThreads) {
-        if (__syncthreads_count(done) == kBlendThreads) break;
-        int32_t i = base + (int32_t)threadIdx.x;
-        if (i < end) {
-            uint32_t e = vals[i];
-            e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
-            const float4* rp = rec + kRec * (int64_t)e;
-            sA[threadIdx.x] = rp[0];
-            sB[threadIdx.x] = rp[1];
-            sC[threadIdx.x] = rp[2].x;
-        }
-        __syncthreads();
-        const int nb = min(kBlendThreads, end - base);
-        if (!done) {
-            for (int k = 0; k < nb; ++k) {
-                float4 A = sA[k];
-                float4 B = sB[k];
-                float dx = fx - A.x, dy = fy - A.y;
-                float q = A.z * dx * dx + 2.0f * A.w * dx * dy + B.x * dy * dy;
-                float al = fminf(0.99f, B.y * __expf(-0.5f * q));
-                if (al < kMinAlpha) continue;
-                float tn = T * (1.0f - al);
-                if (tn < kTStop) {
-                    done = true;
-                    break;
-                }
-                float w = al * T;
-                c0 += B.z * w;
-                c1 += B.w * w;
-                c2 += sC[k] * w;
-                T = tn;
-                ++nc;
+    float T0 = 1.0f, r0 = 0.f, g0 = 0.f, b0 = 0.f;
+    float T1 = 1.0f, r1 = 0.f, g1 = 0.f, b1 = 0.f;
+    int32_t nc0 = 0, nc1 = 0, stop0 = -1, stop1 = -1;
+    bool d0 = !in0, d1 = !in1;
+    for (int32_t base = start; base < end; base += kBlendBatch) {
+        if (__syncthreads_count(d0 && d1) == kBlendThreads) break;
+        for (int l = threadIdx.x; l < kBlendBatch; l += kBlendThreads) {
+            const int32_t i = base + l;
+            if (i < end) {
+                uint32_t e = vals[i];
+                e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
+                const float4* rp = rec + kRec * (int64_t)e;
+                const float4 A = rp[0], B = rp[1];
+                sA[l] = make_float4(A.x, A.y, -0.5f * kL2e * A.z, -kL2e * A.w);
+                sB[l] = make_float4(-0.5f * kL2e * B.x, __log2f(B.y), B.z, B.w);
+                sC[l] = rp[2].x;
             }
         }
+        __syncthreads();
+        const int nb = min(kBlendBatch, end - base);
+        if (!(d0 && d1)) {
+            for (int k = 0; k < nb; ++k) {
+                if ((k & 15) == 0 && __all(d0 && d1)) break;
+                const float4 A = sA[k];
+                const float4 B = sB[k];
+                const float dx = fx - A.x;
+                const float u = A.w * dx;
+                const float t = fmaf(A.z * dx, dx, B.y);
+                const float e0 = fy0 - A.y, e1 = fy1 - A.y;
+                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e0, fmaf(B.x, e0, u), t)));
+                const float al1 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e1, fmaf(B.x, e1, u), t)));
+                const float tn0 = T0 * (1.0f - al0), tn1 = T1 * (1.0f - al1);
+                const bool u0 = !d0 && al0 >= kMinAlpha, u1 = !d1 && al1 >= kMinAlpha;
+                const bool s0 = u0 && tn0 < kTStop, s1 = u1 && tn1 < kTStop;
+                const bool a0 = u0 && !s0, a1 = u1 && !s1;
+                const float w0 = a0 ? al0 * T0 : 0.f, w1 = a1 ? al1 * T1 : 0.f;
+                const float cb = sC[k];
+                r0 = fmaf(B.z, w0, r0); g0 = fmaf(B.w, w0, g0); b0 = fmaf(cb, w0, b0);
+                r1 = fmaf(B.z, w1, r1); g1 = fmaf(B.w, w1, g1); b1 = fmaf(cb, w1, b1);
+                T0 = a0 ? tn0 : T0;
+                T1 = a1 ? tn1 : T1;
+                nc0 += a0 ? 1 : 0;
+                nc1 += a1 ? 1 : 0;
+                stop0 = s0 ? base + k : stop0;
+                stop1 = s1 ? base + k : stop1;
+                d0 = d0 || s0;
+                d1 = d1 || s1;
+            }
+        }
+        __syncthreads();  // the batch is read before the next one is staged
     }
-    if (inside) {
-        const int64_t p = (int64_t)py * s.W + px, np = (int64_t)s.W * s.H;
-        s.out_rgb[p] = c0;
-        s.out_rgb[np + p] = c1;
-        s.out_rgb[2 * np + p] = c2;
-        if (s.out_T) s.out_T[p] = T;
-        if (s.out_nc) s.out_nc[p] = nc;
+    // work of this tile (visits, contributions): a pixel visits its list up to
+    // and including the Gaussian that ends it; one sum per wave, then per block
+    const int32_t len = end - start;
+    int32_t ne = (in0 ? (stop0 >= 0 ? stop0 - start + 1 : len) : 0) + (in1 ? (stop1 >= 0 ? stop1 - start + 1 : len) : 0);
+    int32_t nce = nc0 + nc1;
+    for (int o = 32; o > 0; o >>= 1) {
+        ne += __shfl_xor(ne, o);
+        nce += __shfl_xor(nce, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sEval[threadIdx.x >> 6] = ne;
+        sEval[kBlendThreads / 64 + (threadIdx.x >> 6)] = nce;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t te = 0, tc = 0;
+        for (int w = 0; w < kBlendThreads / 64; ++w) {
+            te += sEval[w];
+            tc += sEval[kBlendThreads / 64 + w];
+        }
+        tile_eval[2 * gt] = te;
+        tile_eval[2 * gt + 1] = tc;
+    }
+    const int64_t np = (int64_t)s.W * s.H;
+    if (in0) {
+        const int64_t p = (int64_t)py0 * s.W + px;
+        s.out_rgb[p] = r0;
+        s.out_rgb[np + p] = g0;
+        s.out_rgb[2 * np + p] = b0;
+        if (s.out_T) s.out_T[p] = T0;
+        if (s.out_nc) s.out_nc[p] = nc0;
+    }
+    if (in1) {
+        const int64_t p = (int64_t)py1 * s.W + px;
+        s.out_rgb[p] = r1;
+        s.out_rgb[np + p] = g1;
+        s.out_rgb[2 * np + p] = b1;
+        if (s.out_T) s.out_T[p] = T1;
+        if (s.out_nc) s.out_nc[p] = nc1;
     }
 }
 
@@ -639,7 +735,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
     hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
     PreArgs pa;
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
-    hipLaunchKernelGGL(k_preprocess, grid_for(r.max_entries), dim3(NT), 0, st, pa);
+    hipLaunchKernelGGL(k_preprocess, grid_fit(k_preprocess, r.max_entries), dim3(NT), 0, st, pa);
     mark(mk, 4, st);
     const int tile_bits = bits_for(tab.total_tiles);
     DupArgs da;
@@ -651,16 +747,16 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st);
         if (e != hipSuccess) return e;
         mark(mk, 5, st);
-        hipLaunchKernelGGL(k_gather_counts, grid_for(r.max_entries / 4 + 1), dim3(NT), 0, st, r.dval[which], r.ntiles,
+        hipLaunchKernelGGL(k_gather_counts, grid_fit(k_gather_counts, r.max_entries / 4 + 1), dim3(NT), 0, st, r.dval[which], r.ntiles,
                            rc, r.scnt);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         mark(mk, 6, st);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_dup_small<false>, grid_for(r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
         mark(mk, 7, st);
-        hipLaunchKernelGGL(k_dup_big<false>, dim3(kGridBlocks), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
         mark(mk, 8, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
@@ -668,8 +764,8 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_fill_ranges, grid_for(2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
-        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_for(r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
+        hipLaunchKernelGGL(k_fill_ranges, grid_fit(k_fill_ranges, 2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
+        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
                            r.ranges, (uint32_t)tab.total_tiles);
     } else {
         mark(mk, 5, st);  // no per-Gaussian depth pass in this mode
@@ -678,24 +774,24 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         mark(mk, 6, st);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_dup_small<true>, grid_for(r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
         mark(mk, 7, st);
-        hipLaunchKernelGGL(k_dup_big<true>, dim3(kGridBlocks), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
         mark(mk, 8, st);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_fill_ranges, grid_for(2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
-        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_for(r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
+        hipLaunchKernelGGL(k_fill_ranges, grid_fit(k_fill_ranges, 2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
+        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
                            32, r.ranges, (uint32_t)tab.total_tiles);
     }
     r.order = nullptr;
     hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)tab.n), dim3(NT), 0, st, r.ranges, tab, rc);
     mark(mk, 10, st);
     hipLaunchKernelGGL(k_blend, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
-                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries);
+                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
     mark(mk, 11, st);
     return hipGetLastError();
 }

@@ -58,6 +58,14 @@ def test_tiny_frame_stage_by_stage(gs, tiny, tiny_cams):
     assert_image(iR, ref["right"])
     st = r.stats()
     assert st["n_visible"] == len(ov) and st["n_gauss"] == len(Gr)
+    # blend work: (pixel, Gaussian) visits per eye; a pixel in an ambiguity
+    # band may end one Gaussian earlier or later
+    for eye, key in ((0, "left"), (1, "right")):
+        ne, bnd = ref[key]["n_eval"], ref[key]["band"] != 0
+        assert abs(st["n_eval"][eye] - int(ne.sum())) <= int(bnd.sum()), (eye, st["n_eval"][eye], int(ne.sum()))
+        nc = ref[key]["n_contrib"]
+        assert abs(st["n_contrib"][eye] - int(nc.sum())) <= int(bnd.sum()), (eye, st["n_contrib"][eye], int(nc.sum()))
+        assert 0 < st["n_contrib"][eye] <= st["n_eval"][eye]
 
 
 def walk(n, step=0.15, turn=0.02):

@@ -68,7 +68,9 @@ def test_two_on_axis_gaussians_closed_form():
 
 def brute_force(mu, cov, rgb, alpha, cam):
     """Every Gaussian at every pixel centre, float64 depth order (ties by index),
-    2D covariance from a central-difference Jacobian of the projection."""
+    2D covariance from a central-difference Jacobian of the projection.
+    Returns the image, the transmittance and, per pixel, the Gaussian whose
+    opacity ended it (-1 where none did)."""
     W, H = cam["width"], cam["height"]
     R, p = np.asarray(cam["R"]), np.asarray(cam["pos"])
     fx = W / (2 * math.tan(cam["fovx"] / 2)); fy = H / (2 * math.tan(cam["fovy"] / 2))
@@ -96,17 +98,19 @@ def brute_force(mu, cov, rgb, alpha, cam):
     recs.sort(key=lambda r: (r[0], r[1]))
     px, py = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
     T = np.ones((H, W)); Cimg = np.zeros((3, H, W)); done = np.zeros((H, W), bool)
+    stopper = np.full((H, W), -1)
     for depth, i, m, Ci in recs:
         dx, dy = px - m[0], py - m[1]
         q = Ci[0, 0] * dx * dx + 2 * Ci[0, 1] * dx * dy + Ci[1, 1] * dy * dy
         a = np.minimum(0.99, alpha[i] * np.exp(-0.5 * q))
         use = (a >= MIN_A) & ~done
         stop = use & (T * (1 - a) < 1e-4)
+        stopper[stop] = i
         done |= stop
         add = use & ~stop
         Cimg += np.where(add, a * T, 0.0)[None] * rgb[i][:, None, None]
         T = np.where(add, T * (1 - a), T)
-    return Cimg, T
+    return Cimg, T, stopper
 
 
 @pytest.mark.parametrize("seed,W,H", [(1, 72, 56), (2, 40, 33), (3, 96, 64)])
@@ -114,15 +118,29 @@ def test_oracle_matches_brute_force(seed, W, H):
     # Gaussians kept inside the Jacobian clamp cone (|t_x / t_z| < 1.3 tan(fov/2)).
     mu, cov, rgb, al = synth.random_gaussians(300, seed=seed, box=2.0, zc=9.0)
     cam = synth.look_camera((0.1, -0.2, 0), (0.02, 0.01, 1), (0, -1, 0), W, H, math.radians(50))
-    out = oracle.render_gaussians(mu, cov, rgb, al, cam)
-    ref, Tref = brute_force(mu.astype(np.float64), cov.astype(np.float64), rgb.astype(np.float64),
-                            al.astype(np.float64), cam)
+    out = oracle.render_gaussians(mu, cov, rgb, al, cam, debug=True)
+    ref, Tref, stopper = brute_force(mu.astype(np.float64), cov.astype(np.float64), rgb.astype(np.float64),
+                                     al.astype(np.float64), cam)
     ok = out["band"] == 0
     assert ok.mean() > 0.99
     diff = np.abs(out["image"] - ref).max(0)
     # The brute force's Jacobian is a central difference (error ~1e-9 relative).
     assert diff[ok].max() < 1e-6, diff[ok].max()
     assert np.abs(out["T"] - Tref)[ok].max() < 1e-6
+    # visit counts: a pixel nothing ended visits its whole tile list; otherwise
+    # the last Gaussian it visited is the one the brute force saw end it
+    ntx = (W + 15) // 16
+    ty, tx = np.divmod(np.arange(H * W).reshape(H, W), W)
+    tile = (ty // 16) * ntx + (tx // 16)
+    ne = out["n_eval"]
+    length = out["ends"][tile] - out["starts"][tile]
+    assert np.all(ne >= out["n_contrib"]) and np.all(ne <= length)
+    free = ok & (stopper < 0)
+    assert np.array_equal(ne[free], length[free])
+    ended = ok & (stopper >= 0)
+    assert ended.any() and free.any()
+    last = out["sorted_g"][out["starts"][tile[ended]] + ne[ended] - 1]
+    assert np.array_equal(last, stopper[ended])
 
 
 def test_transmittance_bounds_and_monotone(tiny, tiny_cams):
