@@ -53,8 +53,6 @@ FORMS = {
 }
 MLP_FLOP_PER_ANCHOR = 2 * (3 * 35 * 32 + 32 * (10 + 30 + 70))  # eq. 3, k = 10
 SRC_DIR = os.path.join(ROOT, "paper_2502_14938_amd", "csrc")
-KERNEL_SOURCES = {"blend": "gsc_raster.hip", "preprocess": "gsc_raster.hip", "duplicate": "gsc_raster.hip",
-                  "derive": "gsc_derive_mfma.hip"}
 
 
 def parse():
@@ -229,22 +227,36 @@ def stage_bytes(counts, W, H, frames):
     return tot
 
 
+KERNEL_FUNCS = {"blend": ("gsc_raster.hip", "k_blend"), "preprocess": ("gsc_raster.hip", "k_preprocess"),
+                "derive": ("gsc_derive_mfma.hip", "k_derive_mfma")}
+
+
+def kernel_source_hash(kernel):
+    """sha256 of a kernel's function text (from its __global__ line to the
+    closing brace at column 0), so a counter summary is tied to the code it
+    measured."""
+    src, name = KERNEL_FUNCS[kernel]
+    text = open(os.path.join(SRC_DIR, src)).read()
+    i = text.find(" void %s(" % name)
+    if i < 0:
+        return None
+    i = text.rfind("\n", 0, i) + 1
+    j = text.find("\n}\n", i)
+    return hashlib.sha256(text[i:j + 3].encode()).hexdigest() if j > 0 else None
+
+
 def traffic_for(kernel, workload_tag):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the kernel's current source; else None."""
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, workload_tag))
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_FUNCS:
         return None
     kv = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = KERNEL_SOURCES.get(kernel)
-    if not src or "source_sha256" not in kv:
-        return None
-    h = hashlib.sha256(open(os.path.join(SRC_DIR, src), "rb").read()).hexdigest()
-    if h != kv["source_sha256"]:
+    if kv.get("kernel_source_sha256") != kernel_source_hash(kernel):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -375,6 +387,7 @@ def run_frames(args):
                            "gaussians": round(mean("n_gauss")),
                            "blend_visits": round(float(np.mean([sum(c["n_eval"]) for c in counts])) if counts else 0),
                            "blend_contrib": round(float(np.mean([sum(c["n_contrib"]) for c in counts])) if counts else 0),
+                           "tall_footprints": round(float(np.mean([c["n_tall"] for c in counts])) if counts else 0),
                            "pairs_per_eye": round(float(np.mean([sum(c["n_pairs"]) / 2 for c in counts])) if counts else 0)},
            "roofline": roofline, "roofline_stages": others}
     out.update(log)

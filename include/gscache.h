@@ -149,6 +149,7 @@ typedef struct gsc_frame_stats {
                                pixel, the Gaussians visited front to back until
                                its transmittance ran out or its list ended */
     int64_t n_contrib[2];   /* of those, the visits that were composited */
+    int64_t n_tall;         /* Gaussians (both eyes) whose footprint spans more than 4 tile rows */
 } gsc_frame_stats;
 
 typedef struct gsc_ctx gsc_ctx;

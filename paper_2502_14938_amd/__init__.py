@@ -62,14 +62,14 @@ class FrameStats(C.Structure):
                 ("n_pairs", C.c_int64 * 2), ("n_evicted", C.c_int64), ("depth_used", C.c_int32),
                 ("depth_next", C.c_int32), ("overflow", C.c_int32), ("pad", C.c_int32),
                 ("device_bytes", C.c_int64), ("n_eval", C.c_int64 * 2),
-                ("n_contrib", C.c_int64 * 2)]
+                ("n_contrib", C.c_int64 * 2), ("n_tall", C.c_int64)]
 
     def as_dict(self):
         return {"frame": self.frame, "n_visible": self.n_visible, "n_miss": self.n_miss, "n_gauss": self.n_gauss,
                 "n_pairs": [self.n_pairs[0], self.n_pairs[1]], "n_evicted": self.n_evicted,
                 "depth_used": self.depth_used, "depth_next": self.depth_next, "overflow": self.overflow,
                 "device_bytes": self.device_bytes, "n_eval": [self.n_eval[0], self.n_eval[1]],
-                "n_contrib": [self.n_contrib[0], self.n_contrib[1]]}
+                "n_contrib": [self.n_contrib[0], self.n_contrib[1]], "n_tall": self.n_tall}
 
 
 _lib = None
