@@ -152,7 +152,8 @@ hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int6
     hipError_t e;
 #define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
     A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
-    A_(r.big_list, max_entries);
+    A_(r.big_list, max_entries); A_(r.tall_cnt, max_entries / 256 + 1); A_(r.tall_off, max_entries / 256 + 1);
+    A_(r.tall_list, max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
@@ -595,7 +596,7 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->depth_used = k.depth_used;
     st->depth_next = k.depth;
     st->overflow = (r.overflow & 1) | (k.overflow & 2);
-    st->n_tall = r.n_big;
+    st->n_tall = r.n_tall;
     size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;
     if (c->rendered && !c->explicit_render && c->last_tab.total_tiles > 0) {

@@ -50,8 +50,9 @@ struct RasterCounters {
     int32_t entry_base[kMaxSeg + 1];
     int32_t n_pairs;              // total tile pairs (all segments)
     int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
+    int32_t n_chunks;             // chunks of 256 depth ranks (tall-entry lists)
+    int32_t n_tall;               // tall entries (more than 4 tile rows)
     int32_t overflow;             // bit0: pair capacity
-    int32_t n_big;                // entries in the large-footprint list
     int32_t pad;
 };
 
@@ -147,7 +148,10 @@ struct View {
 struct Raster {
     int64_t max_entries = 0, max_pairs = 0, max_tiles = 0;
     float4* rec = nullptr;      // [4 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count), spans
-    int32_t* big_list = nullptr;  // entries emitted one wave each
+    int32_t* big_list = nullptr;  // tall entries (ranks), listed in their chunk's 256 slots
+    int32_t* tall_cnt = nullptr;  // [max_entries / 256 + 1] tall entries per chunk of 256 ranks
+    uint32_t* tall_off = nullptr; // [max_entries / 256 + 1] their exclusive prefix
+    int32_t* tall_list = nullptr; // [max_entries] tall entries (ranks), dense
     uint32_t* ntiles = nullptr; // tile count per entry
     uint32_t* scnt = nullptr;   // tile count per depth rank
     int32_t* n_sort = nullptr;  // [1] pairs to sort (clamped to capacity)

@@ -49,7 +49,6 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
     }
     rc->entry_base[tab.n] = acc;
     rc->overflow = 0;
-    rc->n_big = 0;
     if (acc > max_entries) {
         rc->overflow |= 2;
         acc = (int32_t)max_entries;
@@ -365,10 +364,13 @@ struct DupArgs {
 //                preprocess stored give each pair's tile; a wave writes its 64
 //                entries' pairs together, lane j taking pairs j, j + 64, ...
 //                of their concatenation (consecutive lanes, consecutive
-//                slots), so the stores coalesce; taller entries are appended
-//                to a list;
-//   k_dup_big    one wave per listed entry: row spans recomputed one row per
-//                lane, and lanes stride along each row so the stores coalesce.
+//                slots), so the stores coalesce; taller entries are listed
+//                in their chunk's slots (the chunk of 256 ranks a block
+//                step covers, count per chunk; no atomics);
+//   k_dup_big    one wave per tall entry of the dense list (chunk lists
+//                joined by a scan of their counts): row spans recomputed one
+//                row per lane, and lanes stride along each row so the stores
+//                coalesce.
 template <bool kFull>
 __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t, uint32_t e, uint64_t low) {
     if (q >= d.max_pairs) return;
@@ -378,7 +380,8 @@ __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t
 }
 
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict__ big_list, int32_t* n_big) {
+__global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict__ big_list,
+                                                 int32_t* __restrict__ tall_cnt) {
     // per thread (entry): pairs before each row's end, first tile id of each row
     __shared__ uint32_t s_cum[kSmallRows][NT];
     __shared__ uint32_t s_first[kSmallRows][NT];
@@ -386,6 +389,7 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
     __shared__ uint32_t s_out[NT];    // output offset of the entry
     __shared__ uint32_t s_e[NT];      // entry id
     __shared__ uint32_t s_low[NT];    // depth bits (full-key mode)
+    __shared__ uint32_t s_wtall[NT / 64];
     const int64_t ne = d.rc->n_entries;
     const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
@@ -430,16 +434,22 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
         }
         uint32_t tot;
         s_start[threadIdx.x] = wave_excl_scan(n_here, tot);
-        // wave-aggregated append of the tall entries (their order is irrelevant)
+        // tall entries of this chunk of 256 ranks go to the chunk's own slots
+        // of the list (no atomics; their order is irrelevant)
         const uint64_t m = __ballot(is_big);
-        if (m) {
-            int32_t at = 0;
-            const int leader = __ffsll((long long)m) - 1;
-            if (lane == leader) at = atomicAdd(n_big, __popcll(m));
-            at = __shfl(at, leader, 64);
-            if (is_big) big_list[at + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)r;
-        }
+        if (lane == 0) s_wtall[threadIdx.x >> 6] = (uint32_t)__popcll(m);
         __syncthreads();
+        const int64_t chunk = base / NT;
+        if (is_big) {
+            uint32_t at = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            for (int q = 0; q < (int)(threadIdx.x >> 6); ++q) at += s_wtall[q];
+            big_list[chunk * NT + at] = (int32_t)r;
+        }
+        if (threadIdx.x == 0) {
+            uint32_t n = 0;
+            for (int q = 0; q < NT / 64; ++q) n += s_wtall[q];
+            tall_cnt[chunk] = (int32_t)n;
+        }
         // the wave's pairs in rank order, lane j taking pairs j, j + 64, ...:
         // consecutive lanes write consecutive slots of one entry's range
         for (uint32_t j = lane; j < tot; j += 64) {
@@ -461,61 +471,74 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
     }
 }
 
+// Dense list of the tall entries: chunk c's entries at tall_off[c] + i.
+__global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ big_list,
+                                                     const int32_t* __restrict__ tall_cnt,
+                                                     const uint32_t* __restrict__ tall_off, const RasterCounters* rc,
+                                                     int32_t* __restrict__ tall_list) {
+    const int64_t nc = rc->n_chunks;
+    for (int64_t c = blockIdx.x; c < nc; c += gridDim.x)
+        if ((int32_t)threadIdx.x < tall_cnt[c]) tall_list[tall_off[c] + threadIdx.x] = big_list[c * NT + threadIdx.x];
+}
+
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ big_list, const int32_t* n_big) {
+__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_list) {
     const int lane = threadIdx.x & 63;
-    const int64_t nb = *n_big;
+    const int64_t nb = d.rc->n_tall;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t b = wave; b < nb; b += nwaves) {
-        const int64_t r = big_list[b];
-        const uint32_t e = kFull ? (uint32_t)r : d.order[r];
-        const float4* rp = d.rec + kRec * (int64_t)e;
-        const float4 C = rp[2];
-        const uint32_t cnt = __float_as_uint(C.w);
-        const uint32_t rows = __float_as_uint(C.y);
-        const int y0 = rows & 0xffff, y1 = rows >> 16;
-        const Seg& s = d.tab.s[__float_as_uint(C.z)];
-        const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
-        const int64_t o = d.offs[r];
-        uint32_t run = 0;
-        if (y1 - y0 + 1 <= kSmallRows) {
-            const float4 D = rp[3];
-            const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
-                                             __float_as_uint(D.w)};
+        {
+            const int64_t r = tall_list[b];
+            const uint32_t e = kFull ? (uint32_t)r : d.order[r];
+            const float4* rp = d.rec + kRec * (int64_t)e;
+            const float4 C = rp[2];
+            const uint32_t cnt = __float_as_uint(C.w);
+            const uint32_t rows = __float_as_uint(C.y);
+            const int y0 = rows & 0xffff, y1 = rows >> 16;
+            const Seg& s = d.tab.s[__float_as_uint(C.z)];
+            const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
+            const int64_t o = d.offs[r];
+            uint32_t run = 0;
+            if (y1 - y0 + 1 <= kSmallRows) {
+                const float4 D = rp[3];
+                const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
+                                                 __float_as_uint(D.w)};
 #pragma unroll
-            for (int i = 0; i < kSmallRows; ++i) {
-                const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
-                const uint32_t rowbase = (uint32_t)(s.tile_base + (y0 + i) * s.ntx);
-                for (int xx = lo + lane; xx <= hi; xx += 64)
-                    put_pair<kFull>(d, o + run + (uint32_t)(xx - lo), rowbase + (uint32_t)xx, e, low);
-                run += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-            }
-        } else {
-            const float4 A = rp[0], B = rp[1];
-            const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
-            for (int chunk = y0; chunk <= y1; chunk += 64) {
-                int lo = 0, hi = -1;
-                if (chunk + lane <= y1) row_span(el, chunk + lane, s.ntx, s.W, s.H, lo, hi);
-                uint32_t n_row = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot;
-                const uint32_t ex = wave_excl_scan(n_row, tot);
-                const int nr = min(64, y1 - chunk + 1);
-                for (int rr = 0; rr < nr; ++rr) {
-                    const int rlo = __shfl(lo, rr, 64), rhi = __shfl(hi, rr, 64);
-                    const uint32_t rex = (uint32_t)__shfl((int)ex, rr, 64);
-                    const uint32_t rowbase = (uint32_t)(s.tile_base + (chunk + rr) * s.ntx);
-                    for (int xx = rlo + lane; xx <= rhi; xx += 64) {
-                        const uint32_t w = run + rex + (uint32_t)(xx - rlo);
-                        if (w < cnt) put_pair<kFull>(d, o + w, rowbase + (uint32_t)xx, e, low);
-                    }
+                for (int i = 0; i < kSmallRows; ++i) {
+                    const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
+                    const uint32_t rowbase = (uint32_t)(s.tile_base + (y0 + i) * s.ntx);
+                    for (int xx = lo + lane; xx <= hi; xx += 64)
+                        put_pair<kFull>(d, o + run + (uint32_t)(xx - lo), rowbase + (uint32_t)xx, e, low);
+                    run += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
                 }
-                run += tot;
+            } else {
+                const float4 A = rp[0], B = rp[1];
+                const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
+                for (int chunk = y0; chunk <= y1; chunk += 64) {
+                    int lo = 0, hi = -1;
+                    if (chunk + lane <= y1) row_span(el, chunk + lane, s.ntx, s.W, s.H, lo, hi);
+                    uint32_t n_row = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot;
+                    const uint32_t ex = wave_excl_scan(n_row, tot);
+                    const int nr = min(64, y1 - chunk + 1);
+                    for (int rr = 0; rr < nr; ++rr) {
+                        const int rlo = __shfl(lo, rr, 64), rhi = __shfl(hi, rr, 64);
+                        const uint32_t rex = (uint32_t)__shfl((int)ex, rr, 64);
+                        const uint32_t rowbase = (uint32_t)(s.tile_base + (chunk + rr) * s.ntx);
+                        for (int xx = rlo + lane; xx <= rhi; xx += 64) {
+                            const uint32_t w = run + rex + (uint32_t)(xx - rlo);
+                            if (w < cnt) put_pair<kFull>(d, o + w, rowbase + (uint32_t)xx, e, low);
+                        }
+                    }
+                    run += tot;
+                }
             }
         }
     }
 }
 
 __global__ void k_pairs_clamp(RasterCounters* rc, int32_t* n_sort, int64_t max_pairs) {
+    rc->n_chunks = (rc->n_entries + NT - 1) / NT;
     int32_t n = rc->n_pairs;
     if ((int64_t)n > max_pairs) {
         rc->overflow |= 1;
@@ -729,6 +752,17 @@ void seg_camera(Seg& s, const gsc_camera& c) {
     s.nty = (c.height + kTile - 1) / kTile;
 }
 
+// Offsets of the chunks' tall entries and their dense list.
+hipError_t tall_list(Raster& r, hipStream_t st) {
+    RasterCounters* rc = r.cnt;
+    hipError_t e = scan_u32(reinterpret_cast<const uint32_t*>(r.tall_cnt), r.tall_off, &rc->n_chunks, 0, &rc->n_tall,
+                            r.block_sums, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.big_list, r.tall_cnt, r.tall_off, rc,
+                       r.tall_list);
+    return hipGetLastError();
+}
+
 hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st, Marks* mk) {
     RasterCounters* rc = r.cnt;
     mark(mk, 3, st);
@@ -754,9 +788,11 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         mark(mk, 6, st);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
         mark(mk, 7, st);
-        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        e = tall_list(r, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.tall_list);
         mark(mk, 8, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
@@ -774,9 +810,11 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
         hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         mark(mk, 6, st);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
-        hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
         mark(mk, 7, st);
-        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.big_list, &rc->n_big);
+        e = tall_list(r, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.tall_list);
         mark(mk, 8, st);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
