@@ -513,6 +513,7 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
         View& v = c->view[c->nviews == 1 ? 0 : e];
         Seg& s = tab.s[e];
         s.L0 = v.L0; s.L1 = v.L1; s.L2 = v.L2; s.L3 = v.L3; s.G = v.G; s.nG = &v.cnt->n_gauss; s.nG_host = 0;
+        s.anchor_pos = c->scene.posr; s.line_anchor = v.line_anchor; s.k = c->scene.k;
         seg_camera(s, c->eye[e]);
         s.tile_base = tiles;
         tiles += s.ntx * s.nty;
@@ -547,6 +548,7 @@ int gsc_render_gaussians(gsc_ctx* c, const gsc_gaussians* g, const gsc_camera* c
     tab.n = 1;
     Seg& s = tab.s[0];
     s.L0 = c->xg.L0; s.L1 = c->xg.L1; s.L2 = c->xg.L2; s.L3 = c->xg.L3; s.G = nullptr; s.nG = nullptr;
+    s.anchor_pos = nullptr; s.line_anchor = nullptr; s.k = 1;
     s.nG_host = (int32_t)g->n;
     seg_camera(s, *cam);
     s.tile_base = 0;
@@ -724,10 +726,17 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
                 HIP_OR_FAIL(c, hipMemcpy(l1.data(), v.L1, E * 16, hipMemcpyDeviceToHost));
                 HIP_OR_FAIL(c, hipMemcpy(l2.data(), v.L2, E * 16, hipMemcpyDeviceToHost));
                 HIP_OR_FAIL(c, hipMemcpy(l3.data(), v.L3, E * 4, hipMemcpyDeviceToHost));
+                // positions are stored relative to the line's anchor
+                std::vector<int32_t> la((size_t)v.C);
+                std::vector<float4> ap((size_t)c->scene.n);
+                HIP_OR_FAIL(c, hipMemcpy(la.data(), v.line_anchor, la.size() * 4, hipMemcpyDeviceToHost));
+                HIP_OR_FAIL(c, hipMemcpy(ap.data(), c->scene.posr, ap.size() * 16, hipMemcpyDeviceToHost));
                 float* o = (float*)dst;
                 for (int64_t i = 0; i < m; ++i) {
                     int64_t e = G[i];
-                    float row[13] = {l0[e].x, l0[e].y, l0[e].z, l1[e].x, l1[e].y, l1[e].z, l1[e].w,
+                    const float4 a = ap[(size_t)la[(size_t)(e / c->scene.k)]];
+                    float row[13] = {(float)((double)a.x + l0[e].x), (float)((double)a.y + l0[e].y),
+                                     (float)((double)a.z + l0[e].z), l1[e].x, l1[e].y, l1[e].z, l1[e].w,
                                      l2[e].x, l2[e].y, l2[e].z, l2[e].w, l3[e], l0[e].w};
                     std::memcpy(o + 13 * i, row, sizeof(row));
                 }

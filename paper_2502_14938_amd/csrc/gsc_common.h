@@ -58,17 +58,20 @@ struct RasterCounters {
 
 // One (viewer, eye) image of a raster batch; passed by value in kernel args.
 struct Seg {
-    const float4* L0;   // mu.xyz, alpha      [entries of the view's cache]
+    const float4* L0;   // mu - anchor (xyz), alpha   [entries of the view's cache]
     const float4* L1;   // cov xx xy xz yy
     const float4* L2;   // cov yz zz, r, g
     const float* L3;    // b
     const int32_t* G;   // render buffer: cache entry per Gaussian (nullptr = identity)
     const int32_t* nG;  // device count of G (nullptr = nG_host)
     int32_t nG_host;
+    const float4* anchor_pos;    // anchors (x, y, z, radius); nullptr: L0 holds absolute positions
+    const int32_t* line_anchor;  // anchor of each cache line
+    int32_t k;                   // entries per cache line
     int32_t W, H, ntx, nty;
     int32_t tile_base;  // first global tile id of this image
     float R[9];
-    float pos[3];
+    double pos[3];      // eye position (FP64: subtracted from FP32 anchor positions)
     float fx, fy, cx, cy, limx, limy, znear;
     float* out_rgb;     // [3,H,W]
     float* out_T;       // [H,W] or nullptr

@@ -284,12 +284,15 @@ __global__ __launch_bounds__(NT) void k_vslot(const int32_t* __restrict__ visibl
 }
 
 // No-cache schedule: every visible anchor is a miss derived into line i.
-__global__ __launch_bounds__(NT) void k_nocache(int32_t* __restrict__ misses, int32_t* __restrict__ vslot, Counters* cnt) {
+__global__ __launch_bounds__(NT) void k_nocache(const int32_t* __restrict__ visible, int32_t* __restrict__ misses,
+                                                int32_t* __restrict__ vslot, int32_t* __restrict__ line_anchor,
+                                                Counters* cnt) {
     int32_t nv = cnt->n_visible;
     if (gtid() == 0) cnt->n_miss = nv;
     for (int64_t i = gtid(); i < nv; i += gstride()) {
         misses[i] = (int32_t)i;
         vslot[i] = (int32_t)i;
+        line_anchor[i] = visible[i];
     }
 }
 
@@ -387,7 +390,8 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
 
     const bool reuse = (a.flags & GSC_FLAG_REUSE) != 0;
     if (!reuse) {
-        hipLaunchKernelGGL(k_nocache, grid_fit(k_nocache, n), dim3(NT), 0, st, v.misses, v.vslot, cnt);
+        hipLaunchKernelGGL(k_nocache, grid_fit(k_nocache, n), dim3(NT), 0, st, v.visible, v.misses, v.vslot,
+                           v.line_anchor, cnt);
     } else {
         const int64_t C = v.C;
         hipLaunchKernelGGL(k_cache_invalidate, grid_fit(k_cache_invalidate, C), dim3(NT), 0, st, v.line_anchor, v.line_tau, v.slot_of, C,

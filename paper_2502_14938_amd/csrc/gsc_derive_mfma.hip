@@ -319,7 +319,9 @@ __global__ __launch_bounds__(NT) void k_derive_mfma(MfmaDeriveArgs a) {
                     for (int cc = rr; cc < 3; ++cc)
                         S[idx++] = R[rr][0] * v[0] * R[cc][0] + R[rr][1] * v[1] * R[cc][1] + R[rr][2] * v[2] * R[cc][2];
                 const int64_t e = (int64_t)line * k + j;
-                a.L0[e] = make_float4(x.x + sc[0] * off[0], x.y + sc[1] * off[1], x.z + sc[2] * off[2], alpha);
+                // position relative to the anchor (small, so FP32 keeps it to
+                // ~1e-7 m); the rasteriser adds anchor - camera in FP64
+                a.L0[e] = make_float4(sc[0] * off[0], sc[1] * off[1], sc[2] * off[2], alpha);
                 a.L1[e] = make_float4(S[0], S[1], S[2], S[3]);
                 a.L2[e] = make_float4(S[4], S[5], r, gg);
                 a.L3[e] = bb;

@@ -239,7 +239,17 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
             int64_t src = s.G ? (int64_t)s.G[g] : g;
             float4 l0 = s.L0[src], l1 = s.L1[src], l2 = s.L2[src];
             lb = s.L3[src];
-            float vx = l0.x - s.pos[0], vy = l0.y - s.pos[1], vz = l0.z - s.pos[2];
+            // mu - eye = (anchor - eye) + (mu - anchor): the first term in FP64
+            // from the exact FP32 anchor, the second as stored
+            double ax = 0.0, ay = 0.0, az = 0.0;
+            if (s.anchor_pos) {
+                const int32_t an = s.line_anchor[src / s.k];  // valid for every line in the buffer
+                const float4 ap = s.anchor_pos[an >= 0 ? an : 0];
+                ax = ap.x; ay = ap.y; az = ap.z;
+            }
+            float vx = (float)((ax - s.pos[0]) + (double)l0.x);
+            float vy = (float)((ay - s.pos[1]) + (double)l0.y);
+            float vz = (float)((az - s.pos[2]) + (double)l0.z);
             float tx = s.R[0] * vx + s.R[1] * vy + s.R[2] * vz;
             float ty = s.R[3] * vx + s.R[4] * vy + s.R[5] * vz;
             float tz = s.R[6] * vx + s.R[7] * vy + s.R[8] * vz;
@@ -737,7 +747,7 @@ int bits_for(int64_t v) {
 
 void seg_camera(Seg& s, const gsc_camera& c) {
     for (int i = 0; i < 9; ++i) s.R[i] = (float)c.R[i];
-    for (int i = 0; i < 3; ++i) s.pos[i] = (float)c.pos[i];
+    for (int i = 0; i < 3; ++i) s.pos[i] = c.pos[i];
     double tx = std::tan(0.5 * c.fovx), ty = std::tan(0.5 * c.fovy);
     s.fx = (float)(c.width / (2.0 * tx));
     s.fy = (float)(c.height / (2.0 * ty));
