@@ -195,6 +195,7 @@ def quality_pass(torch, r, plain, traj, W, H):
     plain FP32 form: per-eye PSNR and the per-frame counters."""
     r.reset_cache()
     plain.reset_cache()
+    r.count_work(True)  # blend visit counts for the roofline (same frames as the timed pass)
     a = [torch.zeros(3, H, W, device="cuda") for _ in range(4)]
     ps, counts = [], []
     for L, R in traj:
@@ -204,6 +205,7 @@ def quality_pass(torch, r, plain, traj, W, H):
             plain.frame(L, R, a[2], a[3])
             ps += [psnr_dev(torch, a[0], a[2]), psnr_dev(torch, a[1], a[3])]
         counts.append(st)
+    r.count_work(False)
     return np.array(ps), counts
 
 
@@ -314,6 +316,7 @@ def run_frames(args):
     else:
         counts = []
         r.reset_cache()
+        r.count_work(True)
         oL = torch.zeros(3, H, W, device="cuda"); oR = torch.zeros(3, H, W, device="cuda")
         for L, R_ in traj[:max(1, min(len(traj), args.steps))]:
             r.frame(L, R_, oL, oR)

@@ -147,7 +147,8 @@ typedef struct gsc_frame_stats {
     int64_t device_bytes;   /* device memory owned by the context */
     int64_t n_eval[2];      /* (pixel, Gaussian) visits of the blend per eye: per
                                pixel, the Gaussians visited front to back until
-                               its transmittance ran out or its list ended */
+                               its transmittance ran out or its list ended
+                               (0 unless gsc_count_work is on) */
     int64_t n_contrib[2];   /* of those, the visits that were composited */
     int64_t n_tall;         /* Gaussians (both eyes) whose footprint spans more than 4 tile rows */
 } gsc_frame_stats;
@@ -214,6 +215,12 @@ int gsc_reset_cache(gsc_ctx* ctx);
 /* Copies at most cap elements (of the unit above: ints, floats or rows) to
  * host_dst and writes the full count to *n. */
 int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap, int64_t* n);
+
+/* With enable != 0 the blend of later frames also counts its work per eye
+ * (gsc_frame_stats n_eval, n_contrib); off by default, since the counters
+ * cost the blend a few instructions per (pixel, Gaussian) visit.  The
+ * raster-only entry counts whenever it is asked for per-pixel counts. */
+int gsc_count_work(gsc_ctx* ctx, int enable);
 
 /* ---------------- stage timing -------------------------------------------
  * With timing on, every frame (gsc_derive + gsc_render_stereo) records HIP

@@ -107,6 +107,7 @@ SYMBOLS = {
     "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "gsc_server_pending": ([C.c_void_p], C.c_int),
     "gsc_timing": ([C.c_void_p, C.c_int], C.c_int),
+    "gsc_count_work": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing_read": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gsc_server_last_error": ([C.c_void_p], C.c_char_p),
     "gsc_server_leave": ([C.c_void_p, C.c_int32], C.c_int),
@@ -269,6 +270,10 @@ class Renderer:
         return out
 
     # ---------------------------------------------------------- predictor
+    def count_work(self, enable=True):
+        """Let the blend count its visits and contributions (stats n_eval, n_contrib)."""
+        self._check(lib().gsc_count_work(self.h, 1 if enable else 0))
+
     def timing(self, enable=True):
         """Record device time per stage of every frame from now on (or stop)."""
         self._check(lib().gsc_timing(self.h, 1 if enable else 0))

@@ -523,9 +523,11 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
     }
     tab.total_tiles = tiles;
     Marks* mk = frame_marks(c);
-    hipError_t e = raster_batch(tab, c->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->stream, mk);
+    hipError_t e = raster_batch(tab, c->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->count_work,
+                                c->stream, mk);
     if (e != hipSuccess) return hip_fail(c, e, "gsc_render_stereo");
     if (mk) c->marks_used += 1;
+    c->last_count_work = c->count_work;
     c->last_tab = tab;
     c->rendered = true;
     c->explicit_render = false;
@@ -554,7 +556,8 @@ int gsc_render_gaussians(gsc_ctx* c, const gsc_gaussians* g, const gsc_camera* c
     s.tile_base = 0;
     s.out_rgb = out_chw; s.out_T = out_T; s.out_nc = out_nc;
     tab.total_tiles = s.ntx * s.nty;
-    e = raster_batch(tab, c->xraster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->stream);
+    e = raster_batch(tab, c->xraster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->count_work || out_nc,
+                     c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "gsc_render_gaussians");
     c->last_tab = tab;
     c->rendered = true;
@@ -601,7 +604,7 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->n_tall = r.n_tall;
     size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;
-    if (c->rendered && !c->explicit_render && c->last_tab.total_tiles > 0) {
+    if (c->rendered && !c->explicit_render && c->last_count_work && c->last_tab.total_tiles > 0) {
         std::vector<int32_t> te(2 * (size_t)c->last_tab.total_tiles);
         HIP_OR_FAIL(c, hipMemcpy(te.data(), c->raster.tile_eval, te.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int sg = 0; sg < c->last_tab.n && sg < 2; ++sg) {
@@ -615,6 +618,12 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
             st->n_contrib[sg] = co;
         }
     }
+    return GSC_OK;
+}
+
+int gsc_count_work(gsc_ctx* c, int enable) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_count_work: null context");
+    c->count_work = enable != 0;
     return GSC_OK;
 }
 

@@ -224,7 +224,11 @@ inline void mark(Marks* m, int i, hipStream_t st) {
 hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr);
 
 // Raster stage of a batch of segments.
-hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st, Marks* mk = nullptr);
+// count_work: the blend also counts its (pixel, Gaussian) visits and
+// contributions per tile (and writes per-pixel contributor counts when a
+// segment asks for them); without it those counters are not kept.
+hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool count_work, hipStream_t st,
+                        Marks* mk = nullptr);
 
 // Blocks of `threads` threads of `kernel` the whole device holds at once
 // (occupancy x compute units; cached per kernel and device).  Grid-stride

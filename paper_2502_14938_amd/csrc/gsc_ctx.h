@@ -100,6 +100,8 @@ struct gsc_ctx {
     int32_t* lab_iota = nullptr;
     uint8_t* lab_y = nullptr;
     int64_t lab_entries = 0;      // anchors * k the label scratch holds
+    bool count_work = false;       // blend counts visits / contributions (gsc_count_work)
+    bool last_count_work = false;  // ... for the last rendered frame
     // stage timing (gsc_timing): one event set per frame since the last read
     bool timing = false;
     std::vector<gsc::Marks> marks;

@@ -621,6 +621,7 @@ __global__ __launch_bounds__(NT) void k_seg_pairs(const int32_t* __restrict__ ra
 // 1e-4; otherwise composite.  The composite step is predicated (no branches);
 // a wave leaves a batch early once all its pixels are done, the block once
 // every pixel is.
+template <bool kCount>
 __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int32_t* __restrict__ ranges,
                                                           const uint32_t* __restrict__ vals,
                                                           const float4* __restrict__ rec, uint32_t max_entries,
@@ -685,10 +686,12 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
                 r1 = fmaf(B.z, w1, r1); g1 = fmaf(B.w, w1, g1); b1 = fmaf(cb, w1, b1);
                 T0 = a0 ? tn0 : T0;
                 T1 = a1 ? tn1 : T1;
-                nc0 += a0 ? 1 : 0;
-                nc1 += a1 ? 1 : 0;
-                stop0 = s0 ? base + k : stop0;
-                stop1 = s1 ? base + k : stop1;
+                if (kCount) {
+                    nc0 += a0 ? 1 : 0;
+                    nc1 += a1 ? 1 : 0;
+                    stop0 = s0 ? base + k : stop0;
+                    stop1 = s1 ? base + k : stop1;
+                }
                 d0 = d0 || s0;
                 d1 = d1 || s1;
             }
@@ -697,26 +700,28 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
     }
     // work of this tile (visits, contributions): a pixel visits its list up to
     // and including the Gaussian that ends it; one sum per wave, then per block
-    const int32_t len = end - start;
-    int32_t ne = (in0 ? (stop0 >= 0 ? stop0 - start + 1 : len) : 0) + (in1 ? (stop1 >= 0 ? stop1 - start + 1 : len) : 0);
-    int32_t nce = nc0 + nc1;
-    for (int o = 32; o > 0; o >>= 1) {
-        ne += __shfl_xor(ne, o);
-        nce += __shfl_xor(nce, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        sEval[threadIdx.x >> 6] = ne;
-        sEval[kBlendThreads / 64 + (threadIdx.x >> 6)] = nce;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t te = 0, tc = 0;
-        for (int w = 0; w < kBlendThreads / 64; ++w) {
-            te += sEval[w];
-            tc += sEval[kBlendThreads / 64 + w];
+    if (kCount) {
+        const int32_t len = end - start;
+        int32_t ne = (in0 ? (stop0 >= 0 ? stop0 - start + 1 : len) : 0) + (in1 ? (stop1 >= 0 ? stop1 - start + 1 : len) : 0);
+        int32_t nce = nc0 + nc1;
+        for (int o = 32; o > 0; o >>= 1) {
+            ne += __shfl_xor(ne, o);
+            nce += __shfl_xor(nce, o);
         }
-        tile_eval[2 * gt] = te;
-        tile_eval[2 * gt + 1] = tc;
+        if ((threadIdx.x & 63) == 0) {
+            sEval[threadIdx.x >> 6] = ne;
+            sEval[kBlendThreads / 64 + (threadIdx.x >> 6)] = nce;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t te = 0, tc = 0;
+            for (int w = 0; w < kBlendThreads / 64; ++w) {
+                te += sEval[w];
+                tc += sEval[kBlendThreads / 64 + w];
+            }
+            tile_eval[2 * gt] = te;
+            tile_eval[2 * gt + 1] = tc;
+        }
     }
     const int64_t np = (int64_t)s.W * s.H;
     if (in0) {
@@ -725,7 +730,7 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         s.out_rgb[np + p] = g0;
         s.out_rgb[2 * np + p] = b0;
         if (s.out_T) s.out_T[p] = T0;
-        if (s.out_nc) s.out_nc[p] = nc0;
+        if (kCount && s.out_nc) s.out_nc[p] = nc0;
     }
     if (in1) {
         const int64_t p = (int64_t)py1 * s.W + px;
@@ -733,7 +738,7 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         s.out_rgb[np + p] = g1;
         s.out_rgb[2 * np + p] = b1;
         if (s.out_T) s.out_T[p] = T1;
-        if (s.out_nc) s.out_nc[p] = nc1;
+        if (kCount && s.out_nc) s.out_nc[p] = nc1;
     }
 }
 
@@ -773,7 +778,8 @@ hipError_t tall_list(Raster& r, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipStream_t st, Marks* mk) {
+hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool count_work, hipStream_t st,
+                        Marks* mk) {
     RasterCounters* rc = r.cnt;
     mark(mk, 3, st);
     hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
@@ -838,8 +844,12 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, hipS
     r.order = nullptr;
     hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)tab.n), dim3(NT), 0, st, r.ranges, tab, rc);
     mark(mk, 10, st);
-    hipLaunchKernelGGL(k_blend, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
-                       r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
+    if (count_work)
+        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
+                           r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
+    else
+        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
+                           r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
     mark(mk, 11, st);
     return hipGetLastError();
 }

@@ -378,7 +378,7 @@ int gsc_server_step(gsc_server* s) {
         }
     }
     tab.total_tiles = tiles;
-    hipError_t e = raster_batch(tab, s->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, s->st);
+    hipError_t e = raster_batch(tab, s->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, false, s->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&rep->rc, s->raster.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost, s->st);
     if (e != hipSuccess) {

@@ -36,6 +36,7 @@ def test_tiny_frame_stage_by_stage(gs, tiny, tiny_cams):
     L, R = tiny_cams
     r = gs.Renderer(k=tiny.k, max_width=256, max_height=256)
     r.load(tiny)
+    r.count_work(True)
     iL, iR = gpu_frame(r, L, R)
     ref = oracle.render_frame(tiny, L, R, debug=True)
     vis = r.debug("visible")
