@@ -142,7 +142,7 @@ typedef struct gsc_frame_stats {
     int64_t n_evicted;      /* lines evicted for capacity this frame */
     int32_t depth_used;     /* reuse depth d_t applied this frame */
     int32_t depth_next;     /* d_{t+1} */
-    int32_t overflow;       /* bit0 pair capacity, bit1 cache capacity */
+    int32_t overflow;       /* bit0 raster capacity (tile pairs, entries, tall-row spans), bit1 cache capacity */
     int32_t pad;
     int64_t device_bytes;   /* device memory owned by the context */
     int64_t n_eval[2];      /* (pixel, Gaussian) visits of the blend per eye: per

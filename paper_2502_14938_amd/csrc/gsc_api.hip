@@ -154,6 +154,9 @@ hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int6
     A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
     A_(r.big_list, max_entries); A_(r.tall_cnt, max_entries / 256 + 1); A_(r.tall_off, max_entries / 256 + 1);
     A_(r.tall_list, max_entries);
+    A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
+    A_(r.pt_dense, max_entries); A_(r.pt_rowcnt, max_entries); A_(r.pt_rowoff, max_entries);
+    A_(r.spans, 2 * max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
@@ -201,6 +204,7 @@ hipError_t alloc_raster(AllocSet& set, Raster& r, int64_t max_entries, int64_t m
     r.max_entries = max_entries;
     r.max_pairs = max_pairs;
     r.max_tiles = max_tiles;
+    r.span_cap = 2 * max_entries;
     hipError_t e = raster_layout(r, max_entries, max_pairs, max_tiles, full_key,
                                  [&](auto*& p, int64_t cnt) { return dalloc(set, r.bytes, &p, cnt); });
     if (e != hipSuccess) return e;
@@ -572,13 +576,14 @@ int gsc_sync(gsc_ctx* c) {
     if (c->rendered) {
         Raster& R = c->explicit_render ? c->xraster : c->raster;
         HIP_OR_FAIL(c, hipMemcpy(R.cnt_host, R.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
-        of |= R.cnt_host->overflow & 1;
+        of |= (R.cnt_host->overflow & 7) ? 1 : 0;  // tile pairs, entries or tall-row spans
     }
     if (c->loaded && c->derived) {
         HIP_OR_FAIL(c, hipMemcpy(c->view[0].cnt_host, c->view[0].cnt, sizeof(Counters), hipMemcpyDeviceToHost));
         of |= c->view[0].cnt_host->overflow & 2;
     }
-    if (of) return fail(c, GSC_E_CAPACITY, of & 1 ? "tile-pair capacity exceeded" : "cache capacity exceeded");
+    if (of) return fail(c, GSC_E_CAPACITY, of & 1 ? "raster capacity exceeded (tile pairs, entries or tall-row spans)"
+                                                  : "cache capacity exceeded");
     return GSC_OK;
 }
 
@@ -600,7 +605,7 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->n_evicted = k.n_evict;
     st->depth_used = k.depth_used;
     st->depth_next = k.depth;
-    st->overflow = (r.overflow & 1) | (k.overflow & 2);
+    st->overflow = ((r.overflow & 7) ? 1 : 0) | (k.overflow & 2);
     st->n_tall = r.n_tall;
     size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;

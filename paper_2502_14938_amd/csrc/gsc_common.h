@@ -51,8 +51,11 @@ struct RasterCounters {
     int32_t n_pairs;              // total tile pairs (all segments)
     int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
     int32_t n_chunks;             // chunks of 256 depth ranks (tall-entry lists)
-    int32_t n_tall;               // tall entries (more than 4 tile rows)
-    int32_t overflow;             // bit0: pair capacity
+    int32_t n_tall;               // tall entries (more than 4 tile rows) with tiles
+    int32_t n_echunks;            // chunks of 256 entries (preprocess tall lists)
+    int32_t n_tall_e;             // tall entries found by the preprocess
+    int32_t n_rows;               // their tile rows (stored spans)
+    int32_t overflow;             // bit0: pair capacity, bit1: entries, bit2: tall-row spans
     int32_t pad;
 };
 
@@ -155,6 +158,14 @@ struct Raster {
     int32_t* tall_cnt = nullptr;  // [max_entries / 256 + 1] tall entries per chunk of 256 ranks
     uint32_t* tall_off = nullptr; // [max_entries / 256 + 1] their exclusive prefix
     int32_t* tall_list = nullptr; // [max_entries] tall entries (ranks), dense
+    int32_t* pt_list = nullptr;   // [max_entries] tall entries (entry ids) in their chunk's slots
+    int32_t* pt_cnt = nullptr;    // [max_entries / 256 + 1] per chunk of entries
+    uint32_t* pt_off = nullptr;   // [max_entries / 256 + 1]
+    int32_t* pt_dense = nullptr;  // [max_entries] tall entries (entry ids), dense
+    uint32_t* pt_rowcnt = nullptr;  // [max_entries] tile rows of each
+    uint32_t* pt_rowoff = nullptr;  // [max_entries] first stored span of each
+    uint32_t* spans = nullptr;    // [span_cap] row spans of the tall footprints (lo | hi << 16)
+    int64_t span_cap = 0;
     uint32_t* ntiles = nullptr; // tile count per entry
     uint32_t* scnt = nullptr;   // tile count per depth rank
     int32_t* n_sort = nullptr;  // [1] pairs to sort (clamped to capacity)

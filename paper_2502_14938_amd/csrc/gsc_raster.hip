@@ -54,6 +54,7 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
         acc = (int32_t)max_entries;
     }
     rc->n_entries = acc;
+    rc->n_echunks = (acc + NT - 1) / NT;
 }
 
 // Minimum of q(d) = a dx^2 + 2 b dx dy + c dy^2 over the closed rectangle
@@ -214,13 +215,16 @@ struct PreArgs {
     uint32_t* ntiles;
     uint32_t* dkey;
     uint32_t* dval;
+    int32_t* tall_list;  // tall entries of each chunk of 256 entries, in the chunk's slots
+    int32_t* tall_cnt;   // per chunk
 };
 
 __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
+    __shared__ uint32_t s_wtall[NT / 64];
     const int64_t ne = p.rc->n_entries;
     const int lane = threadIdx.x & 63;
-    // block-uniform loop so that whole waves stay together for the
-    // cooperative counting of tall footprints
+    // block-uniform loop: each step covers one chunk of 256 entries, whose
+    // tall footprints the block lists together
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
         const int64_t e = base + threadIdx.x;
         const bool valid = e < ne;
@@ -304,23 +308,24 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
                 }
             }
         }
-        uint64_t big = __ballot(valid && y1 - y0 + 1 > kSmallRows);
-        while (big) {
-            const int src = __ffsll((long long)big) - 1;
-            big &= big - 1ull;
-            const Ellipse eb = shfl_ellipse(el, src);
-            const int by0 = __shfl(y0, src, 64), by1 = __shfl(y1, src, 64), bsi = __shfl(si, src, 64);
-            const Seg& s = p.tab.s[bsi];
-            uint32_t part = 0;
-            for (int yy = by0 + lane; yy <= by1; yy += 64) {
-                int lo, hi;
-                row_span(eb, yy, s.ntx, s.W, s.H, lo, hi);
-                part += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-            }
-            uint32_t tot;
-            wave_excl_scan(part, tot);
-            if (lane == src) count = tot;
+        // tall footprints (more than kSmallRows tile rows) are counted later,
+        // one thread per row (k_tall_rows); list them in this chunk's slots
+        const bool tall = valid && y1 - y0 + 1 > kSmallRows;
+        const uint64_t m = __ballot(tall);
+        if (lane == 0) s_wtall[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        __syncthreads();
+        const int64_t chunk = base / NT;
+        if (tall) {
+            uint32_t at = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            for (int q = 0; q < (int)(threadIdx.x >> 6); ++q) at += s_wtall[q];
+            p.tall_list[chunk * NT + at] = (int32_t)e;
         }
+        if (threadIdx.x == 0) {
+            uint32_t n = 0;
+            for (int q = 0; q < NT / 64; ++q) n += s_wtall[q];
+            p.tall_cnt[chunk] = (int32_t)n;
+        }
+        __syncthreads();  // s_wtall is rewritten by the next step
         if (valid) {
             rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
             p.rec[kRec * e] = A;
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
             p.rec[kRec * e + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
                                               __uint_as_float(spans[2]), __uint_as_float(spans[3]));
             p.ntiles[e] = count;
-            p.dkey[e] = count ? __float_as_uint(depth) : 0u;
+            p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
             p.dval[e] = (uint32_t)e;
         }
     }
@@ -365,6 +370,8 @@ struct DupArgs {
     uint64_t* key64;         // (global tile << 32 | depth bits) (full-key mode)
     uint32_t* val;           // entry id
     int64_t max_pairs;
+    const uint32_t* spans;   // row spans of the tall footprints
+    int64_t span_cap;
 };
 
 // Pair emission.  Every entry owns the output range [offs[r], offs[r] +
@@ -378,9 +385,9 @@ struct DupArgs {
 //                in their chunk's slots (the chunk of 256 ranks a block
 //                step covers, count per chunk; no atomics);
 //   k_dup_big    one wave per tall entry of the dense list (chunk lists
-//                joined by a scan of their counts): row spans recomputed one
-//                row per lane, and lanes stride along each row so the stores
-//                coalesce.
+//                joined by a scan of their counts): the row spans that
+//                k_tall_rows stored, then the entry's pairs written together,
+//                lane j taking pairs j, j + 64, ... (coalesced stores).
 template <bool kFull>
 __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t, uint32_t e, uint64_t low) {
     if (q >= d.max_pairs) return;
@@ -484,66 +491,130 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
 // Dense list of the tall entries: chunk c's entries at tall_off[c] + i.
 __global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ big_list,
                                                      const int32_t* __restrict__ tall_cnt,
-                                                     const uint32_t* __restrict__ tall_off, const RasterCounters* rc,
+                                                     const uint32_t* __restrict__ tall_off, const int32_t* n_chunks,
                                                      int32_t* __restrict__ tall_list) {
-    const int64_t nc = rc->n_chunks;
+    const int64_t nc = *n_chunks;
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x)
         if ((int32_t)threadIdx.x < tall_cnt[c]) tall_list[tall_off[c] + threadIdx.x] = big_list[c * NT + threadIdx.x];
 }
 
 template <bool kFull>
 __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_list) {
-    const int lane = threadIdx.x & 63;
+    __shared__ uint32_t s_ex[NT / 64][64];     // pairs before each of the wave's current 64 rows
+    __shared__ uint32_t s_first[NT / 64][64];  // global tile id of each row's first listed tile
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t nb = d.rc->n_tall;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t b = wave; b < nb; b += nwaves) {
-        {
-            const int64_t r = tall_list[b];
-            const uint32_t e = kFull ? (uint32_t)r : d.order[r];
-            const float4* rp = d.rec + kRec * (int64_t)e;
-            const float4 C = rp[2];
-            const uint32_t cnt = __float_as_uint(C.w);
-            const uint32_t rows = __float_as_uint(C.y);
-            const int y0 = rows & 0xffff, y1 = rows >> 16;
-            const Seg& s = d.tab.s[__float_as_uint(C.z)];
-            const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
-            const int64_t o = d.offs[r];
-            uint32_t run = 0;
-            if (y1 - y0 + 1 <= kSmallRows) {
-                const float4 D = rp[3];
-                const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
-                                                 __float_as_uint(D.w)};
-#pragma unroll
-                for (int i = 0; i < kSmallRows; ++i) {
-                    const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
-                    const uint32_t rowbase = (uint32_t)(s.tile_base + (y0 + i) * s.ntx);
-                    for (int xx = lo + lane; xx <= hi; xx += 64)
-                        put_pair<kFull>(d, o + run + (uint32_t)(xx - lo), rowbase + (uint32_t)xx, e, low);
-                    run += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-                }
-            } else {
-                const float4 A = rp[0], B = rp[1];
-                const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
-                for (int chunk = y0; chunk <= y1; chunk += 64) {
-                    int lo = 0, hi = -1;
-                    if (chunk + lane <= y1) row_span(el, chunk + lane, s.ntx, s.W, s.H, lo, hi);
-                    uint32_t n_row = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot;
-                    const uint32_t ex = wave_excl_scan(n_row, tot);
-                    const int nr = min(64, y1 - chunk + 1);
-                    for (int rr = 0; rr < nr; ++rr) {
-                        const int rlo = __shfl(lo, rr, 64), rhi = __shfl(hi, rr, 64);
-                        const uint32_t rex = (uint32_t)__shfl((int)ex, rr, 64);
-                        const uint32_t rowbase = (uint32_t)(s.tile_base + (chunk + rr) * s.ntx);
-                        for (int xx = rlo + lane; xx <= rhi; xx += 64) {
-                            const uint32_t w = run + rex + (uint32_t)(xx - rlo);
-                            if (w < cnt) put_pair<kFull>(d, o + w, rowbase + (uint32_t)xx, e, low);
-                        }
-                    }
-                    run += tot;
-                }
+        const int64_t r = tall_list[b];
+        const uint32_t e = kFull ? (uint32_t)r : d.order[r];
+        const float4* rp = d.rec + kRec * (int64_t)e;
+        const float4 C = rp[2];
+        const uint32_t cnt = __float_as_uint(C.w);
+        const uint32_t rows = __float_as_uint(C.y);
+        const int y0 = rows & 0xffff, y1 = rows >> 16;
+        const Seg& s = d.tab.s[__float_as_uint(C.z)];
+        const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
+        const int64_t o = d.offs[r];
+        const int64_t sp0 = __float_as_uint(rp[3].x);  // first stored span (k_tall_count)
+        uint32_t run = 0;
+        for (int chunk = y0; chunk <= y1; chunk += 64) {
+            // one row per lane: its stored span, then the rows' pair prefix
+            int lo = 0, hi = -1;
+            const int64_t q = sp0 + (chunk - y0) + lane;
+            if (chunk + lane <= y1 && q < d.span_cap) {
+                const uint32_t sp = d.spans[q];
+                lo = sp & 0xffff;
+                hi = sp >> 16;
             }
+            uint32_t tot;
+            const uint32_t ex = wave_excl_scan(hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
+            s_ex[w][lane] = ex;
+            s_first[w][lane] = (uint32_t)(s.tile_base + (chunk + lane) * s.ntx + lo);
+            __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
+            // the rows' pairs together: lane j takes pairs j, j + 64, ... and
+            // finds its row as the last one whose prefix is <= j (rows without
+            // pairs share the next row's prefix, so the last one has pairs)
+            for (uint32_t j = lane; j < tot; j += 64) {
+                int lo2 = 0, hi2 = 63;
+                while (lo2 < hi2) {
+                    const int mid = (lo2 + hi2 + 1) >> 1;
+                    if (s_ex[w][mid] <= j) lo2 = mid;
+                    else hi2 = mid - 1;
+                }
+                const uint32_t wpos = run + j;
+                if (wpos < cnt) put_pair<kFull>(d, o + wpos, s_first[w][lo2] + (j - s_ex[w][lo2]), e, low);
+            }
+            __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
+            run += tot;
         }
+    }
+}
+
+// Rows of each tall footprint (dense list of entries), for the span offsets.
+__global__ __launch_bounds__(NT) void k_tall_rowcnt(const int32_t* __restrict__ tall_e, const float4* __restrict__ rec,
+                                                    const int32_t* n_tall, uint32_t* __restrict__ rowcnt) {
+    const int64_t n = *n_tall;
+    for (int64_t i = gtid(); i < n; i += gstride()) {
+        const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)tall_e[i] + 2].y);
+        rowcnt[i] = (rows >> 16) - (rows & 0xffff) + 1;
+    }
+}
+
+// One thread per row of every tall footprint: its exact tile span, stored as
+// lo | hi << 16 (hi < lo: empty).  The footprint of row q is the last one
+// whose first row is <= q.
+__global__ __launch_bounds__(NT) void k_tall_rows(SegTable tab, const int32_t* __restrict__ tall_e,
+                                                  const uint32_t* __restrict__ rowoff, const float4* __restrict__ rec,
+                                                  RasterCounters* rc, uint32_t* __restrict__ spans, int64_t cap) {
+    const int64_t nt = rc->n_tall_e;
+    int64_t nr = rc->n_rows;
+    if (nr > cap) {
+        if (gtid() == 0) rc->overflow |= 4;
+        nr = cap;
+    }
+    for (int64_t q = gtid(); q < nr; q += gstride()) {
+        int64_t lo = 0, hi = nt - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if ((int64_t)rowoff[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const float4* rp = rec + kRec * (int64_t)tall_e[lo];
+        const float4 A = rp[0], B = rp[1], C = rp[2];
+        const uint32_t rows = __float_as_uint(C.y);
+        const Seg& s = tab.s[__float_as_uint(C.z)];
+        const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
+        int slo, shi;
+        row_span(el, (int)(rows & 0xffff) + (int)(q - (int64_t)rowoff[lo]), s.ntx, s.W, s.H, slo, shi);
+        spans[q] = shi >= slo ? ((uint32_t)slo | ((uint32_t)shi << 16)) : 0x0000ffffu;
+    }
+}
+
+// One thread per tall footprint: its tile count from the stored spans; the
+// record keeps the offset of its first span (in the spans slot D.x) for
+// the emission.
+__global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ tall_e, const uint32_t* __restrict__ rowoff,
+                                                   const uint32_t* __restrict__ rowcnt,
+                                                   const uint32_t* __restrict__ spans, const RasterCounters* rc,
+                                                   int64_t cap, float4* __restrict__ rec, uint32_t* __restrict__ ntiles,
+                                                   uint32_t* __restrict__ dkey) {
+    const int64_t n = rc->n_tall_e;
+    for (int64_t i = gtid(); i < n; i += gstride()) {
+        const int64_t e = tall_e[i];
+        const int64_t r0 = rowoff[i], r1 = r0 + rowcnt[i] < cap ? r0 + rowcnt[i] : cap;
+        uint32_t count = 0;
+        for (int64_t q = r0; q < r1; ++q) {
+            const uint32_t sp = spans[q];
+            const int lo = sp & 0xffff, hi = sp >> 16;
+            count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+        }
+        float4* rp = rec + kRec * e;
+        rp[2].w = __uint_as_float(count);
+        rp[3].x = __uint_as_float((uint32_t)r0);
+        ntiles[e] = count;
+        if (!count) dkey[e] = 0u;
     }
 }
 
@@ -767,14 +838,35 @@ void seg_camera(Seg& s, const gsc_camera& c) {
     s.nty = (c.height + kTile - 1) / kTile;
 }
 
+// Tall footprints (more than kSmallRows tile rows): dense list of the
+// entries k_preprocess listed per chunk, offsets of their rows, one thread
+// per row for the exact spans, then each footprint's count.
+hipError_t tall_spans(const SegTable& tab, Raster& r, hipStream_t st) {
+    RasterCounters* rc = r.cnt;
+    hipError_t e = scan_u32(reinterpret_cast<const uint32_t*>(r.pt_cnt), r.pt_off, &rc->n_echunks, 0, &rc->n_tall_e,
+                            r.block_sums, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.pt_list, r.pt_cnt, r.pt_off,
+                       &rc->n_echunks, r.pt_dense);
+    hipLaunchKernelGGL(k_tall_rowcnt, grid_fit(k_tall_rowcnt, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.rec,
+                       &rc->n_tall_e, r.pt_rowcnt);
+    e = scan_u32(r.pt_rowcnt, r.pt_rowoff, &rc->n_tall_e, 0, &rc->n_rows, r.block_sums, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tall_rows, grid_fit(k_tall_rows, r.span_cap), dim3(NT), 0, st, tab, r.pt_dense, r.pt_rowoff,
+                       r.rec, rc, r.spans, r.span_cap);
+    hipLaunchKernelGGL(k_tall_count, grid_fit(k_tall_count, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.pt_rowoff,
+                       r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles, r.dkey[0]);
+    return hipGetLastError();
+}
+
 // Offsets of the chunks' tall entries and their dense list.
 hipError_t tall_list(Raster& r, hipStream_t st) {
     RasterCounters* rc = r.cnt;
     hipError_t e = scan_u32(reinterpret_cast<const uint32_t*>(r.tall_cnt), r.tall_off, &rc->n_chunks, 0, &rc->n_tall,
                             r.block_sums, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.big_list, r.tall_cnt, r.tall_off, rc,
-                       r.tall_list);
+    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.big_list, r.tall_cnt, r.tall_off,
+                       &rc->n_chunks, r.tall_list);
     return hipGetLastError();
 }
 
@@ -785,11 +877,15 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
     PreArgs pa;
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
+    pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt;
     hipLaunchKernelGGL(k_preprocess, grid_fit(k_preprocess, r.max_entries), dim3(NT), 0, st, pa);
+    hipError_t e0 = tall_spans(tab, r, st);
+    if (e0 != hipSuccess) return e0;
     mark(mk, 4, st);
     const int tile_bits = bits_for(tab.total_tiles);
     DupArgs da;
     da.tab = tab; da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
+    da.spans = r.spans; da.span_cap = r.span_cap;
     hipError_t e;
     if (!full_key_sort) {
         // low 32 key bits (depth) first, per Gaussian

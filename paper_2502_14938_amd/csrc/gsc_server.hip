@@ -111,7 +111,7 @@ void on_batch_done(void* p) {
     gsc_server* s = b->s;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        const bool pairs_over = (b->rep->rc.overflow & 3) != 0;
+        const bool pairs_over = (b->rep->rc.overflow & 7) != 0;
         for (size_t i = 0; i < b->ids.size(); ++i) {
             const bool cache_over = (b->rep->vc[b->viewer_of[i]].overflow & 2) != 0;
             s->done.push_back({b->ids[i], t, (pairs_over || cache_over) ? GSC_E_CAPACITY : GSC_OK});
