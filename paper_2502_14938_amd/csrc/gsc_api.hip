@@ -156,7 +156,7 @@ hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int6
     A_(r.tall_list, max_entries);
     A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
     A_(r.pt_dense, max_entries); A_(r.pt_rowcnt, max_entries); A_(r.pt_rowoff, max_entries);
-    A_(r.spans, 2 * max_entries);
+    A_(r.spans, 2 * max_entries); A_(r.rowmap, 2 * max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
@@ -600,8 +600,18 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->n_visible = k.n_visible;
     st->n_miss = k.n_miss;
     st->n_gauss = k.n_gauss;
-    st->n_pairs[0] = r.seg_pairs[0];
-    st->n_pairs[1] = r.seg_pairs[1];
+    if (c->rendered && !c->explicit_render && c->last_tab.total_tiles > 0) {
+        // pairs per eye: the lengths of its tiles' runs
+        std::vector<int32_t> rg(2 * (size_t)c->last_tab.total_tiles);
+        HIP_OR_FAIL(c, hipMemcpy(rg.data(), c->raster.ranges, rg.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int sg = 0; sg < c->last_tab.n && sg < 2; ++sg) {
+            const Seg& g = c->last_tab.s[sg];
+            int64_t n = 0;
+            for (int t = 0; t < g.ntx * g.nty; ++t)
+                n += rg[2 * (size_t)(g.tile_base + t) + 1] - rg[2 * (size_t)(g.tile_base + t)];
+            st->n_pairs[sg] = n;
+        }
+    }
     st->n_evicted = k.n_evict;
     st->depth_used = k.depth_used;
     st->depth_next = k.depth;

@@ -49,7 +49,6 @@ struct RasterCounters {
     int32_t n_entries;            // total (segment, Gaussian) entries
     int32_t entry_base[kMaxSeg + 1];
     int32_t n_pairs;              // total tile pairs (all segments)
-    int32_t seg_pairs[kMaxSeg];   // pairs per segment (stats)
     int32_t n_chunks;             // chunks of 256 depth ranks (tall-entry lists)
     int32_t n_tall;               // tall entries (more than 4 tile rows) with tiles
     int32_t n_echunks;            // chunks of 256 entries (preprocess tall lists)
@@ -165,6 +164,7 @@ struct Raster {
     uint32_t* pt_rowcnt = nullptr;  // [max_entries] tile rows of each
     uint32_t* pt_rowoff = nullptr;  // [max_entries] first stored span of each
     uint32_t* spans = nullptr;    // [span_cap] row spans of the tall footprints (lo | hi << 16)
+    int32_t* rowmap = nullptr;    // [span_cap] footprint (dense index) of each stored span
     int64_t span_cap = 0;
     uint32_t* ntiles = nullptr; // tile count per entry
     uint32_t* scnt = nullptr;   // tile count per depth rank

@@ -4,7 +4,7 @@
 //                                   hit/miss, learned staleness, slot
 //                                   allocation, eviction of outdated lines)
 //   decode new anchors           -> derive_mfma (eq. 3, eq. 2; matrix cores)
-//   configure the cache depth    -> k_depth_update (eq. 4, linear guide)
+//   configure the cache depth    -> depth_update (eq. 4, linear guide), in k_compose_count
 //   update the render buffer     -> k_compose_* (opacity mask, Section 6)
 // Every count stays on the device (Counters); the host only enqueues.
 #include <cmath>
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_nocache(const int32_t* __restrict__ visi
 }
 
 // Eq. 4 with the linear guiding function on the update (miss) rate.
-__global__ void k_depth_update(Counters* cnt, int32_t dmax, int32_t guide) {
+__device__ __forceinline__ void depth_update(Counters* cnt, int32_t dmax, int32_t guide) {
     int32_t nx = cnt->n_visible, nm = cnt->n_miss;
     cnt->depth_used = cnt->depth;
     if (guide == GSC_GUIDE_FIXED) {
@@ -309,11 +309,16 @@ __global__ void k_depth_update(Counters* cnt, int32_t dmax, int32_t guide) {
     cnt->depth = (int32_t)(d < 1 ? 1 : (d > dmax ? dmax : d));
 }
 
-__global__ void k_frame_begin(Counters* cnt) {
-    cnt->n_cand = 0;
-    cnt->overflow = 0;
-    cnt->n_evict = 0;
-    cnt->evict_short = 0;
+// Per-frame counters reset, and the unified camera centre of frame t kept
+// for the reuse features of later frames (one block of 64 threads).
+__global__ void k_frame_begin(Counters* cnt, float* pu_hist, int32_t t, DeriveCam cam) {
+    if (threadIdx.x == 0) {
+        cnt->n_cand = 0;
+        cnt->overflow = 0;
+        cnt->n_evict = 0;
+        cnt->evict_short = 0;
+    }
+    if (threadIdx.x < 3) pu_hist[4 * (t & 63) + threadIdx.x] = cam.pos[threadIdx.x];
 }
 
 __global__ void k_evict_freescan_n(const Counters* cnt, int32_t* scan_n, int64_t C) {
@@ -330,15 +335,14 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-__global__ void k_store_pu(float* pu_hist, int32_t t, DeriveCam cam) {
-    if (threadIdx.x < 3) pu_hist[4 * (t & 63) + threadIdx.x] = cam.pos[threadIdx.x];
-}
 
 // ------------------------------------------------------------- compose
 // G_t = [(i, j) : i visible ascending, j ascending, alpha_ij > 0]; each entry
 // is the cache entry (line * k + j).
 __global__ __launch_bounds__(NT) void k_compose_count(const int32_t* __restrict__ vslot, const float4* __restrict__ L0,
-                                                      int k, Counters* cnt, uint32_t* __restrict__ count) {
+                                                      int k, Counters* cnt, uint32_t* __restrict__ count,
+                                                      int32_t dmax, int32_t guide) {
+    if (gtid() == 0) depth_update(cnt, dmax, guide);  // eq. 4, from this frame's counts
     int32_t nv = cnt->n_visible;
     for (int64_t i = gtid(); i < nv; i += gstride()) {
         if (vslot[i] < 0) {  // anchor left without a line (capacity overflow)
@@ -381,8 +385,7 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     const int32_t t = (int32_t)v.t;
     Counters* cnt = v.cnt;
     mark(mk, 0, st);
-    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(1), 0, st, cnt);
-    hipLaunchKernelGGL(k_store_pu, dim3(1), dim3(64), 0, st, v.pu_hist, t, a.cam);
+    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(64), 0, st, cnt, v.pu_hist, t, a.cam);
     // anchor indexing and filtering -> X_t ascending
     hipLaunchKernelGGL(k_select_flags, grid_fit(k_select_flags, n), dim3(NT), 0, st, sc.posr, sc.level, n, a.cam, v.tmp_a);
     GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, nullptr, n, &cnt->n_visible, v.block_sums, st));
@@ -458,9 +461,9 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
         GSC_TRY(derive_mfma(m, n, st));
     }
     mark(mk, 2, st);
-    hipLaunchKernelGGL(k_depth_update, dim3(1), dim3(1), 0, st, cnt, a.d_max, a.guide);
     // compose the render buffer
-    hipLaunchKernelGGL(k_compose_count, grid_fit(k_compose_count, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_a);
+    hipLaunchKernelGGL(k_compose_count, grid_fit(k_compose_count, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_a,
+                       a.d_max, a.guide);
     GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_gauss, v.block_sums, st));
     hipLaunchKernelGGL(k_compose_write, grid_fit(k_compose_write, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_b, v.G);
     mark(mk, 3, st);

@@ -45,7 +45,6 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
         rc->entry_base[s] = acc;
         int32_t n = tab.s[s].nG ? *tab.s[s].nG : tab.s[s].nG_host;
         acc += n;
-        rc->seg_pairs[s] = 0;
     }
     rc->entry_base[tab.n] = acc;
     rc->overflow = 0;
@@ -217,10 +216,13 @@ struct PreArgs {
     uint32_t* dval;
     int32_t* tall_list;  // tall entries of each chunk of 256 entries, in the chunk's slots
     int32_t* tall_cnt;   // per chunk
+    int32_t* ranges;     // [2 * tiles] cleared here for this batch's ranges
+    int64_t n_ranges;
 };
 
 __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
     __shared__ uint32_t s_wtall[NT / 64];
+    for (int64_t i = gtid(); i < p.n_ranges; i += gstride()) p.ranges[i] = 0;
     const int64_t ne = p.rc->n_entries;
     const int lane = threadIdx.x & 63;
     // block-uniform loop: each step covers one chunk of 256 entries, whose
@@ -370,6 +372,7 @@ struct DupArgs {
     uint64_t* key64;         // (global tile << 32 | depth bits) (full-key mode)
     uint32_t* val;           // entry id
     int64_t max_pairs;
+    int32_t* n_sort;         // pairs to sort (set by k_dup_rows)
     const uint32_t* spans;   // row spans of the tall footprints
     int64_t span_cap;
 };
@@ -396,6 +399,18 @@ __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t
     d.val[q] = e;
 }
 
+// Pairs to sort (clamped to the capacity; overflow flagged) and the chunk
+// count of the emission's tall lists; run by one thread of k_dup_rows.
+__device__ __forceinline__ void pairs_clamp(RasterCounters* rc, int32_t* n_sort, int64_t max_pairs) {
+    rc->n_chunks = (rc->n_entries + NT - 1) / NT;
+    int32_t n = rc->n_pairs;
+    if ((int64_t)n > max_pairs) {
+        rc->overflow |= 1;
+        n = (int32_t)max_pairs;
+    }
+    *n_sort = n;
+}
+
 template <bool kFull>
 __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict__ big_list,
                                                  int32_t* __restrict__ tall_cnt) {
@@ -407,6 +422,7 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
     __shared__ uint32_t s_e[NT];      // entry id
     __shared__ uint32_t s_low[NT];    // depth bits (full-key mode)
     __shared__ uint32_t s_wtall[NT / 64];
+    if (blockIdx.x == 0 && threadIdx.x == 0) pairs_clamp(d.rc, d.n_sort, d.max_pairs);
     const int64_t ne = d.rc->n_entries;
     const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
@@ -488,14 +504,34 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
     }
 }
 
-// Dense list of the tall entries: chunk c's entries at tall_off[c] + i.
+// Dense list of the tall entries: chunk c's entries at tall_off[c] + i;
+// with rowcnt, also the tile rows of each (entry ids listed).
 __global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ big_list,
                                                      const int32_t* __restrict__ tall_cnt,
                                                      const uint32_t* __restrict__ tall_off, const int32_t* n_chunks,
-                                                     int32_t* __restrict__ tall_list) {
+                                                     int32_t* __restrict__ tall_list, const float4* __restrict__ rec,
+                                                     uint32_t* __restrict__ rowcnt) {
     const int64_t nc = *n_chunks;
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x)
-        if ((int32_t)threadIdx.x < tall_cnt[c]) tall_list[tall_off[c] + threadIdx.x] = big_list[c * NT + threadIdx.x];
+        if ((int32_t)threadIdx.x < tall_cnt[c]) {
+            const int32_t x = big_list[c * NT + threadIdx.x];
+            tall_list[tall_off[c] + threadIdx.x] = x;
+            if (rowcnt) {
+                const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)x + 2].y);
+                rowcnt[tall_off[c] + threadIdx.x] = (rows >> 16) - (rows & 0xffff) + 1;
+            }
+        }
+}
+
+// Footprint (dense index) of every stored row span.
+__global__ __launch_bounds__(NT) void k_tall_rowmap(const uint32_t* __restrict__ rowoff,
+                                                    const uint32_t* __restrict__ rowcnt, const RasterCounters* rc,
+                                                    int64_t cap, int32_t* __restrict__ rowmap) {
+    const int64_t n = rc->n_tall_e;
+    for (int64_t i = gtid(); i < n; i += gstride()) {
+        const int64_t r0 = rowoff[i], r1 = r0 + rowcnt[i] < cap ? r0 + rowcnt[i] : cap;
+        for (int64_t q = r0; q < r1; ++q) rowmap[q] = (int32_t)i;
+    }
 }
 
 template <bool kFull>
@@ -552,35 +588,19 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
     }
 }
 
-// Rows of each tall footprint (dense list of entries), for the span offsets.
-__global__ __launch_bounds__(NT) void k_tall_rowcnt(const int32_t* __restrict__ tall_e, const float4* __restrict__ rec,
-                                                    const int32_t* n_tall, uint32_t* __restrict__ rowcnt) {
-    const int64_t n = *n_tall;
-    for (int64_t i = gtid(); i < n; i += gstride()) {
-        const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)tall_e[i] + 2].y);
-        rowcnt[i] = (rows >> 16) - (rows & 0xffff) + 1;
-    }
-}
-
 // One thread per row of every tall footprint: its exact tile span, stored as
-// lo | hi << 16 (hi < lo: empty).  The footprint of row q is the last one
-// whose first row is <= q.
+// lo | hi << 16 (hi < lo: empty).
 __global__ __launch_bounds__(NT) void k_tall_rows(SegTable tab, const int32_t* __restrict__ tall_e,
-                                                  const uint32_t* __restrict__ rowoff, const float4* __restrict__ rec,
-                                                  RasterCounters* rc, uint32_t* __restrict__ spans, int64_t cap) {
-    const int64_t nt = rc->n_tall_e;
+                                                  const uint32_t* __restrict__ rowoff, const int32_t* __restrict__ rowmap,
+                                                  const float4* __restrict__ rec, RasterCounters* rc,
+                                                  uint32_t* __restrict__ spans, int64_t cap) {
     int64_t nr = rc->n_rows;
     if (nr > cap) {
         if (gtid() == 0) rc->overflow |= 4;
         nr = cap;
     }
     for (int64_t q = gtid(); q < nr; q += gstride()) {
-        int64_t lo = 0, hi = nt - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if ((int64_t)rowoff[mid] <= q) lo = mid;
-            else hi = mid - 1;
-        }
+        const int64_t lo = rowmap[q];
         const float4* rp = rec + kRec * (int64_t)tall_e[lo];
         const float4 A = rp[0], B = rp[1], C = rp[2];
         const uint32_t rows = __float_as_uint(C.y);
@@ -618,19 +638,7 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
     }
 }
 
-__global__ void k_pairs_clamp(RasterCounters* rc, int32_t* n_sort, int64_t max_pairs) {
-    rc->n_chunks = (rc->n_entries + NT - 1) / NT;
-    int32_t n = rc->n_pairs;
-    if ((int64_t)n > max_pairs) {
-        rc->overflow |= 1;
-        n = (int32_t)max_pairs;
-    }
-    *n_sort = n;
-}
 
-__global__ __launch_bounds__(NT) void k_fill_ranges(int32_t* __restrict__ ranges, int64_t n2) {
-    for (int64_t i = gtid(); i < n2; i += gstride()) ranges[i] = 0;
-}
 
 // Each thread scans 8 consecutive sorted keys (plus one neighbour on each
 // side), so every load of a step is issued before any comparison.
@@ -657,21 +665,6 @@ __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const
     }
 }
 
-// Per-segment pair counts (stats): one block per segment sums its tiles' runs.
-__global__ __launch_bounds__(NT) void k_seg_pairs(const int32_t* __restrict__ ranges, SegTable tab, RasterCounters* rc) {
-    __shared__ int32_t part[NT];
-    const Seg& g = tab.s[blockIdx.x];
-    int64_t t0 = g.tile_base, t1 = g.tile_base + (int64_t)g.ntx * g.nty;
-    int32_t acc = 0;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) acc += ranges[2 * t + 1] - ranges[2 * t];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) rc->seg_pairs[blockIdx.x] = part[0];
-}
 
 // One block per global tile; block -> tile mapping keeps runs of adjacent
 // tiles on one XCD (blocks are dealt round-robin over the 8 XCDs) so that
@@ -847,13 +840,13 @@ hipError_t tall_spans(const SegTable& tab, Raster& r, hipStream_t st) {
                             r.block_sums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.pt_list, r.pt_cnt, r.pt_off,
-                       &rc->n_echunks, r.pt_dense);
-    hipLaunchKernelGGL(k_tall_rowcnt, grid_fit(k_tall_rowcnt, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.rec,
-                       &rc->n_tall_e, r.pt_rowcnt);
+                       &rc->n_echunks, r.pt_dense, r.rec, r.pt_rowcnt);
     e = scan_u32(r.pt_rowcnt, r.pt_rowoff, &rc->n_tall_e, 0, &rc->n_rows, r.block_sums, st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tall_rowmap, grid_fit(k_tall_rowmap, r.max_entries), dim3(NT), 0, st, r.pt_rowoff,
+                       r.pt_rowcnt, rc, r.span_cap, r.rowmap);
     hipLaunchKernelGGL(k_tall_rows, grid_fit(k_tall_rows, r.span_cap), dim3(NT), 0, st, tab, r.pt_dense, r.pt_rowoff,
-                       r.rec, rc, r.spans, r.span_cap);
+                       r.rowmap, r.rec, rc, r.spans, r.span_cap);
     hipLaunchKernelGGL(k_tall_count, grid_fit(k_tall_count, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.pt_rowoff,
                        r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles, r.dkey[0]);
     return hipGetLastError();
@@ -866,7 +859,7 @@ hipError_t tall_list(Raster& r, hipStream_t st) {
                             r.block_sums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.big_list, r.tall_cnt, r.tall_off,
-                       &rc->n_chunks, r.tall_list);
+                       &rc->n_chunks, r.tall_list, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -877,7 +870,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
     PreArgs pa;
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
-    pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt;
+    pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_tiles;
     hipLaunchKernelGGL(k_preprocess, grid_fit(k_preprocess, r.max_entries), dim3(NT), 0, st, pa);
     hipError_t e0 = tall_spans(tab, r, st);
     if (e0 != hipSuccess) return e0;
@@ -885,7 +878,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     const int tile_bits = bits_for(tab.total_tiles);
     DupArgs da;
     da.tab = tab; da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
-    da.spans = r.spans; da.span_cap = r.span_cap;
+    da.spans = r.spans; da.span_cap = r.span_cap; da.n_sort = r.n_sort;
     hipError_t e;
     if (!full_key_sort) {
         // low 32 key bits (depth) first, per Gaussian
@@ -897,7 +890,6 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
                            rc, r.scnt);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         mark(mk, 6, st);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
         hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
@@ -912,14 +904,12 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_fill_ranges, grid_fit(k_fill_ranges, 2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
         hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
                            r.ranges, (uint32_t)tab.total_tiles);
     } else {
         mark(mk, 5, st);  // no per-Gaussian depth pass in this mode
         e = scan_u32(r.ntiles, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_pairs_clamp, dim3(1), dim3(1), 0, st, rc, r.n_sort, r.max_pairs);
         mark(mk, 6, st);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
         hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
@@ -933,12 +923,10 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_fill_ranges, grid_fit(k_fill_ranges, 2 * r.max_tiles), dim3(NT), 0, st, r.ranges, 2 * (int64_t)tab.total_tiles);
         hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
                            32, r.ranges, (uint32_t)tab.total_tiles);
     }
     r.order = nullptr;
-    hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)tab.n), dim3(NT), 0, st, r.ranges, tab, rc);
     mark(mk, 10, st);
     if (count_work)
         hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,

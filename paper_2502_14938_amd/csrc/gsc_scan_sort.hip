@@ -69,34 +69,19 @@ __global__ __launch_bounds__(NT) void k_scan_reduce(const uint32_t* __restrict__
     if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
 }
 
-// One block scans the per-block sums (nb <= 4 * NT).
-__global__ __launch_bounds__(NT) void k_scan_top(uint32_t* __restrict__ block_sums, int nb, int32_t* total) {
-    __shared__ uint32_t wsum[NT / 64];
-    uint32_t v[4], s = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int i = threadIdx.x * 4 + r;
-        v[r] = i < nb ? block_sums[i] : 0u;
-        s += v[r];
-    }
-    uint32_t tot;
-    uint32_t e = block_excl_scan(s, wsum, tot);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int i = threadIdx.x * 4 + r;
-        if (i < nb) block_sums[i] = e;
-        e += v[r];
-    }
-    if (threadIdx.x == 0 && total) *total = (int32_t)tot;
-}
-
+// Each block takes its carry as the sum of the preceding blocks' sums (at
+// most kScanBlocks values, a block reduction), so no separate pass over the
+// block sums is needed; the last block writes the total.
 __global__ __launch_bounds__(NT) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                   const int32_t* n_dev, int64_t n_host,
-                                                  const uint32_t* __restrict__ block_sums) {
+                                                  const uint32_t* __restrict__ block_sums, int32_t* total) {
     __shared__ uint32_t wsum[NT / 64];
+    uint32_t part = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += NT) part += block_sums[i];
+    uint32_t carry = block_sum(part, wsum);
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = (int32_t)(carry + block_sums[blockIdx.x]);
     int64_t b0, b1;
     chunk_of(count_of(n_dev, n_host), SCAN_TILE, b0, b1);
-    uint32_t carry = block_sums[blockIdx.x];
     for (int64_t base = b0; base < b1; base += SCAN_TILE) {
         uint32_t v[4], s = 0;
         int64_t i0 = base + threadIdx.x * 4;
@@ -274,8 +259,7 @@ hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, 
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int64_t n_host, int32_t* total,
                     uint32_t* block_sums, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(NT), 0, st, in, n_dev, n_host, block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(NT), 0, st, block_sums, kScanBlocks, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(NT), 0, st, in, out, n_dev, n_host, block_sums);
+    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(NT), 0, st, in, out, n_dev, n_host, block_sums, total);
     return hipGetLastError();
 }
 
