@@ -108,54 +108,82 @@ __device__ __forceinline__ uint32_t digit(K key, int shift, uint32_t mask) {
     return (uint32_t)(key >> shift) & mask;
 }
 
-// Lanes of the wave holding the same digit (among `active`), from one
-// ballot per digit bit.
-__device__ __forceinline__ uint64_t peers_of(uint32_t d, bool valid, int bits) {
+// Lanes of the wave holding the same BITS-bit digit (among the valid ones),
+// from one ballot per digit bit.
+template <int BITS>
+__device__ __forceinline__ uint64_t peers_of(uint32_t d, bool valid) {
     uint64_t m = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-        bool bit = (d >> b) & 1u;
-        uint64_t bb = __ballot(bit);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
         m &= bit ? bb : ~bb;
     }
     return m;
 }
 
+// SORT_IPT consecutive keys starting at a 16-byte aligned element.
+template <typename K>
+__device__ __forceinline__ void load_run(const K* __restrict__ p, K (&k)[SORT_IPT]) {
+    constexpr int NV = SORT_IPT * (int)sizeof(K) / 16;
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint4 v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = q[j];
+    __builtin_memcpy(k, v, sizeof(v));
+}
+
+// Digit counts of the block's chunk.  Each thread takes SORT_IPT
+// consecutive keys and adds each run of equal digits in one update of its
+// wave's LDS counters, so keys that come in runs (the tile ids of one
+// footprint row, the high digits of nearby depths) cost one update per run.
 template <typename K>
 __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ keys, const int32_t* n_dev, int64_t n_host,
                                                    int shift, int bits, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[4][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6;
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
     for (int i = threadIdx.x; i < 4 * 256; i += NT) (&h[0][0])[i] = 0u;
     __syncthreads();
     int64_t b0, b1;
     chunk_of(count_of(n_dev, n_host), SORT_TILE, b0, b1);
-    const uint64_t lt = (1ull << lane) - 1ull;
     for (int64_t base = b0; base < b1; base += SORT_TILE) {
-        // issue every load of the step before any ranking work
-        uint32_t d[SORT_IPT];
+        const int64_t i0 = base + (int64_t)threadIdx.x * SORT_IPT;
+        const int m = i0 >= b1 ? 0 : (b1 - i0 < SORT_IPT ? (int)(b1 - i0) : SORT_IPT);
+        K k[SORT_IPT];
+        if (m == SORT_IPT) {
+            load_run(keys + i0, k);
+        } else {
 #pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            int64_t i = base + r * NT + threadIdx.x;
-            d[r] = i < b1 ? digit(keys[i], shift, mask) : 0xffffffffu;
+            for (int r = 0; r < SORT_IPT; ++r) k[r] = r < m ? keys[i0 + r] : (K)0;
         }
+        if (m == 0) continue;
+        uint32_t cur = digit(k[0], shift, mask), run = 1u;
 #pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            bool valid = d[r] != 0xffffffffu;
-            uint64_t peers = peers_of(valid ? d[r] : 0u, valid, bits);
-            if (valid && (peers & lt) == 0ull) atomicAdd(&h[w][d[r]], (uint32_t)__popcll(peers));
+        for (int r = 1; r < SORT_IPT; ++r) {
+            if (r < m) {
+                const uint32_t d = digit(k[r], shift, mask);
+                if (d != cur) {
+                    atomicAdd(&h[w][cur], run);
+                    cur = d;
+                    run = 0u;
+                }
+                ++run;
+            }
         }
+        atomicAdd(&h[w][cur], run);
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < nbins; q += NT)
         hist[(int64_t)q * gridDim.x + blockIdx.x] = h[0][q] + h[1][q] + h[2][q] + h[3][q];
 }
 
-template <typename K>
+template <typename K, int BITS>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                      const int32_t* n_dev, int64_t n_host, int shift, int bits,
+                                                      const int32_t* n_dev, int64_t n_host, int shift,
                                                       const uint32_t* __restrict__ offs) {
+    constexpr int bits = BITS;
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t texcl[256];
@@ -187,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
         for (int r = 0; r < SORT_IPT; ++r) {
             bool valid = dg[r] != 0xffffffffu;
             uint32_t d = valid ? dg[r] : 0u;
-            uint64_t peers = peers_of(d, valid, bits);
+            uint64_t peers = peers_of<BITS>(d, valid);
             // every peer reads the wave's running count before the group's
             // first lane advances it (one wave, in-order LDS accesses)
             uint32_t c = valid ? cnt[w][d] : 0u;
@@ -237,6 +265,25 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
 }
 
 template <typename K>
+void launch_scatter(int bits, const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, const int32_t* n_dev,
+                    int64_t n_host, int shift, const uint32_t* offs, hipStream_t st) {
+#define GSC_SCATTER(B)                                                                                           \
+    hipLaunchKernelGGL((k_radix_scatter<K, B>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, n_dev, \
+                       n_host, shift, offs)
+    switch (bits) {
+        case 1: GSC_SCATTER(1); break;
+        case 2: GSC_SCATTER(2); break;
+        case 3: GSC_SCATTER(3); break;
+        case 4: GSC_SCATTER(4); break;
+        case 5: GSC_SCATTER(5); break;
+        case 6: GSC_SCATTER(6); break;
+        case 7: GSC_SCATTER(7); break;
+        default: GSC_SCATTER(8); break;
+    }
+#undef GSC_SCATTER
+}
+
+template <typename K>
 hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0, int bit1,
                            uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
     int cur = 0;
@@ -246,8 +293,7 @@ hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, 
                            bits, hist);
         hipError_t e = scan_u32(hist, hist, nullptr, (int64_t)(1 << bits) * kSortBlocks, nullptr, block_sums, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(kSortBlocks), dim3(NT), 0, st, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n_dev, n_host, shift, bits, hist);
+        launch_scatter<K>(bits, keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, n_host, shift, hist, st);
         cur ^= 1;
     }
     *which = cur;
