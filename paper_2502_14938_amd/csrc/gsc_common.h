@@ -15,6 +15,7 @@ namespace gsc {
 constexpr int kTile = 16;             // 16x16 pixel tiles
 constexpr int kBlendThreads = 128;    // two pixels of a 16x16 tile per thread (rows y, y + 8)
 constexpr int kBlendBatch = 256;      // Gaussians staged in LDS per step
+constexpr int kBlendRun = 128;        // consecutive tiles one XCD takes in a row (blend)
 constexpr int kMaxSeg = 16;           // (viewer, eye) images per raster batch
 constexpr int kGridBlocks = 2048;     // fixed grid of the grid-stride kernels
 constexpr int kScanBlocks = 1024;     // blocks of the device-wide scan

@@ -666,11 +666,12 @@ __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const
 }
 
 
-// One block per global tile; block -> tile mapping keeps runs of adjacent
-// tiles on one XCD (blocks are dealt round-robin over the 8 XCDs) so that
-// Gaussians shared by neighbouring tiles are gathered through one L2.
-// Gaussians are staged in LDS 256 at a time; the block stops as soon as
-// every pixel has reached the transmittance floor.
+// One block per global tile; the block -> tile map gives each XCD runs of
+// kBlendRun adjacent tiles, interleaved over the image, so Gaussians shared
+// by neighbouring tiles are gathered through one L2 and the XCDs get equal
+// shares of dense and sparse image regions.  Gaussians are staged in LDS 256
+// at a time; the block stops as soon as every pixel has reached the
+// transmittance floor.
 // One 16x16 tile per block of 128 threads; thread t owns the pixels
 // (t & 15, t >> 4) and (t & 15, (t >> 4) + 8) of the tile, which share their
 // column offset dx.  Gaussians of the tile's depth-sorted list are staged in
@@ -696,9 +697,14 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
     __shared__ int32_t sEval[2 * (kBlendThreads / 64)];
     constexpr float kL2e = 1.4426950408889634f;
     const int total = tab.total_tiles;
-    const int q8 = total >> 3, r8 = total & 7;
-    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int gt = xcd * q8 + min(xcd, r8) + j;
+    // Blocks go to the 8 XCDs round-robin (block b to XCD b mod 8).  Each
+    // run of 8 x kBlendRun blocks covers 8 runs of kBlendRun consecutive
+    // tiles, one per XCD, so neighbouring tiles (which share Gaussians)
+    // meet in one L2 while every XCD draws tiles from all over the image;
+    // the last partial run keeps the identity map.
+    const int b = blockIdx.x, sc = b / (8 * kBlendRun);
+    const int gt = (sc + 1) * 8 * kBlendRun <= total ? sc * 8 * kBlendRun + (b & 7) * kBlendRun + (b % (8 * kBlendRun)) / 8
+                                                      : b;
     int si = 0;
     while (si + 1 < tab.n && gt >= tab.s[si + 1].tile_base) ++si;
     const Seg& s = tab.s[si];
