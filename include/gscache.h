@@ -248,9 +248,15 @@ int gsc_timing(gsc_ctx* ctx, int enable);
  * the frame did not run both); *frames = frames recorded.  The events skip
  * the system-scope fence (no cache writeback per mark).  Clears the record. */
 int gsc_timing_read(gsc_ctx* ctx, double* ms_out, int32_t n, double* frame_ms, int64_t frame_cap, int64_t* frames);
+/* Which stages get boundary events while timing is on: bit i of stage_mask
+ * selects stage i (default: all).  The frame's first and last events are
+ * always recorded.  Each event makes the stream wait for the kernel before it
+ * to drain (a few microseconds), so timing a few stages disturbs the frame
+ * less than timing all; stages not selected read 0. */
+int gsc_timing_stages(gsc_ctx* ctx, uint32_t stage_mask);
 
 /* ---------------- learned reuse predictor (Linear 6-64-64-1, sigmoid) ----
- * North-star extension of the reuse decision of Section 4 (Alg. 1): for a
+ * An extension of the reuse decision of Section 4 (Alg. 1): for a
  * visible anchor whose cache line is still valid, a small MLP reads six
  * features (view-direction change, distance ratio, age / d_max, level /
  * l_max, camera travel / distance, log2 projected voxel size) and predicts
@@ -295,7 +301,7 @@ int gsc_predictor_grad(gsc_ctx* ctx, const float* X, const float* y, int64_t n, 
 int gsc_predictor_infer(gsc_ctx* ctx, const float* X, int64_t n, float* p_out);
 
 /* ---------------- serving: several viewers, one device -------------------
- * North-star extension around the per-frame path of Section 4 (the paper's
+ * An extension around the per-frame path of Section 4 (the paper's
  * own scheduler, Section 5, is multi-GPU and not this): continuous batching
  * of stereo frame requests from several viewers of uneven resolution, each
  * with its own device cache, over one shared scene.  Every call on a server

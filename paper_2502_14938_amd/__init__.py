@@ -107,6 +107,7 @@ SYMBOLS = {
     "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "gsc_server_pending": ([C.c_void_p], C.c_int),
     "gsc_timing": ([C.c_void_p, C.c_int], C.c_int),
+    "gsc_timing_stages": ([C.c_void_p, C.c_uint32], C.c_int),
     "gsc_count_work": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing_read": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gsc_server_last_error": ([C.c_void_p], C.c_char_p),
@@ -274,8 +275,11 @@ class Renderer:
         """Let the blend count its visits and contributions (stats n_eval, n_contrib)."""
         self._check(lib().gsc_count_work(self.h, 1 if enable else 0))
 
-    def timing(self, enable=True):
-        """Record device time per stage of every frame from now on (or stop)."""
+    def timing(self, enable=True, stages=None):
+        """Record device time of every frame from now on (or stop): the frame
+        and each stage in `stages` (names from STAGES; None: all)."""
+        mask = 0xFFFFFFFF if stages is None else sum(1 << STAGES.index(x) for x in stages)
+        self._check(lib().gsc_timing_stages(self.h, mask))
         self._check(lib().gsc_timing(self.h, 1 if enable else 0))
 
     def timing_read(self, max_frames=4096):

@@ -290,7 +290,13 @@ Marks* frame_marks(gsc_ctx* c) {
             }
         c->marks.push_back(m);
     }
-    return &c->marks[c->marks_used];
+    Marks& m = c->marks[c->marks_used];
+    // boundaries of the selected stages, and the frame's two ends
+    uint32_t want = 1u | (1u << kNumStages);
+    for (int i = 0; i < kNumStages; ++i)
+        if (c->timing_mask >> i & 1u) want |= (1u << i) | (1u << (i + 1));
+    m.want = want;
+    return &m;
 }
 
 void free_marks(gsc_ctx* c) {
@@ -648,6 +654,12 @@ int gsc_timing(gsc_ctx* c, int enable) {
     c->timing = enable != 0;
     c->marks_used = 0;
     for (Marks& m : c->marks) m.recorded = 0;
+    return GSC_OK;
+}
+
+int gsc_timing_stages(gsc_ctx* c, uint32_t stage_mask) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_timing_stages: null context");
+    c->timing_mask = stage_mask;
     return GSC_OK;
 }
 

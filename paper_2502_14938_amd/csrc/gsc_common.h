@@ -228,9 +228,10 @@ constexpr int kNumStages = 11;
 struct Marks {
     hipEvent_t ev[kNumStages + 1];
     uint32_t recorded;  // bit i: ev[i] recorded this frame
+    uint32_t want;      // bit i: record ev[i]
 };
 inline void mark(Marks* m, int i, hipStream_t st) {
-    if (m && hipEventRecord(m->ev[i], st) == hipSuccess) m->recorded |= 1u << i;
+    if (m && (m->want >> i & 1u) && hipEventRecord(m->ev[i], st) == hipSuccess) m->recorded |= 1u << i;
 }
 
 hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr);

@@ -104,6 +104,7 @@ struct gsc_ctx {
     bool last_count_work = false;  // ... for the last rendered frame
     // stage timing (gsc_timing): one event set per frame since the last read
     bool timing = false;
+    uint32_t timing_mask = ~0u;    // stages with boundary events (gsc_timing_stages)
     std::vector<gsc::Marks> marks;
     size_t marks_used = 0;
 };
