@@ -59,10 +59,10 @@ __global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entr
 // Minimum of q(d) = a dx^2 + 2 b dx dy + c dy^2 over the closed rectangle
 // [x0,x1] x [y0,y1] of offsets d (q convex: 0 inside, else on an edge; the
 // edge minimiser of a 1-D quadratic, clamped).  ia = 1/a, ic = 1/c.
-// Contraction is off so that the count and emit passes agree exactly.
+// Every footprint's tile spans are computed once (here or in k_tall_rows)
+// and stored, so counting and emission read the same decisions.
 __device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia, float ic, float x0, float x1,
                                             float y0, float y1) {
-#pragma clang fp contract(off)
     if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
     float best = INFINITY;
     float fx[2] = {x0, x1}, fy[2] = {y0, y1};
@@ -83,7 +83,7 @@ __device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia,
 // pixel-centre band overlaps the tile's x-span; the tiles hit in a row are
 // therefore contiguous.  The extent is computed analytically; tiles clearly
 // inside it (by a margin far above FP32 error) are hit, tiles near its ends
-// get the exact rectangle test.  Count and emit both call this function.
+// get the exact rectangle test.
 struct Ellipse {
     float mx, my, ca, cb, cc, tau;
     float det, xmax, ymax, kr;  // kr: dy of the rightmost point is -cb * kr
@@ -92,7 +92,6 @@ struct Ellipse {
 };
 
 __device__ __forceinline__ Ellipse make_ellipse(float mx, float my, float ca, float cb, float cc, float tau) {
-#pragma clang fp contract(off)
     Ellipse e;
     e.mx = mx; e.my = my; e.ca = ca; e.cb = cb; e.cc = cc; e.tau = tau;
     e.det = ca * cc - cb * cb;
@@ -108,7 +107,6 @@ __device__ __forceinline__ Ellipse make_ellipse(float mx, float my, float ca, fl
 
 // Does the footprint reach the pixel-centre rectangle of tile (tx, ty)?
 __device__ __forceinline__ bool tile_hit(const Ellipse& e, int tx, int ty, int W, int H) {
-#pragma clang fp contract(off)
     float x0 = (float)(kTile * tx) + 0.5f, y0 = (float)(kTile * ty) + 0.5f;
     float x1 = (float)min(kTile * tx + kTile - 1, W - 1) + 0.5f;
     float y1 = (float)min(kTile * ty + kTile - 1, H - 1) + 0.5f;
@@ -116,7 +114,6 @@ __device__ __forceinline__ bool tile_hit(const Ellipse& e, int tx, int ty, int W
 }
 
 __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int W, int H, int& lo, int& hi) {
-#pragma clang fp contract(off)
     lo = 0;
     hi = -1;
     const float y0 = (float)(kTile * ty) + 0.5f - e.my;
@@ -645,22 +642,20 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
 template <typename K>
 __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const int32_t* n_sort, int shift,
                                                int32_t* __restrict__ ranges, uint32_t n_tiles) {
-    constexpr int R = 8;
+    // one key per lane, coalesced; the neighbours come from the adjacent
+    // lanes (the wave's two end lanes read theirs)
     const int64_t n = *n_sort;
-    for (int64_t i0 = gtid() * R; i0 < n; i0 += gstride() * R) {
-        uint32_t t[R + 2];
-#pragma unroll
-        for (int q = 0; q < R + 2; ++q) {
-            int64_t i = i0 - 1 + q;
-            t[q] = (i >= 0 && i < n) ? (uint32_t)(keys[i] >> shift) : 0xffffffffu;
-        }
-#pragma unroll
-        for (int q = 1; q <= R; ++q) {
-            int64_t i = i0 - 1 + q;
-            if (i >= n) break;
-            if (t[q] >= n_tiles) continue;  // never produced by the binning; kept out of bounds-safe reach
-            if (t[q - 1] != t[q]) ranges[2 * (int64_t)t[q]] = (int32_t)i;
-            if (t[q + 1] != t[q]) ranges[2 * (int64_t)t[q] + 1] = (int32_t)(i + 1);
+    const int lane = threadIdx.x & 63;
+    for (int64_t w0 = gtid() - lane; w0 < n; w0 += gstride()) {
+        const int64_t i = w0 + lane;
+        const bool in = i < n;
+        const uint32_t t = in ? (uint32_t)(keys[i] >> shift) : 0xffffffffu;
+        uint32_t prev = __shfl_up(t, 1, 64), next = __shfl_down(t, 1, 64);
+        if (lane == 0) prev = in && i > 0 ? (uint32_t)(keys[i - 1] >> shift) : 0xffffffffu;
+        if (lane == 63) next = i + 1 < n ? (uint32_t)(keys[i + 1] >> shift) : 0xffffffffu;
+        if (in && t < n_tiles) {  // t < n_tiles always holds; keeps a stray key out of bounds-safe reach
+            if (prev != t) ranges[2 * (int64_t)t] = (int32_t)i;
+            if (next != t) ranges[2 * (int64_t)t + 1] = (int32_t)(i + 1);
         }
     }
 }
@@ -910,7 +905,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
+        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
                            r.ranges, (uint32_t)tab.total_tiles);
     } else {
         mark(mk, 5, st);  // no per-Gaussian depth pass in this mode
@@ -929,7 +924,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
+        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
                            32, r.ranges, (uint32_t)tab.total_tiles);
     }
     r.order = nullptr;

@@ -12,7 +12,7 @@ namespace {
 
 constexpr int NT = 256;        // threads per block (4 waves)
 constexpr int SCAN_TILE = 1024;  // elements per scan step (4 per thread)
-constexpr int SORT_IPT = 8;      // elements per thread per sort step
+constexpr int SORT_IPT = 16;     // elements per thread per sort step
 constexpr int SORT_TILE = NT * SORT_IPT;
 constexpr int SORT_WSEG = SORT_TILE / 4;  // elements per wave per step
 
