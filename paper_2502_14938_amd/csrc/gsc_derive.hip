@@ -350,8 +350,13 @@ __global__ __launch_bounds__(NT) void k_compose_count(const int32_t* __restrict_
             continue;
         }
         int64_t base = (int64_t)vslot[i] * k;
+        // all k opacity loads in flight at once (k <= kMaxK)
+        float w[kMaxK];
+#pragma unroll
+        for (int j = 0; j < kMaxK; ++j) w[j] = j < k ? L0[base + j].w : 0.f;
         uint32_t c = 0;
-        for (int j = 0; j < k; ++j) c += L0[base + j].w > 0.f ? 1u : 0u;
+#pragma unroll
+        for (int j = 0; j < kMaxK; ++j) c += w[j] > 0.f ? 1u : 0u;
         count[i] = c;
     }
 }
@@ -363,9 +368,13 @@ __global__ __launch_bounds__(NT) void k_compose_write(const int32_t* __restrict_
     for (int64_t i = gtid(); i < nv; i += gstride()) {
         if (vslot[i] < 0) continue;
         int64_t base = (int64_t)vslot[i] * k;
+        float w[kMaxK];
+#pragma unroll
+        for (int j = 0; j < kMaxK; ++j) w[j] = j < k ? L0[base + j].w : 0.f;
         uint32_t o = off[i];
-        for (int j = 0; j < k; ++j)
-            if (L0[base + j].w > 0.f) G[o++] = (int32_t)(base + j);
+#pragma unroll
+        for (int j = 0; j < kMaxK; ++j)
+            if (w[j] > 0.f) G[o++] = (int32_t)(base + j);
     }
 }
 
