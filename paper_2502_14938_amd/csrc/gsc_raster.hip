@@ -642,20 +642,37 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
 template <typename K>
 __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const int32_t* n_sort, int shift,
                                                int32_t* __restrict__ ranges, uint32_t n_tiles) {
-    // one key per lane, coalesced; the neighbours come from the adjacent
-    // lanes (the wave's two end lanes read theirs)
+    // each lane takes RQ consecutive keys (a wave 64 RQ, coalesced), two such
+    // steps in flight; neighbours across lanes come from the adjacent lanes,
+    // the wave's two end lanes read theirs
+    constexpr int RQ = 4, US = 2;
     const int64_t n = *n_sort;
     const int lane = threadIdx.x & 63;
-    for (int64_t w0 = gtid() - lane; w0 < n; w0 += gstride()) {
-        const int64_t i = w0 + lane;
-        const bool in = i < n;
-        const uint32_t t = in ? (uint32_t)(keys[i] >> shift) : 0xffffffffu;
-        uint32_t prev = __shfl_up(t, 1, 64), next = __shfl_down(t, 1, 64);
-        if (lane == 0) prev = in && i > 0 ? (uint32_t)(keys[i - 1] >> shift) : 0xffffffffu;
-        if (lane == 63) next = i + 1 < n ? (uint32_t)(keys[i + 1] >> shift) : 0xffffffffu;
-        if (in && t < n_tiles) {  // t < n_tiles always holds; keeps a stray key out of bounds-safe reach
-            if (prev != t) ranges[2 * (int64_t)t] = (int32_t)i;
-            if (next != t) ranges[2 * (int64_t)t + 1] = (int32_t)(i + 1);
+    const int64_t wave = gtid() >> 6, nwaves = gstride() >> 6;
+    for (int64_t w0 = wave * (64 * RQ * US); w0 < n; w0 += nwaves * (64 * RQ * US)) {
+        uint32_t t[US][RQ];
+#pragma unroll
+        for (int u = 0; u < US; ++u) {
+            const int64_t i0 = w0 + (int64_t)u * 64 * RQ + (int64_t)lane * RQ;
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) t[u][q] = i0 + q < n ? (uint32_t)(keys[i0 + q] >> shift) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < US; ++u) {
+            const int64_t i0 = w0 + (int64_t)u * 64 * RQ + (int64_t)lane * RQ;
+            uint32_t prev = __shfl_up(t[u][RQ - 1], 1, 64), next = __shfl_down(t[u][0], 1, 64);
+            if (lane == 0) prev = i0 > 0 && i0 - 1 < n ? (uint32_t)(keys[i0 - 1] >> shift) : 0xffffffffu;
+            if (lane == 63) next = i0 + RQ < n ? (uint32_t)(keys[i0 + RQ] >> shift) : 0xffffffffu;
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+                const int64_t i = i0 + q;
+                const uint32_t tq = t[u][q];
+                const uint32_t pq = q == 0 ? prev : t[u][q - 1], nq = q == RQ - 1 ? next : t[u][q + 1];
+                if (i < n && tq < n_tiles) {  // tq < n_tiles always holds; keeps a stray key out of bounds-safe reach
+                    if (pq != tq) ranges[2 * (int64_t)tq] = (int32_t)i;
+                    if (nq != tq) ranges[2 * (int64_t)tq + 1] = (int32_t)(i + 1);
+                }
+            }
         }
     }
 }
@@ -741,11 +758,14 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
                 const float e0 = fy0 - A.y, e1 = fy1 - A.y;
                 const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e0, fmaf(B.x, e0, u), t)));
                 const float al1 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e1, fmaf(B.x, e1, u), t)));
-                const float tn0 = T0 * (1.0f - al0), tn1 = T1 * (1.0f - al1);
+                // weight alpha T; the next transmittance T (1 - alpha) as T - alpha T
+                const float wf0 = al0 * T0, wf1 = al1 * T1;
+                const float tn0 = T0 - wf0, tn1 = T1 - wf1;
                 const bool u0 = !d0 && al0 >= kMinAlpha, u1 = !d1 && al1 >= kMinAlpha;
-                const bool s0 = u0 && tn0 < kTStop, s1 = u1 && tn1 < kTStop;
-                const bool a0 = u0 && !s0, a1 = u1 && !s1;
-                const float w0 = a0 ? al0 * T0 : 0.f, w1 = a1 ? al1 * T1 : 0.f;
+                const bool ok0 = tn0 >= kTStop, ok1 = tn1 >= kTStop;
+                const bool s0 = u0 && !ok0, s1 = u1 && !ok1;
+                const bool a0 = u0 && ok0, a1 = u1 && ok1;
+                const float w0 = a0 ? wf0 : 0.f, w1 = a1 ? wf1 : 0.f;
                 const float cb = sC[k];
                 r0 = fmaf(B.z, w0, r0); g0 = fmaf(B.w, w0, g0); b0 = fmaf(cb, w0, b0);
                 r1 = fmaf(B.z, w1, r1); g1 = fmaf(B.w, w1, g1); b1 = fmaf(cb, w1, b1);
@@ -905,7 +925,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
+        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
                            r.ranges, (uint32_t)tab.total_tiles);
     } else {
         mark(mk, 5, st);  // no per-Gaussian depth pass in this mode
@@ -924,7 +944,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         if (e != hipSuccess) return e;
         mark(mk, 9, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
+        hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
                            32, r.ranges, (uint32_t)tab.total_tiles);
     }
     r.order = nullptr;
