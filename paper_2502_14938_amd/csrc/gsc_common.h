@@ -200,8 +200,11 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int
 // the counts in digit-major order, a scatter through LDS).  Count from
 // *n_dev (device) or n_host.  Returns in *which the buffer index (0/1)
 // holding the result.  hist: [256 * kSortBlocks], block_sums: scan scratch.
+// With gout, the last pass writes gout[i] = gsrc[sorted value i] in place of
+// the sorted keys (which are then not produced).
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
-                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st,
+                          const uint32_t* gsrc = nullptr, uint32_t* gout = nullptr);
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
 

@@ -340,24 +340,6 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
     }
 }
 
-// Tile counts in depth-rank order, for the offset scan (4 gathers in flight
-// per thread).
-__global__ __launch_bounds__(NT) void k_gather_counts(const uint32_t* __restrict__ order,
-                                                      const uint32_t* __restrict__ ntiles, const RasterCounters* rc,
-                                                      uint32_t* __restrict__ out) {
-    const int64_t ne = rc->n_entries;
-    for (int64_t r0 = gtid() * 4; r0 < ne; r0 += gstride() * 4) {
-        uint32_t e[4], c[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) e[q] = r0 + q < ne ? order[r0 + q] : 0u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = r0 + q < ne ? ntiles[e[q]] : 0u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (r0 + q < ne) out[r0 + q] = c[q];
-    }
-}
-
 struct DupArgs {
     SegTable tab;
     RasterCounters* rc;
@@ -904,11 +886,11 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     if (!full_key_sort) {
         // low 32 key bits (depth) first, per Gaussian
         int which = 0;
-        e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st);
+        // the last pass also lays the tile counts out in depth order (scnt)
+        e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st, r.ntiles,
+                           r.scnt);
         if (e != hipSuccess) return e;
         mark(mk, 5, st);
-        hipLaunchKernelGGL(k_gather_counts, grid_fit(k_gather_counts, r.max_entries / 4 + 1), dim3(NT), 0, st, r.dval[which], r.ntiles,
-                           rc, r.scnt);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         mark(mk, 6, st);

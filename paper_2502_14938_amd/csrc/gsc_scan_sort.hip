@@ -178,11 +178,14 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ keys, c
         hist[(int64_t)q * gridDim.x + blockIdx.x] = h[0][q] + h[1][q] + h[2][q] + h[3][q];
 }
 
-template <typename K, int BITS>
+// kGather (last pass only): instead of the keys, write gout[pos] =
+// gsrc[value] (a per-value quantity wanted in sorted order).
+template <typename K, int BITS, bool kGather>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       const int32_t* n_dev, int64_t n_host, int shift,
-                                                      const uint32_t* __restrict__ offs) {
+                                                      const uint32_t* __restrict__ offs,
+                                                      const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gout) {
     constexpr int bits = BITS;
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t run[256];
@@ -255,8 +258,10 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
             K k = skey[i];
             uint32_t d = digit(k, shift, mask);
             uint32_t pos = run[d] + (uint32_t)i - texcl[d];
-            kout[pos] = k;
-            vout[pos] = sval[i];
+            const uint32_t v = sval[i];
+            if (kGather) gout[pos] = gsrc[v];
+            else kout[pos] = k;
+            vout[pos] = v;
         }
         __syncthreads();
         if (threadIdx.x < nbins) run[threadIdx.x] += tot_d;
@@ -266,10 +271,15 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
 
 template <typename K>
 void launch_scatter(int bits, const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, const int32_t* n_dev,
-                    int64_t n_host, int shift, const uint32_t* offs, hipStream_t st) {
-#define GSC_SCATTER(B)                                                                                           \
-    hipLaunchKernelGGL((k_radix_scatter<K, B>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, n_dev, \
-                       n_host, shift, offs)
+                    int64_t n_host, int shift, const uint32_t* offs, const uint32_t* gsrc, uint32_t* gout,
+                    hipStream_t st) {
+#define GSC_SCATTER(B)                                                                                               \
+    if (gout)                                                                                                        \
+        hipLaunchKernelGGL((k_radix_scatter<K, B, true>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, \
+                           n_dev, n_host, shift, offs, gsrc, gout);                                                  \
+    else                                                                                                             \
+        hipLaunchKernelGGL((k_radix_scatter<K, B, false>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, \
+                           n_dev, n_host, shift, offs, gsrc, gout)
     switch (bits) {
         case 1: GSC_SCATTER(1); break;
         case 2: GSC_SCATTER(2); break;
@@ -285,7 +295,8 @@ void launch_scatter(int bits, const K* kin, const uint32_t* vin, K* kout, uint32
 
 template <typename K>
 hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0, int bit1,
-                           uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
+                           uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st, const uint32_t* gsrc,
+                           uint32_t* gout) {
     int cur = 0;
     for (int shift = bit0; shift < bit1; shift += 8) {
         int bits = bit1 - shift < 8 ? bit1 - shift : 8;
@@ -293,7 +304,9 @@ hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, 
                            bits, hist);
         hipError_t e = scan_u32(hist, hist, nullptr, (int64_t)(1 << bits) * kSortBlocks, nullptr, block_sums, st);
         if (e != hipSuccess) return e;
-        launch_scatter<K>(bits, keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, n_host, shift, hist, st);
+        const bool last = shift + 8 >= bit1;
+        launch_scatter<K>(bits, keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, n_host, shift, hist,
+                          last ? gsrc : nullptr, last ? gout : nullptr, st);
         cur ^= 1;
     }
     *which = cur;
@@ -310,13 +323,15 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int
 }
 
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
-                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
-    return radix_sort_impl<uint32_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st);
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st,
+                          const uint32_t* gsrc, uint32_t* gout) {
+    return radix_sort_impl<uint32_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, gsrc, gout);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
-    return radix_sort_impl<uint64_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st);
+    return radix_sort_impl<uint64_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, nullptr,
+                                     nullptr);
 }
 
 }  // namespace gsc
