@@ -217,7 +217,9 @@ struct PreArgs {
     int64_t n_ranges;
 };
 
-__global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
+// (at most 128 VGPRs: four waves per SIMD to cover the chain of dependent
+// loads of an entry)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(PreArgs p) {
     __shared__ uint32_t s_wtall[NT / 64];
     for (int64_t i = gtid(); i < p.n_ranges; i += gstride()) p.ranges[i] = 0;
     const int64_t ne = p.rc->n_entries;
@@ -296,6 +298,9 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
                     y1 = (int)fminf(fmaxf(fy1, -1.f), (float)(s.nty - 1));
                 }
             }
+            // the projected record now: its registers are free for the row spans
+            p.rec[kRec * e] = A;
+            p.rec[kRec * e + 1] = B;
             if (y1 - y0 + 1 <= kSmallRows) {
 #pragma unroll
                 for (int i = 0; i < kSmallRows; ++i) {
@@ -327,8 +332,6 @@ __global__ __launch_bounds__(NT) void k_preprocess(PreArgs p) {
         __syncthreads();  // s_wtall is rewritten by the next step
         if (valid) {
             rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
-            p.rec[kRec * e] = A;
-            p.rec[kRec * e + 1] = B;
             p.rec[kRec * e + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
                                               __uint_as_float(count));
             p.rec[kRec * e + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
