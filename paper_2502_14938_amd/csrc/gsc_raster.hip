@@ -196,6 +196,7 @@ __device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
 // (lanes split the rows) and emitted one wave per entry; shorter ones keep
 // their row spans in the record and are emitted from them.
 constexpr int kSmallRows = 4;
+constexpr int kTallGroup = 8;     // tall entries whose metadata a wave loads together (k_dup_big)
 
 // Per-entry record, 4 x float4 (64 B, one cache line):
 //   A = (mean2d.x, mean2d.y, conic a, conic b)
@@ -413,9 +414,13 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
         uint32_t n_here = 0;
         uint32_t cum[kSmallRows] = {0u, 0u, 0u, 0u}, first[kSmallRows] = {0u, 0u, 0u, 0u};
         if (r < ne) {
+            // two rounds of loads: (depth order, pair offset), then the
+            // record's count / rows word and its spans together
             const uint32_t e = kFull ? (uint32_t)r : d.order[r];
+            const uint32_t out_at = d.offs[r];
             const float4* rp = d.rec + kRec * (int64_t)e;
             const float4 C = rp[2];
+            const float4 D = rp[3];
             const uint32_t cnt = __float_as_uint(C.w);
             if (cnt) {
                 const uint32_t rows = __float_as_uint(C.y);
@@ -423,7 +428,6 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
                 if (y1 - y0 + 1 > kSmallRows) {
                     is_big = true;
                 } else {
-                    const float4 D = rp[3];
                     const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
                                                      __float_as_uint(D.w)};
                     const Seg& sg = d.tab.s[__float_as_uint(C.z)];
@@ -436,7 +440,7 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
                         first[i] = (uint32_t)(sg.tile_base + (y0 + i) * sg.ntx + lo);
                     }
                     n_here = acc;  // equals cnt: the spans are what was counted
-                    s_out[threadIdx.x] = d.offs[r];
+                    s_out[threadIdx.x] = out_at;
                     s_e[threadIdx.x] = e;
                     s_low[threadIdx.x] = kFull ? d.dkey[e] : 0u;
                 }
@@ -524,48 +528,67 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
     const int64_t nb = d.rc->n_tall;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t b = wave; b < nb; b += nwaves) {
-        const int64_t r = tall_list[b];
-        const uint32_t e = kFull ? (uint32_t)r : d.order[r];
-        const float4* rp = d.rec + kRec * (int64_t)e;
-        const float4 C = rp[2];
-        const uint32_t cnt = __float_as_uint(C.w);
-        const uint32_t rows = __float_as_uint(C.y);
-        const int y0 = rows & 0xffff, y1 = rows >> 16;
-        const Seg& s = d.tab.s[__float_as_uint(C.z)];
-        const uint64_t low = kFull ? (uint64_t)d.dkey[e] : 0ull;
-        const int64_t o = d.offs[r];
-        const int64_t sp0 = __float_as_uint(rp[3].x);  // first stored span (k_tall_count)
-        uint32_t run = 0;
-        for (int chunk = y0; chunk <= y1; chunk += 64) {
-            // one row per lane: its stored span, then the rows' pair prefix
-            int lo = 0, hi = -1;
-            const int64_t q = sp0 + (chunk - y0) + lane;
-            if (chunk + lane <= y1 && q < d.span_cap) {
-                const uint32_t sp = d.spans[q];
-                lo = sp & 0xffff;
-                hi = sp >> 16;
-            }
-            uint32_t tot;
-            const uint32_t ex = wave_excl_scan(hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
-            s_ex[w][lane] = ex;
-            s_first[w][lane] = (uint32_t)(s.tile_base + (chunk + lane) * s.ntx + lo);
-            __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
-            // the rows' pairs together: lane j takes pairs j, j + 64, ... and
-            // finds its row as the last one whose prefix is <= j (rows without
-            // pairs share the next row's prefix, so the last one has pairs)
-            for (uint32_t j = lane; j < tot; j += 64) {
-                int lo2 = 0, hi2 = 63;
-                while (lo2 < hi2) {
-                    const int mid = (lo2 + hi2 + 1) >> 1;
-                    if (s_ex[w][mid] <= j) lo2 = mid;
-                    else hi2 = mid - 1;
+    // wave w emits list entries w, w + nwaves, w + 2 nwaves, ... (heavy
+    // footprints cluster in the list; striding spreads them over the waves),
+    // loading the metadata of its next kTallGroup entries together, one per
+    // lane, then emitting them in turn
+    for (int64_t b0 = wave; b0 < nb; b0 += nwaves * kTallGroup) {
+        uint32_t me = 0, mo = 0, mcnt = 0, mrows = 0, mseg = 0, msp0 = 0, mlow = 0;
+        const int64_t bl = b0 + (int64_t)lane * nwaves;
+        if (lane < kTallGroup && bl < nb) {
+            const int64_t r = tall_list[bl];
+            me = kFull ? (uint32_t)r : d.order[r];
+            mo = d.offs[r];
+            const float4* rp = d.rec + kRec * (int64_t)me;
+            const float4 C = rp[2];
+            mcnt = __float_as_uint(C.w);
+            mrows = __float_as_uint(C.y);
+            mseg = __float_as_uint(C.z);
+            msp0 = __float_as_uint(rp[3].x);  // first stored span (k_tall_count)
+            mlow = kFull ? d.dkey[me] : 0u;
+        }
+        const int64_t left = (nb - b0 + nwaves - 1) / nwaves;  // entries of this wave from b0 on
+        const int ng = left < kTallGroup ? (int)left : kTallGroup;
+        for (int gi = 0; gi < ng; ++gi) {
+            const uint32_t e = __shfl(me, gi, 64);
+            const uint32_t cnt = __shfl(mcnt, gi, 64);
+            const uint32_t rows = __shfl(mrows, gi, 64);
+            const int y0 = rows & 0xffff, y1 = rows >> 16;
+            const Seg& s = d.tab.s[__shfl(mseg, gi, 64)];
+            const uint64_t low = (uint64_t)__shfl(mlow, gi, 64);
+            const int64_t o = __shfl(mo, gi, 64);
+            const int64_t sp0 = __shfl(msp0, gi, 64);
+            uint32_t run = 0;
+            for (int chunk = y0; chunk <= y1; chunk += 64) {
+                // one row per lane: its stored span, then the rows' pair prefix
+                int lo = 0, hi = -1;
+                const int64_t q = sp0 + (chunk - y0) + lane;
+                if (chunk + lane <= y1 && q < d.span_cap) {
+                    const uint32_t sp = d.spans[q];
+                    lo = sp & 0xffff;
+                    hi = sp >> 16;
                 }
-                const uint32_t wpos = run + j;
-                if (wpos < cnt) put_pair<kFull>(d, o + wpos, s_first[w][lo2] + (j - s_ex[w][lo2]), e, low);
+                uint32_t tot;
+                const uint32_t ex = wave_excl_scan(hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
+                s_ex[w][lane] = ex;
+                s_first[w][lane] = (uint32_t)(s.tile_base + (chunk + lane) * s.ntx + lo);
+                __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
+                // the rows' pairs together: lane j takes pairs j, j + 64, ... and
+                // finds its row as the last one whose prefix is <= j (rows without
+                // pairs share the next row's prefix, so the last one has pairs)
+                for (uint32_t j = lane; j < tot; j += 64) {
+                    int lo2 = 0, hi2 = 63;
+                    while (lo2 < hi2) {
+                        const int mid = (lo2 + hi2 + 1) >> 1;
+                        if (s_ex[w][mid] <= j) lo2 = mid;
+                        else hi2 = mid - 1;
+                    }
+                    const uint32_t wpos = run + j;
+                    if (wpos < cnt) put_pair<kFull>(d, o + wpos, s_first[w][lo2] + (j - s_ex[w][lo2]), e, low);
+                }
+                __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
+                run += tot;
             }
-            __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
-            run += tot;
         }
     }
 }
