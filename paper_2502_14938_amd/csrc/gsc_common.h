@@ -194,6 +194,10 @@ struct Raster {
 // writing exclusive prefixes to out and the total to *total (device).
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int64_t n_host, int32_t* total,
                     uint32_t* block_sums, hipStream_t st);
+// Stream compaction: ids[k] = the k-th i with flags[i] != 0 (flags 0 or 1,
+// n from *n_dev if non-null), the count to *total (device).
+hipError_t compact_u32(const uint32_t* flags, const int32_t* n_dev, int64_t n_host, int32_t* total, int32_t* ids,
+                       uint32_t* block_sums, hipStream_t st);
 
 // Stable LSD radix sort of (key, value) pairs over bits [bit0, bit1),
 // 8-bit digits, reduce-then-scan per pass (digit counts per block, a scan of

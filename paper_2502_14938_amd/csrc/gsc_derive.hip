@@ -22,11 +22,26 @@ constexpr int NT = 256;
 __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Per-frame counters reset, and the unified camera centre of frame t kept
+// for the reuse features of later frames (run by the first block of the
+// selection kernel).
+__device__ __forceinline__ void frame_begin(Counters* cnt, float* pu_hist, int32_t t, const DeriveCam& cam) {
+    if (threadIdx.x == 0) {
+        cnt->n_cand = 0;
+        cnt->overflow = 0;
+        cnt->n_evict = 0;
+        cnt->evict_short = 0;
+    }
+    if (threadIdx.x < 3) pu_hist[4 * (t & 63) + threadIdx.x] = cam.pos[threadIdx.x];
+}
+
 // ------------------------------------------------------------- selection
 // Keep anchor a iff (level 0 or |x - p_u| <= d_ref 2^-level) and its bounding
 // sphere is not wholly outside any unified-frustum plane (4 sides + near).
 __global__ __launch_bounds__(NT) void k_select_flags(const float4* __restrict__ posr, const uint8_t* __restrict__ level,
-                                                     int64_t n, DeriveCam cam, uint32_t* __restrict__ flags) {
+                                                     int64_t n, DeriveCam cam, uint32_t* __restrict__ flags,
+                                                     Counters* cnt, float* __restrict__ pu_hist, int32_t t) {
+    if (blockIdx.x == 0) frame_begin(cnt, pu_hist, t, cam);
     for (int64_t a = gtid(); a < n; a += gstride()) {
         float4 p = posr[a];
         int l = level[a];
@@ -309,17 +324,6 @@ __device__ __forceinline__ void depth_update(Counters* cnt, int32_t dmax, int32_
     cnt->depth = (int32_t)(d < 1 ? 1 : (d > dmax ? dmax : d));
 }
 
-// Per-frame counters reset, and the unified camera centre of frame t kept
-// for the reuse features of later frames (one block of 64 threads).
-__global__ void k_frame_begin(Counters* cnt, float* pu_hist, int32_t t, DeriveCam cam) {
-    if (threadIdx.x == 0) {
-        cnt->n_cand = 0;
-        cnt->overflow = 0;
-        cnt->n_evict = 0;
-        cnt->evict_short = 0;
-    }
-    if (threadIdx.x < 3) pu_hist[4 * (t & 63) + threadIdx.x] = cam.pos[threadIdx.x];
-}
 
 __global__ void k_evict_freescan_n(const Counters* cnt, int32_t* scan_n, int64_t C) {
     *scan_n = cnt->evict_short > 0 ? (int32_t)C : 0;
@@ -394,11 +398,11 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     const int32_t t = (int32_t)v.t;
     Counters* cnt = v.cnt;
     mark(mk, 0, st);
-    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(64), 0, st, cnt, v.pu_hist, t, a.cam);
-    // anchor indexing and filtering -> X_t ascending
-    hipLaunchKernelGGL(k_select_flags, grid_fit(k_select_flags, n), dim3(NT), 0, st, sc.posr, sc.level, n, a.cam, v.tmp_a);
-    GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, nullptr, n, &cnt->n_visible, v.block_sums, st));
-    hipLaunchKernelGGL(k_compact_ids, grid_fit(k_compact_ids, n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, n, nullptr, v.visible);
+    // anchor indexing and filtering -> X_t ascending (the first block also
+    // starts the frame's counters)
+    hipLaunchKernelGGL(k_select_flags, grid_fit(k_select_flags, n), dim3(NT), 0, st, sc.posr, sc.level, n, a.cam, v.tmp_a,
+                       cnt, v.pu_hist, t);
+    GSC_TRY(compact_u32(v.tmp_a, nullptr, n, &cnt->n_visible, v.visible, v.block_sums, st));
 
     const bool reuse = (a.flags & GSC_FLAG_REUSE) != 0;
     if (!reuse) {
@@ -417,9 +421,7 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
         la.cand_feat = a.collect ? v.cand_feat : nullptr; la.cand_id = v.cand_id; la.cnt = cnt;
         hipLaunchKernelGGL(k_cache_lookup, grid_fit(k_cache_lookup, n), dim3(NT), 0, st, la);
         // misses, ascending visible position (= ascending anchor id)
-        GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_miss, v.block_sums, st));
-        hipLaunchKernelGGL(k_compact_ids, grid_fit(k_compact_ids, n), dim3(NT), 0, st, v.tmp_a, v.tmp_b, 0, &cnt->n_visible,
-                           v.misses);
+        GSC_TRY(compact_u32(v.tmp_a, &cnt->n_visible, 0, &cnt->n_miss, v.misses, v.block_sums, st));
         if (C >= n) {
             hipLaunchKernelGGL(k_direct_assign, grid_fit(k_direct_assign, n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of,
                                v.line_anchor, v.line_tau, v.line_last, v.vslot, t, cnt);

@@ -1,19 +1,22 @@
 // Raster stage (Section 3.1 splatting + Section 6 RasterizeGaussians) for a
 // batch of images ("segments": one per (viewer, eye)), all in one set of
 // launches:
-//   k_entry_bases      segment -> first entry (counts stay on the device)
-//   k_preprocess       EWA projection, conic, opacity-aware extent, exact
-//                      tile count, depth key                (per entry)
+//   k_preprocess       EWA projection, conic, opacity-aware extent, depth
+//                      key, exact tile spans of footprints up to 4 tile
+//                      rows (per entry); segment bases; clears the ranges
+//   tall spans         one thread per tile row of the taller footprints
 //   depth radix pass   stable sort of entries by float32 depth (the low 32
 //                      bits of the (tile | depth) key, applied per Gaussian
-//                      before duplication)
-//   scan + k_duplicate one (global tile id, entry) pair per covered tile,
+//                      before duplication); the last pass also lays the tile
+//                      counts out in depth order
+//   scan + k_dup_rows / k_dup_big
+//                      one (global tile id, entry) pair per covered tile,
 //                      emitted in depth order (LDS-staged, coalesced)
 //   tile radix pass    stable sort of pairs by global tile id (the high bits)
 //   k_ranges           [start, end) of every tile's run
 //   k_blend            front-to-back compositing, one launch over every
 //                      (segment, tile) of the batch, one block per 16x16
-//                      tile (XCD-aware tile order), LDS-staged Gaussian
+//                      tile (interleaved tile runs per XCD), LDS-staged Gaussian
 //                      batches, block-wide early exit
 // With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
 // key and are sorted after duplication instead; the order is the same.
@@ -33,27 +36,18 @@ __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * block
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
 
-__device__ __forceinline__ int seg_of_entry(const RasterCounters* rc, int nseg, int64_t e) {
-    int s = 0;
-    while (s + 1 < nseg && e >= rc->entry_base[s + 1]) ++s;
-    return s;
-}
-
-__global__ void k_entry_bases(SegTable tab, RasterCounters* rc, int64_t max_entries) {
+// Segment -> first entry, from the segments' device counts (every block of
+// k_preprocess computes it; block 0 publishes it for the later kernels).
+__device__ __forceinline__ int32_t entry_bases(const SegTable& tab, int64_t max_entries, int32_t* base,
+                                               bool& over) {
     int32_t acc = 0;
-    for (int s = 0; s < tab.n; ++s) {
-        rc->entry_base[s] = acc;
-        int32_t n = tab.s[s].nG ? *tab.s[s].nG : tab.s[s].nG_host;
-        acc += n;
+    for (int q = 0; q < tab.n; ++q) {
+        base[q] = acc;
+        acc += tab.s[q].nG ? *tab.s[q].nG : tab.s[q].nG_host;
     }
-    rc->entry_base[tab.n] = acc;
-    rc->overflow = 0;
-    if (acc > max_entries) {
-        rc->overflow |= 2;
-        acc = (int32_t)max_entries;
-    }
-    rc->n_entries = acc;
-    rc->n_echunks = (acc + NT - 1) / NT;
+    base[tab.n] = acc;
+    over = acc > max_entries;
+    return over ? (int32_t)max_entries : acc;
 }
 
 // Minimum of q(d) = a dx^2 + 2 b dx dy + c dy^2 over the closed rectangle
@@ -216,14 +210,28 @@ struct PreArgs {
     int32_t* tall_cnt;   // per chunk
     int32_t* ranges;     // [2 * tiles] cleared here for this batch's ranges
     int64_t n_ranges;
+    int64_t max_entries;
 };
 
 // (at most 128 VGPRs: four waves per SIMD to cover the chain of dependent
 // loads of an entry)
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(PreArgs p) {
     __shared__ uint32_t s_wtall[NT / 64];
+    __shared__ int32_t s_base[kMaxSeg + 1];
+    __shared__ int32_t s_ne;
+    if (threadIdx.x == 0) {
+        bool over;
+        s_ne = entry_bases(p.tab, p.max_entries, s_base, over);
+        if (blockIdx.x == 0) {  // this batch's counters, for the later kernels
+            for (int q = 0; q <= p.tab.n; ++q) p.rc->entry_base[q] = s_base[q];
+            p.rc->overflow = over ? 2 : 0;
+            p.rc->n_entries = s_ne;
+            p.rc->n_echunks = (s_ne + NT - 1) / NT;
+        }
+    }
     for (int64_t i = gtid(); i < p.n_ranges; i += gstride()) p.ranges[i] = 0;
-    const int64_t ne = p.rc->n_entries;
+    __syncthreads();
+    const int64_t ne = s_ne;
     const int lane = threadIdx.x & 63;
     // block-uniform loop: each step covers one chunk of 256 entries, whose
     // tall footprints the block lists together
@@ -239,9 +247,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         int y0 = 0, y1 = -1;
         uint32_t spans[kSmallRows] = {0xffffu, 0xffffu, 0xffffu, 0xffffu};
         if (valid) {
-            si = seg_of_entry(p.rc, p.tab.n, e);
+            while (si + 1 < p.tab.n && e >= s_base[si + 1]) ++si;
             const Seg& s = p.tab.s[si];
-            int64_t g = e - p.rc->entry_base[si];
+            int64_t g = e - s_base[si];
             int64_t src = s.G ? (int64_t)s.G[g] : g;
             float4 l0 = s.L0[src], l1 = s.L1[src], l2 = s.L2[src];
             lb = s.L3[src];
@@ -896,10 +904,10 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
                         Marks* mk) {
     RasterCounters* rc = r.cnt;
     mark(mk, 3, st);
-    hipLaunchKernelGGL(k_entry_bases, dim3(1), dim3(1), 0, st, tab, rc, r.max_entries);
     PreArgs pa;
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
     pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_tiles;
+    pa.max_entries = r.max_entries;
     hipLaunchKernelGGL(k_preprocess, grid_fit(k_preprocess, r.max_entries), dim3(NT), 0, st, pa);
     hipError_t e0 = tall_spans(tab, r, st);
     if (e0 != hipSuccess) return e0;

@@ -101,6 +101,37 @@ __global__ __launch_bounds__(NT) void k_scan_down(const uint32_t* __restrict__ i
     }
 }
 
+// Compaction form of the down-sweep: flags in `in` (0 or 1), and
+// ids[prefix] = i for every flagged i (ascending).
+__global__ __launch_bounds__(NT) void k_scan_compact(const uint32_t* __restrict__ in, int32_t* __restrict__ ids,
+                                                     const int32_t* n_dev, int64_t n_host,
+                                                     const uint32_t* __restrict__ block_sums, int32_t* total) {
+    __shared__ uint32_t wsum[NT / 64];
+    uint32_t part = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += NT) part += block_sums[i];
+    uint32_t carry = block_sum(part, wsum);
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = (int32_t)(carry + block_sums[blockIdx.x]);
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, n_host), SCAN_TILE, b0, b1);
+    for (int64_t base = b0; base < b1; base += SCAN_TILE) {
+        uint32_t v[4], s = 0;
+        int64_t i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v[r] = i0 + r < b1 ? in[i0 + r] : 0u;
+            s += v[r];
+        }
+        uint32_t tot;
+        uint32_t e = carry + block_excl_scan(s, wsum, tot);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (v[r]) ids[e] = (int32_t)(i0 + r);
+            e += v[r];
+        }
+        carry += tot;
+    }
+}
+
 // ------------------------------------------------------------ radix sort
 
 template <typename K>
@@ -319,6 +350,13 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int
                     uint32_t* block_sums, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(NT), 0, st, in, n_dev, n_host, block_sums);
     hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(NT), 0, st, in, out, n_dev, n_host, block_sums, total);
+    return hipGetLastError();
+}
+
+hipError_t compact_u32(const uint32_t* flags, const int32_t* n_dev, int64_t n_host, int32_t* total, int32_t* ids,
+                       uint32_t* block_sums, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(NT), 0, st, flags, n_dev, n_host, block_sums);
+    hipLaunchKernelGGL(k_scan_compact, dim3(kScanBlocks), dim3(NT), 0, st, flags, ids, n_dev, n_host, block_sums, total);
     return hipGetLastError();
 }
 
