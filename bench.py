@@ -269,10 +269,11 @@ def traffic_for(kernel, workload_tag):
 
 
 def cpu_baseline(synth, scene, traj):
-    """The FP64 oracle (plain method, no cache) on three stereo frames of the
-    fly-through (first, middle, last), on all host threads it is given."""
+    """The FP64 oracle (plain method, no cache) on five stereo frames spread
+    evenly over the fly-through (first to last), on all host threads it is
+    given."""
     import oracle
-    sample = [0, len(traj) // 2, len(traj) - 1]
+    sample = [round(i * (len(traj) - 1) / 4) for i in range(5)]
     t0 = time.perf_counter()
     for i in sample:
         L, R = traj[i]
@@ -280,8 +281,8 @@ def cpu_baseline(synth, scene, traj):
     dt = time.perf_counter() - t0
     return {"value": round(len(sample) / dt, 5), "unit": "stereo frames/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": "3 stereo frames (0, 149, 299) of the fly-through at 2048x1080, plain FP64 method "
-                      "(no cache), %.1f s" % dt}
+            "sample": "%d stereo frames %s of the fly-through at 2048x1080, plain FP64 method "
+                      "(no cache), %.1f s" % (len(sample), tuple(sample), dt)}
 
 
 # --------------------------------------------------------------------------- frames mode
