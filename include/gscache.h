@@ -230,15 +230,17 @@ int gsc_count_work(gsc_ctx* ctx, int enable);
 #define GSC_STAGE_SCHEDULE 0    /* unified-camera selection, cache schedule */
 #define GSC_STAGE_DERIVE 1      /* MLP derivation of the misses (MFMA) */
 #define GSC_STAGE_COMPOSE 2     /* depth update, render buffer */
-#define GSC_STAGE_PREPROCESS 3  /* projection, conic, extent, tile counts (both eyes) */
-#define GSC_STAGE_DEPTH_SORT 4  /* per-Gaussian depth radix pass */
-#define GSC_STAGE_PAIR_SCAN 5   /* pair offsets in depth order */
-#define GSC_STAGE_DUP_ROWS 6    /* pair emission, footprints of up to 4 tile rows */
-#define GSC_STAGE_DUP_BIG 7     /* pair emission, taller footprints */
-#define GSC_STAGE_TILE_SORT 8   /* tile-id radix passes over the pairs */
-#define GSC_STAGE_RANGES 9      /* per-tile ranges */
-#define GSC_STAGE_BLEND 10      /* persistent blend */
-#define GSC_NUM_STAGES 11
+#define GSC_STAGE_PREPROCESS 3  /* projection, conic, extent, spans of footprints up to 4 tile rows */
+#define GSC_STAGE_TALL_SPANS 4  /* row spans and tile counts of taller footprints */
+#define GSC_STAGE_DEPTH_SORT 5  /* per-Gaussian depth radix passes */
+#define GSC_STAGE_PAIR_SCAN 6   /* pair offsets in depth order */
+#define GSC_STAGE_DUP_ROWS 7    /* pair emission, footprints of up to 4 tile rows */
+#define GSC_STAGE_TALL_LIST 8   /* dense list of the taller footprints */
+#define GSC_STAGE_DUP_BIG 9     /* pair emission, taller footprints */
+#define GSC_STAGE_TILE_SORT 10  /* tile-id radix passes over the pairs */
+#define GSC_STAGE_RANGES 11     /* per-tile ranges */
+#define GSC_STAGE_BLEND 12      /* blend */
+#define GSC_NUM_STAGES 13
 /* Switch timing on (enable != 0) or off; clears what was recorded.  Waits
  * for the stream. */
 int gsc_timing(gsc_ctx* ctx, int enable);

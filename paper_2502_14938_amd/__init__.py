@@ -152,8 +152,8 @@ def _current_stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-STAGES = ("schedule", "derive", "compose", "preprocess", "depth_sort", "pair_scan", "dup_rows", "dup_big",
-          "tile_sort", "ranges", "blend")
+STAGES = ("schedule", "derive", "compose", "preprocess", "tall_spans", "depth_sort", "pair_scan", "dup_rows",
+          "tall_list", "dup_big", "tile_sort", "ranges", "blend")
 
 
 class Renderer:

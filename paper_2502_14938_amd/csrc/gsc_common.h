@@ -231,7 +231,7 @@ struct DeriveArgs {
 };
 // Optional stage timing: HIP events recorded on the stream at the stage
 // boundaries of one frame (GSC_STAGE_* order of the public header).
-constexpr int kNumStages = 11;
+constexpr int kNumStages = 13;
 struct Marks {
     hipEvent_t ev[kNumStages + 1];
     uint32_t recorded;  // bit i: ev[i] recorded this frame

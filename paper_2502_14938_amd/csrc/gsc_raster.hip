@@ -909,9 +909,10 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_tiles;
     pa.max_entries = r.max_entries;
     hipLaunchKernelGGL(k_preprocess, grid_fit(k_preprocess, r.max_entries), dim3(NT), 0, st, pa);
+    mark(mk, 4, st);
     hipError_t e0 = tall_spans(tab, r, st);
     if (e0 != hipSuccess) return e0;
-    mark(mk, 4, st);
+    mark(mk, 5, st);
     const int tile_bits = bits_for(tab.total_tiles);
     DupArgs da;
     da.tab = tab; da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
@@ -924,54 +925,56 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st, r.ntiles,
                            r.scnt);
         if (e != hipSuccess) return e;
-        mark(mk, 5, st);
+        mark(mk, 6, st);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
-        mark(mk, 6, st);
+        mark(mk, 7, st);
         da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
         hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
-        mark(mk, 7, st);
+        mark(mk, 8, st);
         e = tall_list(r, st);
         if (e != hipSuccess) return e;
+        mark(mk, 9, st);
         hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.tall_list);
-        mark(mk, 8, st);
+        mark(mk, 10, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
         e = radix_sort_u32(r.pkey, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
-        mark(mk, 9, st);
+        mark(mk, 11, st);
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
                            r.ranges, (uint32_t)tab.total_tiles);
     } else {
-        mark(mk, 5, st);  // no per-Gaussian depth pass in this mode
+        mark(mk, 6, st);  // no per-Gaussian depth pass in this mode
         e = scan_u32(r.ntiles, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
-        mark(mk, 6, st);
+        mark(mk, 7, st);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
         hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
-        mark(mk, 7, st);
+        mark(mk, 8, st);
         e = tall_list(r, st);
         if (e != hipSuccess) return e;
+        mark(mk, 9, st);
         hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.tall_list);
-        mark(mk, 8, st);
+        mark(mk, 10, st);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
-        mark(mk, 9, st);
+        mark(mk, 11, st);
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
                            32, r.ranges, (uint32_t)tab.total_tiles);
     }
     r.order = nullptr;
-    mark(mk, 10, st);
+    mark(mk, 12, st);
     if (count_work)
         hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
                            r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
     else
         hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
                            r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
-    mark(mk, 11, st);
+    mark(mk, 13, st);
     return hipGetLastError();
 }
 
