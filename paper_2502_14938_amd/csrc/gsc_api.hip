@@ -136,7 +136,7 @@ hipError_t view_layout(View& v, int64_t n, int64_t C, int k, Fn&& A) {
     hipError_t e;
 #define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
     A_(v.slot_of, n); A_(v.line_anchor, C); A_(v.line_tau, C); A_(v.line_last, C);
-    A_(v.L0, C * k); A_(v.L1, C * k); A_(v.L2, C * k); A_(v.L3, C * k);
+    A_(v.L0, C * k); A_(v.L1, C * k); A_(v.L2, C * k); A_(v.L3, C * k); A_(v.line_mask, C);
     A_(v.pu_hist, 64 * 4); A_(v.visible, n); A_(v.vslot, n);
     A_(v.tmp_a, m); A_(v.tmp_b, m); A_(v.tmp_c, m); A_(v.tmp_d, m);
     A_(v.evict_hist, 64); A_(v.evict_scan_n, 1);

@@ -128,6 +128,7 @@ struct View {
     int32_t* slot_of = nullptr; // [n] line of each anchor or -1
     int32_t* line_anchor = nullptr, *line_tau = nullptr, *line_last = nullptr;  // [C]
     float4* L0 = nullptr, *L1 = nullptr, *L2 = nullptr;  // [C*k]
+    uint16_t* line_mask = nullptr;  // [C] bit j: entry j of the line has alpha > 0
     float* L3 = nullptr;
     float* pu_hist = nullptr;   // [64][4] unified camera centre per frame (t mod 64)
     int32_t* visible = nullptr; // [n]

@@ -343,9 +343,9 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // ------------------------------------------------------------- compose
 // G_t = [(i, j) : i visible ascending, j ascending, alpha_ij > 0]; each entry
 // is the cache entry (line * k + j).
-__global__ __launch_bounds__(NT) void k_compose_count(const int32_t* __restrict__ vslot, const float4* __restrict__ L0,
-                                                      int k, Counters* cnt, uint32_t* __restrict__ count,
-                                                      int32_t dmax, int32_t guide) {
+__global__ __launch_bounds__(NT) void k_compose_count(const int32_t* __restrict__ vslot,
+                                                      const uint16_t* __restrict__ line_mask, Counters* cnt,
+                                                      uint32_t* __restrict__ count, int32_t dmax, int32_t guide) {
     if (gtid() == 0) depth_update(cnt, dmax, guide);  // eq. 4, from this frame's counts
     int32_t nv = cnt->n_visible;
     for (int64_t i = gtid(); i < nv; i += gstride()) {
@@ -353,32 +353,24 @@ __global__ __launch_bounds__(NT) void k_compose_count(const int32_t* __restrict_
             count[i] = 0u;
             continue;
         }
-        int64_t base = (int64_t)vslot[i] * k;
-        // all k opacity loads in flight at once (k <= kMaxK)
-        float w[kMaxK];
-#pragma unroll
-        for (int j = 0; j < kMaxK; ++j) w[j] = j < k ? L0[base + j].w : 0.f;
-        uint32_t c = 0;
-#pragma unroll
-        for (int j = 0; j < kMaxK; ++j) c += w[j] > 0.f ? 1u : 0u;
-        count[i] = c;
+        count[i] = (uint32_t)__popc(line_mask[vslot[i]]);  // set by the derivation
     }
 }
 
-__global__ __launch_bounds__(NT) void k_compose_write(const int32_t* __restrict__ vslot, const float4* __restrict__ L0,
-                                                      int k, Counters* cnt, const uint32_t* __restrict__ off,
-                                                      int32_t* __restrict__ G) {
+__global__ __launch_bounds__(NT) void k_compose_write(const int32_t* __restrict__ vslot,
+                                                      const uint16_t* __restrict__ line_mask, int k, Counters* cnt,
+                                                      const uint32_t* __restrict__ off, int32_t* __restrict__ G) {
     int32_t nv = cnt->n_visible;
     for (int64_t i = gtid(); i < nv; i += gstride()) {
         if (vslot[i] < 0) continue;
-        int64_t base = (int64_t)vslot[i] * k;
-        float w[kMaxK];
-#pragma unroll
-        for (int j = 0; j < kMaxK; ++j) w[j] = j < k ? L0[base + j].w : 0.f;
+        const int64_t base = (int64_t)vslot[i] * k;
+        uint32_t mk = line_mask[vslot[i]];
         uint32_t o = off[i];
-#pragma unroll
-        for (int j = 0; j < kMaxK; ++j)
-            if (w[j] > 0.f) G[o++] = (int32_t)(base + j);
+        while (mk) {
+            const int j = __ffs(mk) - 1;
+            mk &= mk - 1u;
+            G[o++] = (int32_t)(base + j);
+        }
     }
 }
 
@@ -463,7 +455,7 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
         MfmaDeriveArgs m;
         m.posr = sc.posr; m.feat = sc.feat; m.scale = sc.scale; m.offsets = sc.offsets; m.k = sc.k;
         m.visible = v.visible; m.misses = v.misses; m.vslot = v.vslot; m.L0 = v.L0; m.L1 = v.L1; m.L2 = v.L2;
-        m.L3 = v.L3; m.cam_pos[0] = a.cam.pos[0]; m.cam_pos[1] = a.cam.pos[1]; m.cam_pos[2] = a.cam.pos[2];
+        m.L3 = v.L3; m.line_mask = v.line_mask; m.cam_pos[0] = a.cam.pos[0]; m.cam_pos[1] = a.cam.pos[1]; m.cam_pos[2] = a.cam.pos[2];
         m.n_miss = &cnt->n_miss; m.mode = a.precision;
         m.fr.l1_f32 = sc.fr_l1_f32; m.fr.l2_f32 = sc.fr_l2_f32; m.fr.l1_bf16 = sc.fr_l1_bf16;
         m.fr.l2_bf16 = sc.fr_l2_bf16; m.fr.l1_fp8 = sc.fr_l1_fp8; m.fr.l2_fp8 = sc.fr_l2_fp8;
@@ -473,10 +465,11 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     }
     mark(mk, 2, st);
     // compose the render buffer
-    hipLaunchKernelGGL(k_compose_count, grid_fit(k_compose_count, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_a,
-                       a.d_max, a.guide);
+    hipLaunchKernelGGL(k_compose_count, grid_fit(k_compose_count, n), dim3(NT), 0, st, v.vslot, v.line_mask, cnt,
+                       v.tmp_a, a.d_max, a.guide);
     GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_gauss, v.block_sums, st));
-    hipLaunchKernelGGL(k_compose_write, grid_fit(k_compose_write, n), dim3(NT), 0, st, v.vslot, v.L0, sc.k, cnt, v.tmp_b, v.G);
+    hipLaunchKernelGGL(k_compose_write, grid_fit(k_compose_write, n), dim3(NT), 0, st, v.vslot, v.line_mask, sc.k, cnt,
+                       v.tmp_b, v.G);
     mark(mk, 3, st);
     return hipGetLastError();
 }

@@ -48,6 +48,7 @@ struct MfmaDeriveArgs {
     float4* L1;
     float4* L2;
     float* L3;
+    uint16_t* line_mask;  // [lines] bit j: Gaussian j has alpha > 0 (may be null)
     float cam_pos[3];
     const int32_t* n_miss;
     int mode;  // GSC_PREC_*

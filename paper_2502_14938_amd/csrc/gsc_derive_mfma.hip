@@ -326,6 +326,17 @@ __global__ __launch_bounds__(NT) void k_derive_mfma(MfmaDeriveArgs a) {
                 a.L2[e] = make_float4(S[4], S[5], r, gg);
                 a.L3[e] = bb;
             }
+            // the line's mask of kept Gaussians (alpha > 0, the render
+            // buffer's test), from the same alphas
+            if (a.line_mask && lane < 16) {
+                const int m = tile * 16 + lane;
+                const int32_t line = sLine[w][lane];
+                if (m < n && line >= 0) {
+                    uint32_t mk = 0;
+                    for (int j = 0; j < k; ++j) mk |= tanhf(O[w][lane][j]) > 0.f ? 1u << j : 0u;
+                    a.line_mask[line] = (uint16_t)mk;
+                }
+            }
         }
         __syncthreads();
     }
