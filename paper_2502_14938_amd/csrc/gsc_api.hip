@@ -523,7 +523,10 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
         View& v = c->view[c->nviews == 1 ? 0 : e];
         Seg& s = tab.s[e];
         s.L0 = v.L0; s.L1 = v.L1; s.L2 = v.L2; s.L3 = v.L3; s.G = v.G; s.nG = &v.cnt->n_gauss; s.nG_host = 0;
-        s.anchor_pos = c->scene.posr; s.line_anchor = v.line_anchor; s.k = c->scene.k;
+        // direct-mapped cache (the schedule gives anchor a line a): the
+        // line index is the anchor, no lookup needed
+        const bool direct = (c->cfg.flags & GSC_FLAG_REUSE) && c->nviews == 1 && v.C >= c->scene.n;
+        s.anchor_pos = c->scene.posr; s.line_anchor = direct ? nullptr : v.line_anchor; s.k = c->scene.k;
         seg_camera(s, c->eye[e]);
         s.tile_base = tiles;
         tiles += s.ntx * s.nty;

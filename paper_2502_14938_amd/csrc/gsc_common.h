@@ -69,7 +69,7 @@ struct Seg {
     const int32_t* nG;  // device count of G (nullptr = nG_host)
     int32_t nG_host;
     const float4* anchor_pos;    // anchors (x, y, z, radius); nullptr: L0 holds absolute positions
-    const int32_t* line_anchor;  // anchor of each cache line
+    const int32_t* line_anchor;  // anchor of each cache line (nullptr: line i belongs to anchor i)
     int32_t k;                   // entries per cache line
     int32_t W, H, ntx, nty;
     int32_t tile_base;  // first global tile id of this image

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // from the exact FP32 anchor, the second as stored
             double ax = 0.0, ay = 0.0, az = 0.0;
             if (s.anchor_pos) {
-                const int32_t an = s.line_anchor[src / s.k];  // valid for every line in the buffer
+                const int32_t an = s.line_anchor ? s.line_anchor[src / s.k] : (int32_t)(src / s.k);  // valid for every line in the buffer
                 const float4 ap = s.anchor_pos[an >= 0 ? an : 0];
                 ax = ap.x; ay = ap.y; az = ap.z;
             }

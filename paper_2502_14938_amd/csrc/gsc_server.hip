@@ -361,7 +361,8 @@ int gsc_server_step(gsc_server* s) {
         for (int eye = 0; eye < 2; ++eye) {
             Seg& sg = tab.s[tab.n++];
             sg.L0 = v.v.L0; sg.L1 = v.v.L1; sg.L2 = v.v.L2; sg.L3 = v.v.L3;
-            sg.anchor_pos = c->scene.posr; sg.line_anchor = v.v.line_anchor; sg.k = c->scene.k;
+            const bool direct = (c->cfg.flags & GSC_FLAG_REUSE) && v.v.C >= c->scene.n;  // line a = anchor a
+            sg.anchor_pos = c->scene.posr; sg.line_anchor = direct ? nullptr : v.v.line_anchor; sg.k = c->scene.k;
             sg.G = v.v.G; sg.nG = &v.v.cnt->n_gauss; sg.nG_host = 0;
             seg_camera(sg, r.eye[eye]);
             sg.tile_base = tiles;
