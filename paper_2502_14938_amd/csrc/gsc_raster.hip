@@ -638,10 +638,15 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
         const int64_t e = tall_e[i];
         const int64_t r0 = rowoff[i], r1 = r0 + rowcnt[i] < cap ? r0 + rowcnt[i] : cap;
         uint32_t count = 0;
-        for (int64_t q = r0; q < r1; ++q) {
-            const uint32_t sp = spans[q];
-            const int lo = sp & 0xffff, hi = sp >> 16;
-            count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+        for (int64_t q0 = r0; q0 < r1; q0 += 4) {  // four independent loads per step
+            uint32_t sp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sp[u] = q0 + u < r1 ? spans[q0 + u] : 0x0000ffffu;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int lo = sp[u] & 0xffff, hi = sp[u] >> 16;
+                count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+            }
         }
         float4* rp = rec + kRec * e;
         rp[2].w = __uint_as_float(count);
