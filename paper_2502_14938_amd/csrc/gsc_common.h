@@ -13,8 +13,8 @@
 namespace gsc {
 
 constexpr int kTile = 16;             // 16x16 pixel tiles
-constexpr int kBlendThreads = 128;    // two pixels of a 16x16 tile per thread (rows y, y + 8)
-constexpr int kBlendBatch = 256;      // Gaussians staged in LDS per step
+constexpr int kBlendThreads = 64;     // one wave per 16x16 tile, four pixels per thread (blend)
+constexpr int kBlendBatch = 128;      // Gaussians staged in LDS per step (blend)
 constexpr int kBlendRun = 128;        // consecutive tiles one XCD takes in a row (blend)
 constexpr int kMaxSeg = 16;           // (viewer, eye) images per raster batch
 constexpr int kGridBlocks = 2048;     // fixed grid of the grid-stride kernels

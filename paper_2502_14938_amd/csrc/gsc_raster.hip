@@ -699,35 +699,31 @@ __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const
 }
 
 
-// One block per global tile; the block -> tile map gives each XCD runs of
-// kBlendRun adjacent tiles, interleaved over the image, so Gaussians shared
-// by neighbouring tiles are gathered through one L2 and the XCDs get equal
-// shares of dense and sparse image regions.  Gaussians are staged in LDS 256
-// at a time; the block stops as soon as every pixel has reached the
-// transmittance floor.
-// One 16x16 tile per block of 128 threads; thread t owns the pixels
-// (t & 15, t >> 4) and (t & 15, (t >> 4) + 8) of the tile, which share their
-// column offset dx.  Gaussians of the tile's depth-sorted list are staged in
-// LDS, 256 at a time, with the conic pre-scaled so that the exponent is
-// base 2 and the log2 of the opacity folded in:
+// One wave (one block) per global tile; the block -> tile map gives each
+// XCD runs of kBlendRun adjacent tiles, interleaved over the image, so
+// Gaussians shared by neighbouring tiles are gathered through one L2 and the
+// XCDs get equal shares of dense and sparse image regions.  Thread t owns the
+// four pixels (t & 15, (t >> 4) + 4 i), i < 4, of its 16x16 tile, which share
+// their column offset dx and the per-Gaussian terms that depend on it only.
+// Gaussians of the tile's depth-sorted list are staged in LDS, kBlendBatch at
+// a time, with the conic pre-scaled so that the exponent is base 2 and the
+// log2 of the opacity folded in:
 //   alpha = min(0.99, 2^(a' dx^2 + b' dx dy + c' dy^2 + log2 o)),
 //   a' = -log2(e)/2 a, b' = -log2(e) b, c' = -log2(e)/2 c,
 // equal to min(0.99, o exp(-q/2)) of the conic quadratic q (the hardware
 // exp2 flushes results below 2^-126 to zero, far below the 1/255 cut-off).
-// Per pixel: skip
-// alpha < 1/255; stop before a Gaussian that would take T(1 - alpha) below
-// 1e-4; otherwise composite.  The composite step is predicated (no branches);
-// a wave leaves a batch early once all its pixels are done, the block once
-// every pixel is.
+// Per pixel: skip alpha < 1/255; stop before a Gaussian that would take
+// T(1 - alpha) below 1e-4; otherwise composite.  The composite step is
+// predicated (no branches); the wave stops once all its pixels are done.
+static_assert(kBlendThreads == 64, "k_blend maps one wave of 64 threads onto a 16x16 tile");
 template <bool kCount>
 __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int32_t* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ vals,
-                                                          const float4* __restrict__ rec, uint32_t max_entries,
-                                                          int32_t* __restrict__ tile_eval) {
-    __shared__ float4 sA[kBlendBatch];  // mx, my, a', b'
-    __shared__ float4 sB[kBlendBatch];  // c', log2 o, r, g
-    __shared__ float sC[kBlendBatch];   // b
-    __shared__ int32_t sEval[2 * (kBlendThreads / 64)];
+                                              const uint32_t* __restrict__ vals, const float4* __restrict__ rec,
+                                              uint32_t max_entries, int32_t* __restrict__ tile_eval) {
+    constexpr int BB = kBlendBatch;
+    __shared__ float4 sA[BB];  // mx, my, a', b'
+    __shared__ float4 sB[BB];  // c', log2 o, r, g
+    __shared__ float sC[BB];   // b
     constexpr float kL2e = 1.4426950408889634f;
     const int total = tab.total_tiles;
     // Blocks go to the 8 XCDs round-robin (block b to XCD b mod 8).  Each
@@ -735,26 +731,34 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
     // tiles, one per XCD, so neighbouring tiles (which share Gaussians)
     // meet in one L2 while every XCD draws tiles from all over the image;
     // the last partial run keeps the identity map.
-    const int b = blockIdx.x, sc = b / (8 * kBlendRun);
-    const int gt = (sc + 1) * 8 * kBlendRun <= total ? sc * 8 * kBlendRun + (b & 7) * kBlendRun + (b % (8 * kBlendRun)) / 8
-                                                      : b;
+    const int bb = blockIdx.x, sc = bb / (8 * kBlendRun);
+    const int gt = (sc + 1) * 8 * kBlendRun <= total ? sc * 8 * kBlendRun + (bb & 7) * kBlendRun + (bb % (8 * kBlendRun)) / 8
+                                                      : bb;
     int si = 0;
     while (si + 1 < tab.n && gt >= tab.s[si + 1].tile_base) ++si;
     const Seg& s = tab.s[si];
     const int lt = gt - s.tile_base;
     const int tx = lt % s.ntx, ty = lt / s.ntx;
+    // thread t owns the pixels (t & 15, (t >> 4) + 4 i), i < 4, of the tile
     const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-    const int py0 = ty * kTile + (threadIdx.x / kTile), py1 = py0 + kTile / 2;
-    const bool in0 = px < s.W && py0 < s.H, in1 = px < s.W && py1 < s.H;
-    const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f, fy1 = (float)py1 + 0.5f;
+    const float fx = (float)px + 0.5f;
+    int py[4];
+    float fy[4], T[4], cr[4], cg[4], cbl[4];
+    int32_t nc[4], stp[4];
+    bool d[4], in[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        py[i] = ty * kTile + (threadIdx.x >> 4) + 4 * i;
+        in[i] = px < s.W && py[i] < s.H;
+        fy[i] = (float)py[i] + 0.5f;
+        T[i] = 1.0f; cr[i] = 0.f; cg[i] = 0.f; cbl[i] = 0.f;
+        nc[i] = 0; stp[i] = -1;
+        d[i] = !in[i];
+    }
     const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    float T0 = 1.0f, r0 = 0.f, g0 = 0.f, b0 = 0.f;
-    float T1 = 1.0f, r1 = 0.f, g1 = 0.f, b1 = 0.f;
-    int32_t nc0 = 0, nc1 = 0, stop0 = -1, stop1 = -1;
-    bool d0 = !in0, d1 = !in1;
-    for (int32_t base = start; base < end; base += kBlendBatch) {
-        if (__syncthreads_count(d0 && d1) == kBlendThreads) break;
-        for (int l = threadIdx.x; l < kBlendBatch; l += kBlendThreads) {
+    for (int32_t base = start; base < end; base += BB) {
+        if (__all(d[0] && d[1] && d[2] && d[3])) break;
+        for (int l = threadIdx.x; l < BB; l += kBlendThreads) {
             const int32_t i = base + l;
             if (i < end) {
                 uint32_t e = vals[i];
@@ -767,84 +771,65 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
             }
         }
         __syncthreads();
-        const int nb = min(kBlendBatch, end - base);
-        if (!(d0 && d1)) {
-            for (int k = 0; k < nb; ++k) {
-                if ((k & 15) == 0 && __all(d0 && d1)) break;
-                const float4 A = sA[k];
-                const float4 B = sB[k];
-                const float dx = fx - A.x;
-                const float u = A.w * dx;
-                const float t = fmaf(A.z * dx, dx, B.y);
-                const float e0 = fy0 - A.y, e1 = fy1 - A.y;
-                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e0, fmaf(B.x, e0, u), t)));
-                const float al1 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e1, fmaf(B.x, e1, u), t)));
+        const int nb = min(BB, end - base);
+        for (int k = 0; k < nb; ++k) {
+            if ((k & 15) == 0 && __all(d[0] && d[1] && d[2] && d[3])) break;
+            const float4 A = sA[k];
+            const float4 B = sB[k];
+            const float cb = sC[k];
+            const float dx = fx - A.x;
+            const float u = A.w * dx;
+            const float t = fmaf(A.z * dx, dx, B.y);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float e0 = fy[i] - A.y;
+                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e0, fmaf(B.x, e0, u), t)));
                 // weight alpha T; the next transmittance T (1 - alpha) as T - alpha T
-                const float wf0 = al0 * T0, wf1 = al1 * T1;
-                const float tn0 = T0 - wf0, tn1 = T1 - wf1;
-                const bool u0 = !d0 && al0 >= kMinAlpha, u1 = !d1 && al1 >= kMinAlpha;
-                const bool ok0 = tn0 >= kTStop, ok1 = tn1 >= kTStop;
-                const bool s0 = u0 && !ok0, s1 = u1 && !ok1;
-                const bool a0 = u0 && ok0, a1 = u1 && ok1;
-                const float w0 = a0 ? wf0 : 0.f, w1 = a1 ? wf1 : 0.f;
-                const float cb = sC[k];
-                r0 = fmaf(B.z, w0, r0); g0 = fmaf(B.w, w0, g0); b0 = fmaf(cb, w0, b0);
-                r1 = fmaf(B.z, w1, r1); g1 = fmaf(B.w, w1, g1); b1 = fmaf(cb, w1, b1);
-                T0 = a0 ? tn0 : T0;
-                T1 = a1 ? tn1 : T1;
+                const float wf = al * T[i];
+                const float tn = T[i] - wf;
+                const bool uu = !d[i] && al >= kMinAlpha;
+                const bool ok = tn >= kTStop;
+                const bool st = uu && !ok;
+                const bool ac = uu && ok;
+                const float w = ac ? wf : 0.f;
+                cr[i] = fmaf(B.z, w, cr[i]); cg[i] = fmaf(B.w, w, cg[i]); cbl[i] = fmaf(cb, w, cbl[i]);
+                T[i] = ac ? tn : T[i];
                 if (kCount) {
-                    nc0 += a0 ? 1 : 0;
-                    nc1 += a1 ? 1 : 0;
-                    stop0 = s0 ? base + k : stop0;
-                    stop1 = s1 ? base + k : stop1;
+                    nc[i] += ac ? 1 : 0;
+                    stp[i] = st ? base + k : stp[i];
                 }
-                d0 = d0 || s0;
-                d1 = d1 || s1;
+                d[i] = d[i] || st;
             }
         }
         __syncthreads();  // the batch is read before the next one is staged
     }
-    // work of this tile (visits, contributions): a pixel visits its list up to
-    // and including the Gaussian that ends it; one sum per wave, then per block
     if (kCount) {
         const int32_t len = end - start;
-        int32_t ne = (in0 ? (stop0 >= 0 ? stop0 - start + 1 : len) : 0) + (in1 ? (stop1 >= 0 ? stop1 - start + 1 : len) : 0);
-        int32_t nce = nc0 + nc1;
+        int32_t ne = 0, nce = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ne += in[i] ? (stp[i] >= 0 ? stp[i] - start + 1 : len) : 0;
+            nce += nc[i];
+        }
         for (int o = 32; o > 0; o >>= 1) {
             ne += __shfl_xor(ne, o);
             nce += __shfl_xor(nce, o);
         }
-        if ((threadIdx.x & 63) == 0) {
-            sEval[threadIdx.x >> 6] = ne;
-            sEval[kBlendThreads / 64 + (threadIdx.x >> 6)] = nce;
-        }
-        __syncthreads();
         if (threadIdx.x == 0) {
-            int32_t te = 0, tc = 0;
-            for (int w = 0; w < kBlendThreads / 64; ++w) {
-                te += sEval[w];
-                tc += sEval[kBlendThreads / 64 + w];
-            }
-            tile_eval[2 * gt] = te;
-            tile_eval[2 * gt + 1] = tc;
+            tile_eval[2 * gt] = ne;
+            tile_eval[2 * gt + 1] = nce;
         }
     }
     const int64_t np = (int64_t)s.W * s.H;
-    if (in0) {
-        const int64_t p = (int64_t)py0 * s.W + px;
-        s.out_rgb[p] = r0;
-        s.out_rgb[np + p] = g0;
-        s.out_rgb[2 * np + p] = b0;
-        if (s.out_T) s.out_T[p] = T0;
-        if (kCount && s.out_nc) s.out_nc[p] = nc0;
-    }
-    if (in1) {
-        const int64_t p = (int64_t)py1 * s.W + px;
-        s.out_rgb[p] = r1;
-        s.out_rgb[np + p] = g1;
-        s.out_rgb[2 * np + p] = b1;
-        if (s.out_T) s.out_T[p] = T1;
-        if (kCount && s.out_nc) s.out_nc[p] = nc1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!in[i]) continue;
+        const int64_t p = (int64_t)py[i] * s.W + px;
+        s.out_rgb[p] = cr[i];
+        s.out_rgb[np + p] = cg[i];
+        s.out_rgb[2 * np + p] = cbl[i];
+        if (s.out_T) s.out_T[p] = T[i];
+        if (kCount && s.out_nc) s.out_nc[p] = nc[i];
     }
 }
 
