@@ -788,9 +788,8 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
                 const float wf = al * T[i];
                 const float tn = T[i] - wf;
                 const bool uu = !d[i] && al >= kMinAlpha;
-                const bool ok = tn >= kTStop;
-                const bool st = uu && !ok;
-                const bool ac = uu && ok;
+                const bool ac = uu && tn >= kTStop;  // composite
+                const bool st = uu != ac;            // stop here (uu and not ac)
                 const float w = ac ? wf : 0.f;
                 cr[i] = fmaf(B.z, w, cr[i]); cg[i] = fmaf(B.w, w, cg[i]); cbl[i] = fmaf(cb, w, cbl[i]);
                 T[i] = ac ? tn : T[i];
