@@ -760,7 +760,14 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         if (__all(d[0] && d[1] && d[2] && d[3])) break;
         for (int l = threadIdx.x; l < BB; l += kBlendThreads) {
             const int32_t i = base + l;
-            if (i < end) {
+            if (i >= end) {
+                // padding past the tile's last entry: alpha = 2^-inf = 0 is
+                // below the 1/255 cut, so these change no pixel and the
+                // unrolled loop below needs no bound of its own
+                sA[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+                sB[l] = make_float4(0.f, -INFINITY, 0.f, 0.f);
+                sC[l] = 0.f;
+            } else {
                 uint32_t e = vals[i];
                 e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
                 const float4* rp = rec + kRec * (int64_t)e;
@@ -772,32 +779,39 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         }
         __syncthreads();
         const int nb = min(BB, end - base);
-        for (int k = 0; k < nb; ++k) {
-            if ((k & 15) == 0 && __all(d[0] && d[1] && d[2] && d[3])) break;
-            const float4 A = sA[k];
-            const float4 B = sB[k];
-            const float cb = sC[k];
-            const float dx = fx - A.x;
-            const float u = A.w * dx;
-            const float t = fmaf(A.z * dx, dx, B.y);
+        // groups of 8: the done flags stay in scalar masks inside a group
+        // and the LDS reads take immediate offsets; the padding above makes
+        // a partial last group safe
+        for (int k0 = 0; k0 < nb; k0 += 8) {
+            if (__all(d[0] && d[1] && d[2] && d[3])) break;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float e0 = fy[i] - A.y;
-                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e0, fmaf(B.x, e0, u), t)));
-                // weight alpha T; the next transmittance T (1 - alpha) as T - alpha T
-                const float wf = al * T[i];
-                const float tn = T[i] - wf;
-                const bool uu = !d[i] && al >= kMinAlpha;
-                const bool ac = uu && tn >= kTStop;  // composite
-                const bool st = uu != ac;            // stop here (uu and not ac)
-                const float w = ac ? wf : 0.f;
-                cr[i] = fmaf(B.z, w, cr[i]); cg[i] = fmaf(B.w, w, cg[i]); cbl[i] = fmaf(cb, w, cbl[i]);
-                T[i] = ac ? tn : T[i];
-                if (kCount) {
-                    nc[i] += ac ? 1 : 0;
-                    stp[i] = st ? base + k : stp[i];
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = k0 + kk;
+                const float4 A = sA[k];
+                const float4 B = sB[k];
+                const float cb = sC[k];
+                const float dx = fx - A.x;
+                const float u = A.w * dx;
+                const float t = fmaf(A.z * dx, dx, B.y);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float e0 = fy[i] - A.y;
+                    const float al = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(e0, fmaf(B.x, e0, u), t)));
+                    // weight alpha T; the next transmittance T (1 - alpha) as T - alpha T
+                    const float wf = al * T[i];
+                    const float tn = T[i] - wf;
+                    const bool uu = !d[i] && al >= kMinAlpha;
+                    const bool ac = uu && tn >= kTStop;  // composite
+                    const bool st = uu != ac;            // stop here (uu and not ac)
+                    const float w = ac ? wf : 0.f;
+                    cr[i] = fmaf(B.z, w, cr[i]); cg[i] = fmaf(B.w, w, cg[i]); cbl[i] = fmaf(cb, w, cbl[i]);
+                    T[i] = ac ? tn : T[i];
+                    if (kCount) {
+                        nc[i] += ac ? 1 : 0;
+                        stp[i] = st ? base + k : stp[i];
+                    }
+                    d[i] = d[i] || st;
                 }
-                d[i] = d[i] || st;
             }
         }
         __syncthreads();  // the batch is read before the next one is staged
