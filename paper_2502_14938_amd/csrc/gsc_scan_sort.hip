@@ -139,18 +139,22 @@ __device__ __forceinline__ uint32_t digit(K key, int shift, uint32_t mask) {
     return (uint32_t)(key >> shift) & mask;
 }
 
-// Lanes of the wave holding the same BITS-bit digit (among the valid ones),
-// from one ballot per digit bit.
+// Lanes of the wave holding the same BITS-bit digit (among the valid ones).
+// A lane differs from this one where some digit bit's ballot differs from
+// this lane's own bit, so the complement of OR over bits of (ballot XOR own
+// bit replicated to 32 bits), in two 32-bit halves, is the peer set.
 template <int BITS>
 __device__ __forceinline__ uint64_t peers_of(uint32_t d, bool valid) {
-    uint64_t m = __ballot(valid);
+    const uint64_t vb = __ballot(valid);
+    uint32_t lo = ~(uint32_t)vb, hi = ~(uint32_t)(vb >> 32);
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
+        const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);  // bit b: 0 or all ones
+        const uint64_t bb = __ballot(t != 0u);
+        lo |= (uint32_t)bb ^ t;
+        hi |= (uint32_t)(bb >> 32) ^ t;
     }
-    return m;
+    return ~(((uint64_t)hi << 32) | (uint64_t)lo);
 }
 
 // SORT_IPT consecutive keys starting at a 16-byte aligned element.
@@ -236,14 +240,25 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
         __syncthreads();
         K key[SORT_IPT];
         uint32_t val[SORT_IPT], dg[SORT_IPT], lr[SORT_IPT];
-        // issue every load of the sub-tile before any ranking work
+        // issue every load of the sub-tile before any ranking work; a full
+        // sub-tile needs no per-element bound
+        const int64_t i0 = base + w * SORT_WSEG + lane;
+        if (base + SORT_TILE <= b1) {
 #pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            int64_t i = base + w * SORT_WSEG + r * 64 + lane;
-            bool valid = i < b1;
-            key[r] = valid ? kin[i] : (K)0;
-            val[r] = valid ? vin[i] : 0u;
-            dg[r] = valid ? digit(key[r], shift, mask) : 0xffffffffu;
+            for (int r = 0; r < SORT_IPT; ++r) {
+                key[r] = kin[i0 + r * 64];
+                val[r] = vin[i0 + r * 64];
+            }
+#pragma unroll
+            for (int r = 0; r < SORT_IPT; ++r) dg[r] = digit(key[r], shift, mask);
+        } else {
+#pragma unroll
+            for (int r = 0; r < SORT_IPT; ++r) {
+                const bool valid = i0 + r * 64 < b1;
+                key[r] = valid ? kin[i0 + r * 64] : (K)0;
+                val[r] = valid ? vin[i0 + r * 64] : 0u;
+                dg[r] = valid ? digit(key[r], shift, mask) : 0xffffffffu;
+            }
         }
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
