@@ -153,8 +153,10 @@ __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int 
         if (!has_s) return;
         l = s_lo;
     }
+    // tile l is hit (found by the scan above, or the interior's first), so
+    // the scan from the right stops short of it
     int h = -1;
-    int stop = has_s ? s_hi + 1 : l;
+    int stop = has_s ? s_hi + 1 : l + 1;
     for (int tx = c_hi; tx >= stop; --tx)
         if (tile_hit(e, tx, ty, W, H)) { h = tx; break; }
     if (h < 0) h = has_s ? s_hi : l;
@@ -557,6 +559,15 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
         }
         const int64_t left = (nb - b0 + nwaves - 1) / nwaves;  // entries of this wave from b0 on
         const int ng = left < kTallGroup ? (int)left : kTallGroup;
+        // the first 64 rows' spans of every entry of the group, loads in flight together
+        uint32_t pre[kTallGroup];
+#pragma unroll
+        for (int gi = 0; gi < kTallGroup; ++gi) {
+            const uint32_t rows = __shfl(mrows, gi, 64);
+            const int64_t q = (int64_t)__shfl(msp0, gi, 64) + lane;
+            const bool ok = gi < ng && lane <= (int)(rows >> 16) - (int)(rows & 0xffff) && q < d.span_cap;
+            pre[gi] = ok ? d.spans[q] : 0xffffu;
+        }
         for (int gi = 0; gi < ng; ++gi) {
             const uint32_t e = __shfl(me, gi, 64);
             const uint32_t cnt = __shfl(mcnt, gi, 64);
@@ -571,11 +582,15 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
                 // one row per lane: its stored span, then the rows' pair prefix
                 int lo = 0, hi = -1;
                 const int64_t q = sp0 + (chunk - y0) + lane;
-                if (chunk + lane <= y1 && q < d.span_cap) {
-                    const uint32_t sp = d.spans[q];
-                    lo = sp & 0xffff;
-                    hi = sp >> 16;
+                uint32_t sp = 0xffffu;
+                if (chunk == y0) {
+#pragma unroll
+                    for (int g2 = 0; g2 < kTallGroup; ++g2) sp = g2 == gi ? pre[g2] : sp;
+                } else if (chunk + lane <= y1 && q < d.span_cap) {
+                    sp = d.spans[q];
                 }
+                lo = sp & 0xffff;
+                hi = sp >> 16;
                 uint32_t tot;
                 const uint32_t ex = wave_excl_scan(hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
                 s_ex[w][lane] = ex;
@@ -584,8 +599,9 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
                 // the rows' pairs together: lane j takes pairs j, j + 64, ... and
                 // finds its row as the last one whose prefix is <= j (rows without
                 // pairs share the next row's prefix, so the last one has pairs)
+                const int last = y1 - chunk < 63 ? y1 - chunk : 63;  // rows past it hold the total
                 for (uint32_t j = lane; j < tot; j += 64) {
-                    int lo2 = 0, hi2 = 63;
+                    int lo2 = 0, hi2 = last;
                     while (lo2 < hi2) {
                         const int mid = (lo2 + hi2 + 1) >> 1;
                         if (s_ex[w][mid] <= j) lo2 = mid;

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
     int64_t b0, b1;
-    chunk_of(count_of(n_dev, n_host), SORT_TILE, b0, b1);
+    const int64_t n = count_of(n_dev, n_host);
+    chunk_of(n, SORT_TILE, b0, b1);
     if (b0 >= b1) return;
     if (threadIdx.x < nbins) run[threadIdx.x] = offs[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -303,7 +304,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
         for (int i = threadIdx.x; i < n_tile; i += NT) {
             K k = skey[i];
             uint32_t d = digit(k, shift, mask);
-            uint32_t pos = run[d] + (uint32_t)i - texcl[d];
+            const uint32_t pos = run[d] + (uint32_t)i - texcl[d];
+            if ((int64_t)pos >= n) continue;  // never, for consistent counts; keeps writes in bounds
             const uint32_t v = sval[i];
             if (kGather) gout[pos] = gsrc[v];
             else kout[pos] = k;
