@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true", help="skip the PSNR gate pass (profiling runs)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP32 form beside")
+    ap.add_argument("--frames-in-flight", type=int, default=1, choices=[1, 2],
+                    help="timed passes: 2 overlaps each frame's blend with the next frame's earlier stages")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--rate", type=float, default=72.0, help="serving: frame requests per second per viewer")
@@ -162,15 +164,18 @@ def make_renderer(gs, scene, form, W, H, args, params=None):
     return r
 
 
-def timed_pass(torch, r, traj, steps, warmup, W, H, tag="timed", stages=None):
+def timed_pass(torch, r, traj, steps, warmup, W, H, tag="timed", stages=None, in_flight=1):
     """Warm up, reset the cache, then time `steps` frames along the
     trajectory (frame i % len).  Returns (wall seconds, per-frame device ms,
     summed stage ms, frames) - device times from the library's own events,
     recorded at the frame's ends and around the stages in `stages` (None:
-    every stage; each event pauses the stream for a few microseconds)."""
+    every stage; each event pauses the stream for a few microseconds).
+    in_flight=2: each frame's blend overlaps the next frame's earlier stages
+    (the renderer's two-frame pipeline, on for this pass only)."""
     oL = torch.zeros(3, H, W, device="cuda")
     oR = torch.zeros(3, H, W, device="cuda")
     n = len(traj)
+    r.pipeline(in_flight == 2)
     for i in range(warmup):
         r.frame(*traj[i % n], oL, oR)
     torch.cuda.synchronize()
@@ -189,6 +194,7 @@ def timed_pass(torch, r, traj, steps, warmup, W, H, tag="timed", stages=None):
     stages, lat, frames = r.timing_read(max_frames=steps)
     r.timing(False)
     r.sync()  # raises if a capacity was exceeded
+    r.pipeline(False)
     return t1 - t0, lat, stages, frames
 
 
@@ -310,14 +316,14 @@ def run_frames(args):
     # the timed pass: events at the frame's ends (latency) and around the
     # dominant kernel only (its live launch time)
     total_s, lat, stages, frames = timed_pass(torch, r, traj, args.steps, args.warmup, W, H, "timed:" + form,
-                                              stages=dom_stages)
+                                              stages=dom_stages, in_flight=args.frames_in_flight)
     fps = args.steps / total_s
     plain = None
     plain_out = None
     if form != "plain" and not args.no_plain:
         plain = make_renderer(gs, scene, "plain", W, H, args)
         p_s, p_lat, p_stages, _ = timed_pass(torch, plain, traj, args.steps, args.warmup, W, H, "timed:plain",
-                                             stages=dom_stages)
+                                             stages=dom_stages, in_flight=args.frames_in_flight)
         plain_out = {"fps": round(args.steps / p_s, 2), "p50_ms": round(float(np.percentile(p_lat, 50)), 4),
                      "p99_ms": round(float(np.percentile(p_lat, 99)), 4)}
     quality = None
@@ -394,7 +400,7 @@ def run_frames(args):
            "data": "synthetic",
            "config": {"workload": WORKLOAD, "form": form, "d_max": args.d_max,
                       "predictor_threshold": args.threshold if FORMS[form].get("predictor") else None,
-                      "raster_dtype": "f32"},
+                      "raster_dtype": "f32", "frames_in_flight": args.frames_in_flight},
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                           "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
            "quality_vs_plain_fp32": quality, "plain_fp32": plain_out,

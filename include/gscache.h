@@ -222,6 +222,22 @@ int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap,
  * raster-only entry counts whenever it is asked for per-pixel counts. */
 int gsc_count_work(gsc_ctx* ctx, int enable);
 
+/* Two frames in flight (enable != 0): each stereo frame's blend runs on a
+ * stream the library owns, overlapping the next frame's selection, schedule,
+ * derivation, composition, preprocess, sorts and emission on the context's
+ * stream.  Frames alternate between two raster buffer sets (the second one
+ * is allocated here, once per loaded scene, the size of the first), and a
+ * frame reuses a set only after the blend that last read it has finished.
+ * A frame's output images are complete only after gsc_sync (or another call
+ * documented to wait for the stream); the caller must not read them, or
+ * reuse their memory, before.  The images are those of the sequential order
+ * (same kernels, same inputs).  Waits for the streams; requires a loaded
+ * scene to enable (GSC_E_NOT_LOADED); GSC_E_OOM if the second set does not
+ * fit.  Off by default; loading a scene switches it off.  Section 5 renders
+ * whole frames asynchronously on several GPU workers; on one GPU this
+ * overlaps the stages of consecutive frames instead. */
+int gsc_pipeline(gsc_ctx* ctx, int enable);
+
 /* ---------------- stage timing -------------------------------------------
  * With timing on, every frame (gsc_derive + gsc_render_stereo) records HIP
  * events on the context's stream at its stage boundaries; gsc_timing_read

@@ -109,6 +109,7 @@ SYMBOLS = {
     "gsc_timing": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing_stages": ([C.c_void_p, C.c_uint32], C.c_int),
     "gsc_count_work": ([C.c_void_p, C.c_int], C.c_int),
+    "gsc_pipeline": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing_read": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gsc_server_last_error": ([C.c_void_p], C.c_char_p),
     "gsc_server_leave": ([C.c_void_p, C.c_int32], C.c_int),
@@ -274,6 +275,12 @@ class Renderer:
     def count_work(self, enable=True):
         """Let the blend count its visits and contributions (stats n_eval, n_contrib)."""
         self._check(lib().gsc_count_work(self.h, 1 if enable else 0))
+
+    def pipeline(self, enable=True):
+        """Two frames in flight: each frame's blend overlaps the next frame's
+        stages up to its tile ranges.  A frame's images are complete only
+        after sync() (or a later call that waits, such as stats())."""
+        self._check(lib().gsc_pipeline(self.h, 1 if enable else 0))
 
     def timing(self, enable=True, stages=None):
         """Record device time of every frame from now on (or stop): the frame

@@ -95,9 +95,20 @@ bool valid_camera(const gsc_camera& c) {
 }
 
 
+// Waits for the context's stream and, with two frames in flight, for the
+// blend stream.
+hipError_t sync_all(gsc_ctx* c) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && c->blend_stream) e = hipStreamSynchronize(c->blend_stream);
+    return e;
+}
+
+// Raster buffers of the last stereo frame.
+Raster& stereo_raster(gsc_ctx* c) { return c->last_set ? c->raster2 : c->raster; }
+
 void free_explicit(gsc_ctx* c) {
     if (c->xmem.empty()) return;
-    (void)hipStreamSynchronize(c->stream);
+    (void)sync_all(c);
     c->xmem.release();
     c->xraster = Raster();
     c->xg = {};
@@ -107,7 +118,7 @@ void free_explicit(gsc_ctx* c) {
 
 void free_labels(gsc_ctx* c) {
     if (c->lmem.empty()) return;
-    (void)hipStreamSynchronize(c->stream);
+    (void)sync_all(c);
     c->lmem.release();
     c->lab_L0 = c->lab_L1 = c->lab_L2 = nullptr;
     c->lab_L3 = nullptr;
@@ -119,12 +130,16 @@ void free_labels(gsc_ctx* c) {
 void free_all(gsc_ctx* c) {
     free_labels(c);
     if (c->mem.empty()) return;
-    (void)hipStreamSynchronize(c->stream);
+    (void)sync_all(c);
     c->mem.release();
     c->scene = Scene();
     c->view[0] = View();
     c->view[1] = View();
     c->raster = Raster();
+    c->raster2 = Raster();
+    c->pipeline = false;
+    c->blend_pending[0] = c->blend_pending[1] = false;
+    c->last_set = 0;
     c->loaded = false;
 }
 
@@ -340,11 +355,16 @@ int gsc_create(const gsc_config* cfg, void* stream, gsc_ctx** out) {
 
 void gsc_destroy(gsc_ctx* c) {
     if (!c) return;
-    (void)hipStreamSynchronize(c->stream);
+    (void)sync_all(c);
     gsc::free_marks(c);
     gsc::pred_free(c);
     gsc::free_explicit(c);
     gsc::free_all(c);
+    for (int i = 0; i < 2; ++i) {
+        if (c->front_done[i]) (void)hipEventDestroy(c->front_done[i]);
+        if (c->blend_done[i]) (void)hipEventDestroy(c->blend_done[i]);
+    }
+    if (c->blend_stream) (void)hipStreamDestroy(c->blend_stream);
     delete c;
 }
 
@@ -429,6 +449,9 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
             free_all(c);
             return fail(c, GSC_E_OOM, "gsc_load_anchors: view allocation");
         }
+    c->rcap_entries = max_entries;
+    c->rcap_pairs = max_pairs;
+    c->rcap_tiles = 2 * ntx * nty;
     if (alloc_raster(c->mem, c->raster, max_entries, max_pairs, 2 * ntx * nty,
                      (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0) != hipSuccess) {
         free_all(c);
@@ -536,9 +559,22 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
     }
     tab.total_tiles = tiles;
     Marks* mk = frame_marks(c);
-    hipError_t e = raster_batch(tab, c->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->count_work,
-                                c->stream, mk);
+    // two frames in flight: this frame's set was last read by the blend two
+    // frames back, which must finish before the preprocess rewrites it
+    const int set = c->pipeline ? (int)(c->pipe_frames & 1) : 0;
+    Raster& R = set ? c->raster2 : c->raster;
+    hipError_t e = hipSuccess;
+    if (c->pipeline && c->blend_pending[set]) e = hipStreamWaitEvent(c->stream, c->blend_done[set], 0);
+    if (e == hipSuccess)
+        e = raster_batch(tab, R, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, c->count_work, c->stream, mk,
+                         c->pipeline ? c->blend_stream : nullptr, c->pipeline ? c->front_done[set] : nullptr);
+    if (e == hipSuccess && c->pipeline) {
+        e = hipEventRecord(c->blend_done[set], c->blend_stream);
+        c->blend_pending[set] = e == hipSuccess;
+        c->pipe_frames += 1;
+    }
     if (e != hipSuccess) return hip_fail(c, e, "gsc_render_stereo");
+    c->last_set = set;
     if (mk) c->marks_used += 1;
     c->last_count_work = c->count_work;
     c->last_tab = tab;
@@ -580,10 +616,10 @@ int gsc_render_gaussians(gsc_ctx* c, const gsc_gaussians* g, const gsc_camera* c
 
 int gsc_sync(gsc_ctx* c) {
     if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_sync: null context");
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    HIP_OR_FAIL(c, sync_all(c));
     int of = 0;
     if (c->rendered) {
-        Raster& R = c->explicit_render ? c->xraster : c->raster;
+        Raster& R = c->explicit_render ? c->xraster : stereo_raster(c);
         HIP_OR_FAIL(c, hipMemcpy(R.cnt_host, R.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
         of |= (R.cnt_host->overflow & 7) ? 1 : 0;  // tile pairs, entries or tall-row spans
     }
@@ -599,12 +635,13 @@ int gsc_sync(gsc_ctx* c) {
 int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     if (!c || !st) return fail(c, GSC_E_INVALID_ARG, "gsc_get_stats: null argument");
     std::memset(st, 0, sizeof(*st));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    HIP_OR_FAIL(c, sync_all(c));
     if (!c->loaded) return GSC_OK;
     HIP_OR_FAIL(c, hipMemcpy(c->view[0].cnt_host, c->view[0].cnt, sizeof(Counters), hipMemcpyDeviceToHost));
-    HIP_OR_FAIL(c, hipMemcpy(c->raster.cnt_host, c->raster.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
+    Raster& SR = stereo_raster(c);
+    HIP_OR_FAIL(c, hipMemcpy(SR.cnt_host, SR.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
     const Counters& k = *c->view[0].cnt_host;
-    const RasterCounters& r = *c->raster.cnt_host;
+    const RasterCounters& r = *SR.cnt_host;
     st->frame = c->frame;
     st->n_visible = k.n_visible;
     st->n_miss = k.n_miss;
@@ -612,7 +649,7 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     if (c->rendered && !c->explicit_render && c->last_tab.total_tiles > 0) {
         // pairs per eye: the lengths of its tiles' runs
         std::vector<int32_t> rg(2 * (size_t)c->last_tab.total_tiles);
-        HIP_OR_FAIL(c, hipMemcpy(rg.data(), c->raster.ranges, rg.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(c, hipMemcpy(rg.data(), SR.ranges, rg.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int sg = 0; sg < c->last_tab.n && sg < 2; ++sg) {
             const Seg& g = c->last_tab.s[sg];
             int64_t n = 0;
@@ -626,11 +663,11 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->depth_next = k.depth;
     st->overflow = ((r.overflow & 7) ? 1 : 0) | (k.overflow & 2);
     st->n_tall = r.n_tall;
-    size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->xg_bytes;
+    size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->raster2.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;
     if (c->rendered && !c->explicit_render && c->last_count_work && c->last_tab.total_tiles > 0) {
         std::vector<int32_t> te(2 * (size_t)c->last_tab.total_tiles);
-        HIP_OR_FAIL(c, hipMemcpy(te.data(), c->raster.tile_eval, te.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(c, hipMemcpy(te.data(), SR.tile_eval, te.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int sg = 0; sg < c->last_tab.n && sg < 2; ++sg) {
             const Seg& g = c->last_tab.s[sg];
             int64_t ev = 0, co = 0;
@@ -651,9 +688,36 @@ int gsc_count_work(gsc_ctx* c, int enable) {
     return GSC_OK;
 }
 
+int gsc_pipeline(gsc_ctx* c, int enable) {
+    if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_pipeline: null context");
+    HIP_OR_FAIL(c, sync_all(c));
+    c->blend_pending[0] = c->blend_pending[1] = false;
+    c->pipe_frames = 0;
+    if (!enable) {
+        c->pipeline = false;
+        return GSC_OK;
+    }
+    if (!c->loaded) return fail(c, GSC_E_NOT_LOADED, "gsc_pipeline: no scene loaded");
+    if (!c->blend_stream) {
+        HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->blend_stream, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->front_done[i], hipEventDisableTiming));
+            HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->blend_done[i], hipEventDisableTiming));
+        }
+    }
+    if (c->raster2.bytes == 0 &&
+        alloc_raster(c->mem, c->raster2, c->rcap_entries, c->rcap_pairs, c->rcap_tiles,
+                     (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0) != hipSuccess) {
+        c->raster2 = Raster();
+        return fail(c, GSC_E_OOM, "gsc_pipeline: second raster buffer set");
+    }
+    c->pipeline = true;
+    return GSC_OK;
+}
+
 int gsc_timing(gsc_ctx* c, int enable) {
     if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_timing: null context");
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    HIP_OR_FAIL(c, sync_all(c));
     c->timing = enable != 0;
     c->marks_used = 0;
     for (Marks& m : c->marks) m.recorded = 0;
@@ -669,7 +733,7 @@ int gsc_timing_stages(gsc_ctx* c, uint32_t stage_mask) {
 int gsc_timing_read(gsc_ctx* c, double* ms, int32_t n, double* frame_ms, int64_t frame_cap, int64_t* frames) {
     if (!c || !ms || n < 0 || frame_cap < 0 || (frame_cap > 0 && !frame_ms))
         return fail(c, GSC_E_INVALID_ARG, "gsc_timing_read: bad argument");
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    HIP_OR_FAIL(c, sync_all(c));
     for (int32_t i = 0; i < n; ++i) ms[i] = 0.0;
     for (size_t f = 0; f < c->marks_used; ++f) {
         Marks& m = c->marks[f];
@@ -703,12 +767,12 @@ int gsc_reset_cache(gsc_ctx* c) {
 int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_t* n) {
     if (!c || !n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: null argument");
     if (!c->loaded && !c->explicit_render) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing to copy");
-    Raster& R = c->explicit_render ? c->xraster : c->raster;
+    Raster& R = c->explicit_render ? c->xraster : stereo_raster(c);
     const bool view_item = what <= GSC_DBG_DERIVED || what == GSC_DBG_DEPTH;
     if (view_item && !c->loaded) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: no scene loaded");
     if (eye < 0 || eye > 1) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: eye must be 0 or 1");
     if (cap > 0 && !dst) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: null destination");
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    HIP_OR_FAIL(c, sync_all(c));
     View& v = c->view[c->nviews == 1 ? 0 : eye];
     Counters kz = {};
     if (c->loaded) {

@@ -248,8 +248,11 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr
 // count_work: the blend also counts its (pixel, Gaussian) visits and
 // contributions per tile (and writes per-pixel contributor counts when a
 // segment asks for them); without it those counters are not kept.
+// blend_st (optional): the stream the blend runs on, after front_done is
+// recorded on st once the tile ranges are written (the stage marks of the
+// blend go to blend_st as well).
 hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool count_work, hipStream_t st,
-                        Marks* mk = nullptr);
+                        Marks* mk = nullptr, hipStream_t blend_st = nullptr, hipEvent_t front_done = nullptr);
 
 // Blocks of `threads` threads of `kernel` the whole device holds at once
 // (occupancy x compute units; cached per kernel and device).  Grid-stride

@@ -65,6 +65,19 @@ struct gsc_ctx {
     gsc::View view[2];               // view[1] only without de-redundancy (per-eye derive)
     gsc::Raster raster;
     gsc::Raster xraster;             // raster-only entry
+    // two frames in flight (gsc_pipeline): a frame's blend runs on
+    // blend_stream while the next frame's stages up to its tile ranges run on
+    // `stream`; the frames alternate between raster and raster2, and a frame
+    // reuses a set only after the blend that last read it has finished
+    bool pipeline = false;
+    gsc::Raster raster2;
+    hipStream_t blend_stream = nullptr;
+    hipEvent_t front_done[2] = {nullptr, nullptr};
+    hipEvent_t blend_done[2] = {nullptr, nullptr};
+    bool blend_pending[2] = {false, false};
+    int64_t pipe_frames = 0;
+    int last_set = 0;                // raster set of the last stereo frame
+    int64_t rcap_entries = 0, rcap_pairs = 0, rcap_tiles = 0;  // raster capacities of the loaded scene
     int nviews = 1;
     bool loaded = false, have_pair = false, derived = false, rendered = false, explicit_render = false;
     gsc_camera eye[2]{}, unified{};

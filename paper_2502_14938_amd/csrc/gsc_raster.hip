@@ -85,17 +85,21 @@ struct Ellipse {
     float ia, ic;               // 1/ca, 1/cc
 };
 
+// The extents (xmax, ymax, kr, and the row extents below) only place the
+// candidate range and the certain interior, each widened by the margin, which
+// is far above the 1-ulp error of the hardware square root and reciprocal;
+// ia and ic enter the exact test and stay correctly rounded.
 __device__ __forceinline__ Ellipse make_ellipse(float mx, float my, float ca, float cb, float cc, float tau) {
     Ellipse e;
     e.mx = mx; e.my = my; e.ca = ca; e.cb = cb; e.cc = cc; e.tau = tau;
     e.det = ca * cc - cb * cb;
-    float id = e.det > 0.f ? 1.0f / e.det : 0.f;
-    e.xmax = sqrtf(tau * cc * id);
-    e.ymax = sqrtf(tau * ca * id);
-    e.kr = sqrtf(tau * id / cc);
-    e.margin = 2e-3f * (e.xmax + e.ymax) + 0.05f;
     e.ia = 1.0f / ca;
     e.ic = 1.0f / cc;
+    const float id = e.det > 0.f ? __builtin_amdgcn_rcpf(e.det) : 0.f;
+    e.xmax = __builtin_amdgcn_sqrtf(tau * cc * id);
+    e.ymax = __builtin_amdgcn_sqrtf(tau * ca * id);
+    e.kr = __builtin_amdgcn_sqrtf(tau * id * e.ic);
+    e.margin = 2e-3f * (e.xmax + e.ymax) + 0.05f;
     return e;
 }
 
@@ -123,8 +127,8 @@ __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int 
     } else {
         float dyr = fminf(fmaxf(-e.cb * e.kr, b0), b1);
         float dyl = fminf(fmaxf(e.cb * e.kr, b0), b1);
-        float sr = sqrtf(fmaxf(e.ca * e.tau - e.det * dyr * dyr, 0.f));
-        float sl = sqrtf(fmaxf(e.ca * e.tau - e.det * dyl * dyl, 0.f));
+        float sr = __builtin_amdgcn_sqrtf(fmaxf(e.ca * e.tau - e.det * dyr * dyr, 0.f));
+        float sl = __builtin_amdgcn_sqrtf(fmaxf(e.ca * e.tau - e.det * dyl * dyl, 0.f));
         R = (-e.cb * dyr + sr) * e.ia;
         L = (-e.cb * dyl - sl) * e.ia;
         certain = true;
@@ -920,7 +924,7 @@ hipError_t tall_list(Raster& r, hipStream_t st) {
 }
 
 hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool count_work, hipStream_t st,
-                        Marks* mk) {
+                        Marks* mk, hipStream_t blend_st, hipEvent_t front_done) {
     RasterCounters* rc = r.cnt;
     mark(mk, 3, st);
     PreArgs pa;
@@ -986,14 +990,21 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
                            32, r.ranges, (uint32_t)tab.total_tiles);
     }
     r.order = nullptr;
-    mark(mk, 12, st);
+    hipStream_t bs = st;
+    if (blend_st && blend_st != st) {
+        e = hipEventRecord(front_done, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(blend_st, front_done, 0);
+        if (e != hipSuccess) return e;
+        bs = blend_st;
+    }
+    mark(mk, 12, bs);
     if (count_work)
-        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
+        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, bs, tab, r.ranges,
                            r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
     else
-        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, st, tab, r.ranges,
+        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)tab.total_tiles), dim3(kBlendThreads), 0, bs, tab, r.ranges,
                            r.pval[r.sorted_buf], r.rec, (uint32_t)r.max_entries, r.tile_eval);
-    mark(mk, 13, st);
+    mark(mk, 13, bs);
     return hipGetLastError();
 }
 
