@@ -128,27 +128,39 @@ struct LookupArgs {
 
 // Hit iff the anchor still owns a line (after invalidation every owned line
 // has 1 <= t - tau <= d_t), reuse is on and the predictor does not flag it.
-// Every visible owned line is stamped last_used = t.
+// Every visible owned line is stamped last_used = t.  The loop is uniform
+// per wave: the predictor runs on the whole wave (matrix cores) whenever one
+// of its lanes has a candidate.
 __global__ __launch_bounds__(NT) void k_cache_lookup(LookupArgs a) {
-    int32_t nv = a.cnt->n_visible;
-    for (int64_t i = gtid(); i < nv; i += gstride()) {
-        int32_t aid = a.visible[i];
-        int32_t s = a.slot_of[aid];
-        bool hit = s >= 0 && a.reuse;
-        if (s >= 0) a.line_last[s] = a.t;
-        if (hit && (a.predictor || a.cand_feat)) {
-            float f[kPredIn];
-            int32_t tau = a.line_tau[s];
-            reuse_features(a.posr[aid], a.level[aid], a.lmax, a.scale + 6 * (int64_t)aid, a.cam.pos,
-                           a.pu_hist + 4 * (tau & 63), a.t - tau, a.dmax, a.cam.fx, f);
-            if (a.cand_feat) {
-                int32_t c = atomicAdd(&a.cnt->n_cand, 1);
-                for (int q = 0; q < kPredIn; ++q) a.cand_feat[(int64_t)c * kPredIn + q] = f[q];
-                a.cand_id[c] = aid;
+    __shared__ uint32_t s_h[NT / 64][kPredLdsWave];
+    const int32_t nv = a.cnt->n_visible;
+    const int lane = threadIdx.x & 63;
+    for (int64_t w0 = gtid() - lane; w0 < nv; w0 += gstride()) {
+        const int64_t i = w0 + lane;
+        const bool valid = i < nv;
+        bool hit = false;
+        float f[kPredIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (valid) {
+            const int32_t aid = a.visible[i];
+            const int32_t s = a.slot_of[aid];
+            hit = s >= 0 && a.reuse;
+            if (s >= 0) a.line_last[s] = a.t;
+            if (hit && (a.predictor || a.cand_feat)) {
+                const int32_t tau = a.line_tau[s];
+                reuse_features(a.posr[aid], a.level[aid], a.lmax, a.scale + 6 * (int64_t)aid, a.cam.pos,
+                               a.pu_hist + 4 * (tau & 63), a.t - tau, a.dmax, a.cam.fx, f);
+                if (a.cand_feat) {
+                    const int32_t c = atomicAdd(&a.cnt->n_cand, 1);
+                    for (int q = 0; q < kPredIn; ++q) a.cand_feat[(int64_t)c * kPredIn + q] = f[q];
+                    a.cand_id[c] = aid;
+                }
             }
-            if (a.predictor && pred_prob_bf16(a.pred_wbf, a.pred_w32, f) > a.thr) hit = false;
         }
-        a.miss_flag[i] = hit ? 0u : 1u;
+        if (a.predictor && __any(hit)) {
+            const float p = pred_prob_bf16_wave(a.pred_wbf, a.pred_w32, f, s_h[threadIdx.x >> 6]);
+            if (hit && p > a.thr) hit = false;
+        }
+        if (valid) a.miss_flag[i] = hit ? 0u : 1u;
     }
 }
 

@@ -165,13 +165,21 @@ __global__ __launch_bounds__(NT) void k_pred_to_bf16(const float* __restrict__ w
 }
 
 
+// One candidate per lane; the loop is uniform per wave (the predictor runs
+// on the whole wave).
 __global__ __launch_bounds__(NT) void k_pred_infer(const uint16_t* __restrict__ wb, const float* __restrict__ w32,
                                                    const float* __restrict__ X, int64_t n, float* __restrict__ out) {
-    for (int64_t r = gtid(); r < n; r += gstride()) {
-        float x[kPredIn];
+    __shared__ uint32_t s_h[NT / 64][kPredLdsWave];
+    const int lane = threadIdx.x & 63;
+    for (int64_t w0 = gtid() - lane; w0 < n; w0 += gstride()) {
+        const int64_t r = w0 + lane;
+        float x[kPredIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (r < n) {
 #pragma unroll
-        for (int i = 0; i < kPredIn; ++i) x[i] = X[r * kPredIn + i];
-        out[r] = pred_prob_bf16(wb, w32, x);
+            for (int i = 0; i < kPredIn; ++i) x[i] = X[r * kPredIn + i];
+        }
+        const float p = pred_prob_bf16_wave(wb, w32, x, s_h[threadIdx.x >> 6]);
+        if (r < n) out[r] = p;
     }
 }
 
