@@ -10,12 +10,11 @@ namespace gsc {
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
-// Two floats rounded to BF16 (nearest-even) and packed low | high << 16.
+// Two floats rounded to BF16 (nearest-even) and packed low | high << 16
+// (one hardware conversion of the pair).
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-    uint32_t a = __float_as_uint(lo), b = __float_as_uint(hi);
-    a += 0x7fffu + ((a >> 16) & 1u);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (a >> 16) | (b & 0xffff0000u);
+    const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // acc + w.lo * h.lo + w.hi * h.hi (BF16 pairs, FP32 accumulation).
@@ -34,11 +33,7 @@ constexpr int kPredLdsStride = 34;
 constexpr int kPredLdsWave = 64 * kPredLdsStride;
 
 // BF16 value rounded from x (nearest-even), as a float.
-__device__ __forceinline__ float round_bf16(float x) {
-    uint32_t a = __float_as_uint(x);
-    a += 0x7fffu + ((a >> 16) & 1u);
-    return __uint_as_float(a & 0xffff0000u);
-}
+__device__ __forceinline__ float round_bf16(float x) { return (float)(__bf16)x; }
 
 // p(stale) of the wave's 64 candidates (the features f of this lane's),
 // BF16 weights and activations, FP32 accumulation.
