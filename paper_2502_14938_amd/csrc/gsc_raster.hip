@@ -678,25 +678,49 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
 
 
 
-// Each thread scans 8 consecutive sorted keys (plus one neighbour on each
-// side), so every load of a step is issued before any comparison.
+// R consecutive keys from a 16-byte aligned address, in 16-byte loads.
+template <typename K, int R>
+__device__ __forceinline__ void load_keys(const K* __restrict__ p, K (&k)[R]) {
+    constexpr int NV = R * (int)sizeof(K) / 16;
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint4 v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = q[j];
+    __builtin_memcpy(k, v, sizeof(v));
+}
+
+// Each thread scans RQ x US keys in US runs of RQ consecutive ones (plus one
+// neighbour on each side of a run), so every load of a step is issued before
+// any comparison.
 template <typename K>
 __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const int32_t* n_sort, int shift,
                                                int32_t* __restrict__ ranges, uint32_t n_tiles) {
     // each lane takes RQ consecutive keys (a wave 64 RQ, coalesced), two such
     // steps in flight; neighbours across lanes come from the adjacent lanes,
     // the wave's two end lanes read theirs
-    constexpr int RQ = 4, US = 2;
+    constexpr int RQ = 4, US = 4;
     const int64_t n = *n_sort;
     const int lane = threadIdx.x & 63;
     const int64_t wave = gtid() >> 6, nwaves = gstride() >> 6;
     for (int64_t w0 = wave * (64 * RQ * US); w0 < n; w0 += nwaves * (64 * RQ * US)) {
         uint32_t t[US][RQ];
+        if (w0 + 64 * RQ * US <= n) {
+            // a full step: each lane's RQ keys in one load (16-byte aligned: i0 % RQ == 0)
 #pragma unroll
-        for (int u = 0; u < US; ++u) {
-            const int64_t i0 = w0 + (int64_t)u * 64 * RQ + (int64_t)lane * RQ;
+            for (int u = 0; u < US; ++u) {
+                const int64_t i0 = w0 + (int64_t)u * 64 * RQ + (int64_t)lane * RQ;
+                K k[RQ];
+                load_keys<K, RQ>(keys + i0, k);
 #pragma unroll
-            for (int q = 0; q < RQ; ++q) t[u][q] = i0 + q < n ? (uint32_t)(keys[i0 + q] >> shift) : 0xffffffffu;
+                for (int q = 0; q < RQ; ++q) t[u][q] = (uint32_t)(k[q] >> shift);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < US; ++u) {
+                const int64_t i0 = w0 + (int64_t)u * 64 * RQ + (int64_t)lane * RQ;
+#pragma unroll
+                for (int q = 0; q < RQ; ++q) t[u][q] = i0 + q < n ? (uint32_t)(keys[i0 + q] >> shift) : 0xffffffffu;
+            }
         }
 #pragma unroll
         for (int u = 0; u < US; ++u) {
