@@ -66,6 +66,9 @@ def test_null_and_invalid_arguments(L):
     assert L.gsc_set_camera_pair(None, None, None, 0.0) == -1
     n = C.c_int64()
     assert L.gsc_debug_copy(None, 0, 0, None, 0, C.byref(n)) == -1
+    assert L.gsc_pipeline(None, 1) == -1
+    assert L.gsc_timing_stages(None, 1) == -1
+    assert L.gsc_count_work(None, 1) == -1
     L.gsc_destroy(None)
 
 
