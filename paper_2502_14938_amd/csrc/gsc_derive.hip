@@ -38,11 +38,22 @@ __device__ __forceinline__ void frame_begin(Counters* cnt, float* pu_hist, int32
 // ------------------------------------------------------------- selection
 // Keep anchor a iff (level 0 or |x - p_u| <= d_ref 2^-level) and its bounding
 // sphere is not wholly outside any unified-frustum plane (4 sides + near).
+// Direct-mapped cache (line_anchor non-null: line a can only hold anchor a):
+// the invalidation of Alg. 1 is done here too, anchor a's line dropped when
+// its age exceeds the current depth (the depth is the previous frame's
+// update; starting the frame leaves it alone).
 __global__ __launch_bounds__(NT) void k_select_flags(const float4* __restrict__ posr, const uint8_t* __restrict__ level,
                                                      int64_t n, DeriveCam cam, uint32_t* __restrict__ flags,
-                                                     Counters* cnt, float* __restrict__ pu_hist, int32_t t) {
+                                                     Counters* cnt, float* __restrict__ pu_hist, int32_t t,
+                                                     int32_t* __restrict__ line_anchor, const int32_t* __restrict__ line_tau,
+                                                     int32_t* __restrict__ slot_of) {
     if (blockIdx.x == 0) frame_begin(cnt, pu_hist, t, cam);
+    const int32_t depth = cnt->depth;
     for (int64_t a = gtid(); a < n; a += gstride()) {
+        if (line_anchor && line_anchor[a] >= 0 && t - line_tau[a] > depth) {
+            slot_of[a] = -1;
+            line_anchor[a] = -1;
+        }
         float4 p = posr[a];
         int l = level[a];
         bool keep = true;
@@ -124,8 +135,22 @@ struct LookupArgs {
     float* cand_feat;      // optional: features of candidates (for label collection)
     int32_t* cand_id;
     Counters* cnt;
+    // direct-mapped cache: a miss takes line aid here, and every visible
+    // anchor's render-buffer line is its own id
+    int32_t direct;
+    int32_t* slot_of_w;
+    int32_t* line_anchor;
+    int32_t* line_tau_w;
+    int32_t* vslot;
 };
 
+// Direct-mapped lines, used when there is a line for every anchor: anchor a
+// owns line a.  Free lines can then never run short, so there is no free
+// list and no eviction, and the hit/miss decisions are the same as with any
+// other choice of free line.  Misses (re)take their line at frame t (here,
+// in the lookup); every visible anchor's buffer position points at its own
+// line.
+//
 // Hit iff the anchor still owns a line (after invalidation every owned line
 // has 1 <= t - tau <= d_t), reuse is on and the predictor does not flag it.
 // Every visible owned line is stamped last_used = t.  The loop is uniform
@@ -140,9 +165,10 @@ __global__ __launch_bounds__(NT) void k_cache_lookup(LookupArgs a) {
         const bool valid = i < nv;
         bool hit = false;
         float f[kPredIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int32_t aid = 0, s = -1;
         if (valid) {
-            const int32_t aid = a.visible[i];
-            const int32_t s = a.slot_of[aid];
+            aid = a.visible[i];
+            s = a.slot_of[aid];
             hit = s >= 0 && a.reuse;
             if (s >= 0) a.line_last[s] = a.t;
             if (hit && (a.predictor || a.cand_feat)) {
@@ -160,7 +186,20 @@ __global__ __launch_bounds__(NT) void k_cache_lookup(LookupArgs a) {
             const float p = pred_prob_bf16_wave(a.pred_wbf, a.pred_w32, f, s_h[threadIdx.x >> 6]);
             if (hit && p > a.thr) hit = false;
         }
-        if (valid) a.miss_flag[i] = hit ? 0u : 1u;
+        if (valid) {
+            a.miss_flag[i] = hit ? 0u : 1u;
+            if (a.direct) {
+                a.vslot[i] = aid;
+                if (!hit) {  // derived this frame into line aid
+                    if (s < 0) {
+                        a.slot_of_w[aid] = aid;
+                        a.line_anchor[aid] = aid;
+                        a.line_last[aid] = a.t;
+                    }
+                    a.line_tau_w[aid] = a.t;
+                }
+            }
+        }
     }
 }
 
@@ -281,28 +320,6 @@ __global__ __launch_bounds__(NT) void k_assign(const int32_t* __restrict__ misse
     }
 }
 
-// Direct-mapped lines, used when there is a line for every anchor: anchor a
-// owns line a.  Free lines can then never run short, so there is no free
-// list and no eviction, and the hit/miss decisions are the same as with any
-// other choice of free line.  Misses (re)take their line at frame t; every
-// visible anchor's buffer position points at its own line.
-__global__ __launch_bounds__(NT) void k_direct_assign(const int32_t* __restrict__ misses,
-                                                      const int32_t* __restrict__ visible, int32_t* __restrict__ slot_of,
-                                                      int32_t* __restrict__ line_anchor, int32_t* __restrict__ line_tau,
-                                                      int32_t* __restrict__ line_last, int32_t* __restrict__ vslot,
-                                                      int32_t t, Counters* cnt) {
-    const int32_t nm = cnt->n_miss, nv = cnt->n_visible;
-    for (int64_t j = gtid(); j < nm; j += gstride()) {
-        const int32_t aid = visible[misses[j]];
-        if (slot_of[aid] < 0) {
-            slot_of[aid] = aid;
-            line_anchor[aid] = aid;
-            line_last[aid] = t;
-        }
-        line_tau[aid] = t;
-    }
-    for (int64_t i = gtid(); i < nv; i += gstride()) vslot[i] = visible[i];
-}
 
 __global__ __launch_bounds__(NT) void k_vslot(const int32_t* __restrict__ visible, const int32_t* __restrict__ slot_of,
                                               int32_t* __restrict__ vslot, Counters* cnt) {
@@ -404,18 +421,20 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     mark(mk, 0, st);
     // anchor indexing and filtering -> X_t ascending (the first block also
     // starts the frame's counters)
+    const bool reuse = (a.flags & GSC_FLAG_REUSE) != 0;
+    const bool direct = reuse && v.C >= n;  // line a holds anchor a or nothing
     hipLaunchKernelGGL(k_select_flags, grid_fit(k_select_flags, n), dim3(NT), 0, st, sc.posr, sc.level, n, a.cam, v.tmp_a,
-                       cnt, v.pu_hist, t);
+                       cnt, v.pu_hist, t, direct ? v.line_anchor : nullptr, v.line_tau, v.slot_of);
     GSC_TRY(compact_u32(v.tmp_a, nullptr, n, &cnt->n_visible, v.visible, v.block_sums, st));
 
-    const bool reuse = (a.flags & GSC_FLAG_REUSE) != 0;
     if (!reuse) {
         hipLaunchKernelGGL(k_nocache, grid_fit(k_nocache, n), dim3(NT), 0, st, v.visible, v.misses, v.vslot,
                            v.line_anchor, cnt);
     } else {
         const int64_t C = v.C;
-        hipLaunchKernelGGL(k_cache_invalidate, grid_fit(k_cache_invalidate, C), dim3(NT), 0, st, v.line_anchor, v.line_tau, v.slot_of, C,
-                           t, cnt);
+        if (!direct)  // (direct: done in k_select_flags)
+            hipLaunchKernelGGL(k_cache_invalidate, grid_fit(k_cache_invalidate, C), dim3(NT), 0, st, v.line_anchor, v.line_tau,
+                               v.slot_of, C, t, cnt);
         LookupArgs la;
         la.visible = v.visible; la.slot_of = v.slot_of; la.line_last = v.line_last; la.line_tau = v.line_tau;
         la.miss_flag = v.tmp_a; la.t = t; la.reuse = 1;
@@ -423,13 +442,12 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
         la.thr = a.pred_thr; la.posr = sc.posr; la.level = sc.level; la.scale = sc.scale; la.pu_hist = v.pu_hist;
         la.lmax = sc.l_max; la.dmax = a.d_max; la.cam = a.cam; la.pred_wbf = a.pred_wbf; la.pred_w32 = a.pred_w;
         la.cand_feat = a.collect ? v.cand_feat : nullptr; la.cand_id = v.cand_id; la.cnt = cnt;
+        la.direct = direct ? 1 : 0; la.slot_of_w = v.slot_of; la.line_anchor = v.line_anchor; la.line_tau_w = v.line_tau;
+        la.vslot = v.vslot;
         hipLaunchKernelGGL(k_cache_lookup, grid_fit(k_cache_lookup, n), dim3(NT), 0, st, la);
         // misses, ascending visible position (= ascending anchor id)
         GSC_TRY(compact_u32(v.tmp_a, &cnt->n_visible, 0, &cnt->n_miss, v.misses, v.block_sums, st));
-        if (C >= n) {
-            hipLaunchKernelGGL(k_direct_assign, grid_fit(k_direct_assign, n), dim3(NT), 0, st, v.misses, v.visible, v.slot_of,
-                               v.line_anchor, v.line_tau, v.line_last, v.vslot, t, cnt);
-        } else {
+        if (!direct) {
             // misses that need a line, and their ranks
             uint32_t* need = v.tmp_a;
             uint32_t* need_rank = v.tmp_b;
