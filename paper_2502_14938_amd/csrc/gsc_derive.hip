@@ -4,11 +4,12 @@
 //                                   hit/miss, learned staleness, slot
 //                                   allocation, eviction of outdated lines)
 //   decode new anchors           -> derive_mfma (eq. 3, eq. 2; matrix cores)
-//   configure the cache depth    -> depth_update (eq. 4, linear guide), in k_compose_count
+//   configure the cache depth    -> depth_update (eq. 4, linear guide), in k_compose_reduce
 //   update the render buffer     -> k_compose_* (opacity mask, Section 6)
 // Every count stays on the device (Counters); the host only enqueues.
 #include <cmath>
 
+#include "gsc_blockscan.h"
 #include "gsc_common.h"
 #include "gsc_derive_mfma.h"
 #include "gsc_pred_bf16.h"
@@ -369,40 +370,74 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 }
 
 
+
 // ------------------------------------------------------------- compose
 // G_t = [(i, j) : i visible ascending, j ascending, alpha_ij > 0]; each entry
 // is the cache entry (line * k + j).
-__global__ __launch_bounds__(NT) void k_compose_count(const int32_t* __restrict__ vslot,
-                                                      const uint16_t* __restrict__ line_mask, Counters* cnt,
-                                                      uint32_t* __restrict__ count, int32_t dmax, int32_t guide) {
+static_assert(NT == blockscan::kThreads, "the fused compose scan uses the block-scan shape");
+
+// Composition of the render buffer as one fused scan: visible anchor i
+// contributes the Gaussians of its line whose opacity is positive (the
+// line's mask, set by the derivation; none for an anchor left without a line
+// at a capacity overflow), written to G in visible order at the exclusive
+// prefix of the contributions.  The reduce pass sums each block's chunk and
+// runs the depth update (eq. 4) from this frame's counts; the down-sweep
+// writes the ids.
+__device__ __forceinline__ uint32_t compose_mask(const int32_t* __restrict__ vslot,
+                                                 const uint16_t* __restrict__ line_mask, int64_t i, int32_t& slot) {
+    slot = vslot[i];
+    return slot < 0 ? 0u : (uint32_t)line_mask[slot];
+}
+
+__global__ __launch_bounds__(NT) void k_compose_reduce(const int32_t* __restrict__ vslot,
+                                                       const uint16_t* __restrict__ line_mask, Counters* cnt,
+                                                       int32_t dmax, int32_t guide, uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t wsum[NT / 64];
     if (gtid() == 0) depth_update(cnt, dmax, guide);  // eq. 4, from this frame's counts
-    int32_t nv = cnt->n_visible;
-    for (int64_t i = gtid(); i < nv; i += gstride()) {
-        if (vslot[i] < 0) {  // anchor left without a line (capacity overflow)
-            count[i] = 0u;
-            continue;
-        }
-        count[i] = (uint32_t)__popc(line_mask[vslot[i]]);  // set by the derivation
+    int64_t b0, b1;
+    blockscan::chunk_of(cnt->n_visible, blockscan::kTile, b0, b1);
+    uint32_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) {
+        int32_t slot;
+        s += (uint32_t)__popc(compose_mask(vslot, line_mask, i, slot));
     }
+    const uint32_t t = blockscan::block_sum(s, wsum);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(NT) void k_compose_write(const int32_t* __restrict__ vslot,
-                                                      const uint16_t* __restrict__ line_mask, int k, Counters* cnt,
-                                                      const uint32_t* __restrict__ off, int32_t* __restrict__ G) {
-    int32_t nv = cnt->n_visible;
-    for (int64_t i = gtid(); i < nv; i += gstride()) {
-        if (vslot[i] < 0) continue;
-        const int64_t base = (int64_t)vslot[i] * k;
-        uint32_t mk = line_mask[vslot[i]];
-        uint32_t o = off[i];
-        while (mk) {
-            const int j = __ffs(mk) - 1;
-            mk &= mk - 1u;
-            G[o++] = (int32_t)(base + j);
+__global__ __launch_bounds__(NT) void k_compose_scatter(const int32_t* __restrict__ vslot,
+                                                        const uint16_t* __restrict__ line_mask, int k, Counters* cnt,
+                                                        const uint32_t* __restrict__ block_sums, int32_t* __restrict__ G) {
+    __shared__ uint32_t wsum[NT / 64];
+    uint32_t carry = blockscan::block_carry(block_sums, wsum, &cnt->n_gauss);
+    int64_t b0, b1;
+    blockscan::chunk_of(cnt->n_visible, blockscan::kTile, b0, b1);
+    for (int64_t base = b0; base < b1; base += blockscan::kTile) {
+        uint32_t mk[4], s = 0;
+        int32_t slot[4];
+        const int64_t i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            mk[r] = 0u;
+            slot[r] = -1;
+            if (i0 + r < b1) mk[r] = compose_mask(vslot, line_mask, i0 + r, slot[r]);
+            s += (uint32_t)__popc(mk[r]);
         }
+        uint32_t tot;
+        uint32_t o = carry + blockscan::block_excl_scan(s, wsum, tot);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gb = (int64_t)slot[r] * k;
+            uint32_t m = mk[r];
+            while (m) {
+                const int j = __ffs(m) - 1;
+                m &= m - 1u;
+                G[o++] = (int32_t)(gb + j);
+            }
+        }
+        carry += tot;
     }
 }
-
 
 }  // namespace
 
@@ -495,11 +530,10 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
     }
     mark(mk, 2, st);
     // compose the render buffer
-    hipLaunchKernelGGL(k_compose_count, grid_fit(k_compose_count, n), dim3(NT), 0, st, v.vslot, v.line_mask, cnt,
-                       v.tmp_a, a.d_max, a.guide);
-    GSC_TRY(scan_u32(v.tmp_a, v.tmp_b, &cnt->n_visible, 0, &cnt->n_gauss, v.block_sums, st));
-    hipLaunchKernelGGL(k_compose_write, grid_fit(k_compose_write, n), dim3(NT), 0, st, v.vslot, v.line_mask, sc.k, cnt,
-                       v.tmp_b, v.G);
+    hipLaunchKernelGGL(k_compose_reduce, dim3(kScanBlocks), dim3(NT), 0, st, v.vslot, v.line_mask, cnt, a.d_max, a.guide,
+                       v.block_sums);
+    hipLaunchKernelGGL(k_compose_scatter, dim3(kScanBlocks), dim3(NT), 0, st, v.vslot, v.line_mask, sc.k, cnt,
+                       v.block_sums, v.G);
     mark(mk, 3, st);
     return hipGetLastError();
 }

@@ -4,6 +4,7 @@
 // read the element count from device memory, so a frame never needs a host
 // round trip to size a launch.  Wave64 throughout: wave scans use
 // __shfl_up over 64 lanes, digit ranking uses 64-bit ballots.
+#include "gsc_blockscan.h"
 #include "gsc_common.h"
 
 namespace gsc {
@@ -16,45 +17,12 @@ constexpr int SORT_IPT = 16;     // elements per thread per sort step
 constexpr int SORT_TILE = NT * SORT_IPT;
 constexpr int SORT_WSEG = SORT_TILE / 4;  // elements per wave per step
 
-__device__ __forceinline__ int64_t count_of(const int32_t* n_dev, int64_t n_host) {
-    return n_dev ? (int64_t)(*n_dev) : n_host;
-}
-
-__device__ __forceinline__ void chunk_of(int64_t n, int64_t align, int64_t& b0, int64_t& b1) {
-    int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    per = (per + align - 1) / align * align;
-    b0 = (int64_t)blockIdx.x * per;
-    b1 = b0 + per < n ? b0 + per : n;
-}
-
-// Exclusive scan across the 256 threads of a block (one value each).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) {
-        uint32_t s = wsum[i];
-        pre += i < w ? s : 0u;
-        tot += s;
-    }
-    __syncthreads();
-    total = tot;
-    return pre + x - v;
-}
-
-__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* wsum) {
-    uint32_t t;
-    block_excl_scan(v, wsum, t);
-    return t;
-}
+using blockscan::block_carry;
+using blockscan::block_excl_scan;
+using blockscan::block_sum;
+using blockscan::chunk_of;
+using blockscan::count_of;
+static_assert(NT == blockscan::kThreads && SCAN_TILE == blockscan::kTile, "scan block shape");
 
 // ------------------------------------------------------------------ scan
 
@@ -69,17 +37,14 @@ __global__ __launch_bounds__(NT) void k_scan_reduce(const uint32_t* __restrict__
     if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
 }
 
-// Each block takes its carry as the sum of the preceding blocks' sums (at
-// most kScanBlocks values, a block reduction), so no separate pass over the
-// block sums is needed; the last block writes the total.
+// Each block takes its carry as the sum of the preceding blocks' sums (a
+// block reduction, no separate pass over the block sums); the last block
+// writes the total.
 __global__ __launch_bounds__(NT) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                   const int32_t* n_dev, int64_t n_host,
                                                   const uint32_t* __restrict__ block_sums, int32_t* total) {
     __shared__ uint32_t wsum[NT / 64];
-    uint32_t part = 0;
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += NT) part += block_sums[i];
-    uint32_t carry = block_sum(part, wsum);
-    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = (int32_t)(carry + block_sums[blockIdx.x]);
+    uint32_t carry = block_carry(block_sums, wsum, total);
     int64_t b0, b1;
     chunk_of(count_of(n_dev, n_host), SCAN_TILE, b0, b1);
     for (int64_t base = b0; base < b1; base += SCAN_TILE) {
@@ -107,10 +72,7 @@ __global__ __launch_bounds__(NT) void k_scan_compact(const uint32_t* __restrict_
                                                      const int32_t* n_dev, int64_t n_host,
                                                      const uint32_t* __restrict__ block_sums, int32_t* total) {
     __shared__ uint32_t wsum[NT / 64];
-    uint32_t part = 0;
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += NT) part += block_sums[i];
-    uint32_t carry = block_sum(part, wsum);
-    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = (int32_t)(carry + block_sums[blockIdx.x]);
+    uint32_t carry = block_carry(block_sums, wsum, total);
     int64_t b0, b1;
     chunk_of(count_of(n_dev, n_host), SCAN_TILE, b0, b1);
     for (int64_t base = b0; base < b1; base += SCAN_TILE) {
