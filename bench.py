@@ -75,6 +75,11 @@ def parse():
     ap.add_argument("--serving-frames", type=int, default=600)
     ap.add_argument("--viewers", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--queue-timeout-ms", type=float, default=0.0,
+                    help="serving queue policy: drop requests older than this (0: off)")
+    ap.add_argument("--queue-pose-m", type=float, default=0.0, help="serving queue policy: pose gate, metres (0: off)")
+    ap.add_argument("--queue-pose-deg", type=float, default=0.0, help="serving queue policy: pose gate, degrees (0: off)")
+    ap.add_argument("--queue-ordered", action="store_true", help="serving queue policy: discard frames delivered late")
     return ap.parse_args()
 
 
@@ -432,6 +437,8 @@ def run_serving(args):
     form = args.form if not FORMS[args.form].get("predictor") else "cached-bf16"
     base = make_renderer(gs, scene, form, 2560, 1440, args)
     srv = gs.Server(base, int(args.budget_gb * (1 << 30)))
+    srv.policy(pose_m=args.queue_pose_m, pose_rad=math.radians(args.queue_pose_deg),
+               timeout_s=args.queue_timeout_ms * 1e-3, ordered=args.queue_ordered)
     # warm the kernels (one frame of the first viewer, separate server)
     warm = gs.Server(base, int(args.budget_gb * (1 << 30)))
     w0, h0 = wl[0]["res"]
@@ -449,6 +456,8 @@ def run_serving(args):
     pool = [[] for _ in range(nv)]
     req = {}                 # request id -> (viewer, frame, arrival, buffers)
     lat = [[] for _ in range(nv)]
+    outstanding = [0] * nv   # requests queued or in flight per viewer
+    dropped = {"unchanged": 0, "timeout": 0, "expired": 0}
     launched = completed = 0
     total = sum(len(v["arrivals"]) for v in wl)
     waits_admission = 0
@@ -473,9 +482,17 @@ def run_serving(args):
                                                        torch.empty(3, H, W, device="cuda"))
                 L, R = wl[v]["cams"][f]
                 rid = srv.submit(vid[v], L, R, t0 + arr[f], bufs[0], bufs[1])
-                req[rid] = (v, f, t0 + arr[f], bufs)
                 nxt[v] += 1
                 busy = True
+                if rid is None:  # pose gate: not queued
+                    dropped["unchanged"] += 1
+                    pool[v].append(bufs)
+                    completed += 1
+                    if nxt[v] == len(arr) and outstanding[v] == 0:
+                        srv.leave(vid[v])
+                    continue
+                req[rid] = (v, f, t0 + arr[f], bufs)
+                outstanding[v] += 1
         # keep one batch running and one queued behind it
         if launched - completed <= args.viewers:
             n = srv.step()
@@ -484,13 +501,16 @@ def run_serving(args):
         for rid, t_done, status in srv.poll(1024):
             busy = True
             v, f, ta, bufs = req.pop(rid)
-            if status != 0:
+            outstanding[v] -= 1
+            if status in (gs.GSC_E_TIMEOUT, gs.GSC_E_EXPIRED):
+                dropped["timeout" if status == gs.GSC_E_TIMEOUT else "expired"] += 1
+            elif status != 0:
                 raise RuntimeError("request %d failed with status %d" % (rid, status))
-            if f >= 10:
+            elif f >= 10:
                 lat[v].append(t_done - ta)
             pool[v].append(bufs)
             completed += 1
-            if nxt[v] == len(wl[v]["arrivals"]) and f == len(wl[v]["arrivals"]) - 1:
+            if nxt[v] == len(wl[v]["arrivals"]) and outstanding[v] == 0:
                 srv.leave(vid[v])
         if time.monotonic() - last_progress > 20.0:
             print("serving: %d/%d frames done" % (completed, total), file=sys.stderr, flush=True)
@@ -517,8 +537,12 @@ def run_serving(args):
            "latency_ms_by_resolution": {k: {"p50": round(1e3 * float(np.percentile(x, 50)), 3),
                                             "p99": round(1e3 * float(np.percentile(x, 99)), 3), "frames": len(x)}
                                         for k, x in per_res.items()},
-           "served_stereo_frames_per_s": round(total / wall, 2), "offered_per_s": round(nv * args.rate, 1),
-           "wall_s": round(wall, 2), "admission_retries": waits_admission}
+           "served_stereo_frames_per_s": round((total - sum(dropped.values())) / wall, 2),
+           "offered_per_s": round(nv * args.rate, 1),
+           "wall_s": round(wall, 2), "admission_retries": waits_admission,
+           "queue_policy": {"timeout_ms": args.queue_timeout_ms, "pose_m": args.queue_pose_m,
+                            "pose_deg": args.queue_pose_deg, "ordered": bool(args.queue_ordered)},
+           "dropped": dropped}
     srv.close()
     print(json.dumps(out), flush=True)
 

@@ -44,6 +44,9 @@ extern "C" {
 #define GSC_E_CAPACITY (-4)    /* tile-pair or cache capacity exceeded this frame (see stats) */
 #define GSC_E_BUDGET (-5)      /* serving: viewer does not fit the HBM budget now */
 #define GSC_E_HIP (-6)         /* a HIP runtime call failed */
+#define GSC_E_UNCHANGED (-7)   /* serving queue: pose changed less than the threshold; not queued */
+#define GSC_E_TIMEOUT (-8)     /* serving queue (poll status): older than the timeout; dropped unrendered */
+#define GSC_E_EXPIRED (-9)     /* serving queue (poll status): a newer frame of the viewer was delivered first */
 
 /* Derivation arithmetic (the projection and compositing are always FP32). */
 #define GSC_PREC_F32 0  /* FP32 weights, activations and accumulation */
@@ -364,6 +367,20 @@ int gsc_server_step(gsc_server* s);
 int gsc_server_poll(gsc_server* s, int64_t* ids, double* t_done, int32_t* status, int32_t cap);
 /* Requests queued or in flight. */
 int gsc_server_pending(gsc_server* s);
+/* Queue policy of Section 5 (each part off when its argument is negative or
+ * zero; all off by default):
+ *   pose gate: gsc_server_submit queues a request only when its unified
+ *     camera moved more than pose_m (metres) or turned more than pose_rad
+ *     (radians, angle between viewing directions) since the viewer's last
+ *     queued request; otherwise it returns GSC_E_UNCHANGED, nothing queued;
+ *   timeout: gsc_server_step drops queued requests whose t_arrival is more
+ *     than timeout_s before the host monotonic clock (t_arrival must be on
+ *     that clock), unrendered; poll reports them with GSC_E_TIMEOUT;
+ *   ordered (nonzero): a request that finishes after a request of the same
+ *     viewer with a later t_arrival was delivered is discarded; poll reports
+ *     it with GSC_E_EXPIRED (its output buffers hold the render anyway).
+ * Applies to later calls; queued requests keep their place. */
+int gsc_server_policy(gsc_server* s, double pose_m, double pose_rad, double timeout_s, int ordered);
 /* Remove a viewer with no queued requests and free its buffers (waits for
  * outstanding batches). */
 int gsc_server_leave(gsc_server* s, int32_t viewer);

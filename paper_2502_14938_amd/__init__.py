@@ -15,8 +15,9 @@ LIB_PATH = os.path.join(_HERE, "libgscache.so")
 
 GSC_OK = 0
 GSC_E_INVALID_ARG, GSC_E_NOT_LOADED, GSC_E_OOM, GSC_E_CAPACITY, GSC_E_BUDGET, GSC_E_HIP = -1, -2, -3, -4, -5, -6
+GSC_E_UNCHANGED, GSC_E_TIMEOUT, GSC_E_EXPIRED = -7, -8, -9
 ERRORS = {-1: "GSC_E_INVALID_ARG", -2: "GSC_E_NOT_LOADED", -3: "GSC_E_OOM", -4: "GSC_E_CAPACITY",
-          -5: "GSC_E_BUDGET", -6: "GSC_E_HIP"}
+          -5: "GSC_E_BUDGET", -6: "GSC_E_HIP", -7: "GSC_E_UNCHANGED", -8: "GSC_E_TIMEOUT", -9: "GSC_E_EXPIRED"}
 PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT = 1, 2, 4, 8
 GUIDE = {"linear": 0, "fixed": 1}
@@ -106,6 +107,7 @@ SYMBOLS = {
     "gsc_server_step": ([C.c_void_p], C.c_int),
     "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "gsc_server_pending": ([C.c_void_p], C.c_int),
+    "gsc_server_policy": ([C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int], C.c_int),
     "gsc_timing": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing_stages": ([C.c_void_p, C.c_uint32], C.c_int),
     "gsc_count_work": ([C.c_void_p, C.c_int], C.c_int),
@@ -400,12 +402,22 @@ class Server:
             return None
         return self._check(rc)
 
-    def submit(self, viewer, left: dict, right: dict, t_arrival, out_left, out_right) -> int:
+    def submit(self, viewer, left: dict, right: dict, t_arrival, out_left, out_right):
+        """Request id, or None when the queue policy's pose gate did not queue it."""
         l, r = camera(left), camera(right)
-        rid = self._check(lib().gsc_server_submit(self.h, viewer, C.byref(l), C.byref(r), float(t_arrival),
-                                                  _ptr(out_left), _ptr(out_right)))
+        rc = lib().gsc_server_submit(self.h, viewer, C.byref(l), C.byref(r), float(t_arrival),
+                                     _ptr(out_left), _ptr(out_right))
+        if rc == GSC_E_UNCHANGED:
+            return None
+        rid = self._check(rc)
         self._outs[rid] = (out_left, out_right)  # keep the buffers alive until completion
         return rid
+
+    def policy(self, pose_m=0.0, pose_rad=0.0, timeout_s=0.0, ordered=False):
+        """Queue policy (each part off at <= 0): pose gate, timeout on the
+        host monotonic clock (time.monotonic()), display order."""
+        self._check(lib().gsc_server_policy(self.h, float(pose_m), float(pose_rad), float(timeout_s),
+                                            1 if ordered else 0))
 
     def step(self) -> int:
         return self._check(lib().gsc_server_step(self.h))

@@ -15,6 +15,7 @@
 //   poll     completions, timestamped on the host monotonic clock by a host
 //            function the stream runs when the batch's kernels are done
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <ctime>
 #include <deque>
@@ -50,6 +51,8 @@ struct Request {
 
 struct Viewer {
     int32_t max_w = 0, max_h = 0;
+    bool has_pose = false;            // pose of the last queued request (pose gate)
+    double pose[3] = {0, 0, 0}, dir[3] = {0, 0, 1};
     View v;
     AllocSet mem;
     int64_t entries = 0, pairs = 0, tiles = 0;  // share of the batch raster
@@ -85,6 +88,10 @@ struct gsc_server {
         int32_t status;
     };
     std::vector<Done> done;
+    std::vector<double> last_delivered;  // per viewer slot: t_arrival of its last delivered frame
+    // queue policy (gsc_server_policy); <= 0: off
+    double pose_m = 0.0, pose_rad = 0.0, timeout_s = 0.0;
+    bool ordered = false;
     std::vector<BatchReport*> free_reports;
     std::vector<BatchReport*> all_reports;
     int64_t in_flight = 0;
@@ -98,6 +105,8 @@ struct Batch {
     int nviewers;
     std::vector<int64_t> ids;
     std::vector<int> viewer_of;  // batch-local viewer index of each request
+    std::vector<int32_t> viewer_id;
+    std::vector<double> t_arrival;
 };
 
 int sfail(gsc_server* s, int code, const std::string& msg) {
@@ -114,7 +123,14 @@ void on_batch_done(void* p) {
         const bool pairs_over = (b->rep->rc.overflow & 7) != 0;
         for (size_t i = 0; i < b->ids.size(); ++i) {
             const bool cache_over = (b->rep->vc[b->viewer_of[i]].overflow & 2) != 0;
-            s->done.push_back({b->ids[i], t, (pairs_over || cache_over) ? GSC_E_CAPACITY : GSC_OK});
+            int32_t status = (pairs_over || cache_over) ? GSC_E_CAPACITY : GSC_OK;
+            if (s->ordered && status == GSC_OK) {
+                // display order: never deliver a frame older than one already delivered
+                double& last = s->last_delivered[(size_t)b->viewer_id[i]];
+                if (b->t_arrival[i] < last) status = GSC_E_EXPIRED;
+                else last = b->t_arrival[i];
+            }
+            s->done.push_back({b->ids[i], t, status});
         }
         s->free_reports.push_back(b->rep);
         s->in_flight -= 1;
@@ -262,6 +278,11 @@ int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height) {
         return sfail(s, GSC_E_HIP, "gsc_server_admit: cache reset failed");
     }
     s->viewers[id] = std::move(v);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);  // completions read it on a runtime thread
+        if (s->last_delivered.size() < s->viewers.size()) s->last_delivered.resize(s->viewers.size());
+        s->last_delivered[(size_t)id] = -INFINITY;
+    }
     if (resize_raster(s) != hipSuccess) {
         s->viewers[id]->mem.release();
         s->viewers[id].reset();
@@ -286,10 +307,30 @@ int64_t gsc_server_submit(gsc_server* s, int32_t viewer, const gsc_camera* left,
     if (left->width > v->max_w || left->height > v->max_h)
         return sfail(s, GSC_E_INVALID_ARG, "gsc_server_submit: image larger than the viewer's admitted size");
     Request r;
-    r.id = s->next_id++;
     r.eye[0] = *left;
     r.eye[1] = *right;
     unified_camera(*left, *right, r.unified);
+    // viewing direction: the camera's z axis in world coordinates (third row
+    // of the world-to-camera rotation)
+    const double dir[3] = {r.unified.R[6], r.unified.R[7], r.unified.R[8]};
+    if ((s->pose_m > 0.0 || s->pose_rad > 0.0) && v->has_pose) {
+        double d2 = 0.0, dot = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double dp = r.unified.pos[k] - v->pose[k];
+            d2 += dp * dp;
+            dot += dir[k] * v->dir[k];
+        }
+        const double ang = std::acos(std::max(-1.0, std::min(1.0, dot)));
+        const bool moved = s->pose_m > 0.0 && std::sqrt(d2) > s->pose_m;
+        const bool turned = s->pose_rad > 0.0 && ang > s->pose_rad;
+        if (!moved && !turned) return sfail(s, GSC_E_UNCHANGED, "gsc_server_submit: pose change below the threshold");
+    }
+    v->has_pose = true;
+    for (int k = 0; k < 3; ++k) {
+        v->pose[k] = r.unified.pos[k];
+        v->dir[k] = dir[k];
+    }
+    r.id = s->next_id++;
     r.t_arrival = t_arrival;
     r.out[0] = out_left;
     r.out[1] = out_right;
@@ -300,6 +341,18 @@ int64_t gsc_server_submit(gsc_server* s, int32_t viewer, const gsc_camera* left,
 int gsc_server_step(gsc_server* s) {
     if (!s) return GSC_E_INVALID_ARG;
     gsc_ctx* c = s->ctx;
+    // queue timeout: requests waited too long are dropped unrendered
+    if (s->timeout_s > 0.0) {
+        const double now = now_monotonic();
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto& vp : s->viewers) {
+            if (!vp) continue;
+            while (!vp->queue.empty() && now - vp->queue.front().t_arrival > s->timeout_s) {
+                s->done.push_back({vp->queue.front().id, now, GSC_E_TIMEOUT});
+                vp->queue.pop_front();
+            }
+        }
+    }
     // oldest head request first, one request per viewer per batch
     std::vector<int32_t> pick;
     for (int32_t i = 0; i < (int32_t)s->viewers.size(); ++i)
@@ -373,6 +426,8 @@ int gsc_server_step(gsc_server* s) {
         }
         b->ids.push_back(r.id);
         b->viewer_of.push_back(i);
+        b->viewer_id.push_back(pick[i]);
+        b->t_arrival.push_back(r.t_arrival);
         if (hipMemcpyAsync(&rep->vc[i], v.v.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s->st) != hipSuccess) {
             delete b;
             return sfail(s, GSC_E_HIP, "gsc_server_step: counter copy");
@@ -412,6 +467,18 @@ int gsc_server_poll(gsc_server* s, int64_t* ids, double* t_done, int32_t* status
     }
     s->done.erase(s->done.begin(), s->done.begin() + m);
     return m;
+}
+
+int gsc_server_policy(gsc_server* s, double pose_m, double pose_rad, double timeout_s, int ordered) {
+    if (!s) return GSC_E_INVALID_ARG;
+    if (!std::isfinite(pose_m) || !std::isfinite(pose_rad) || !std::isfinite(timeout_s))
+        return sfail(s, GSC_E_INVALID_ARG, "gsc_server_policy: non-finite argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->pose_m = pose_m;
+    s->pose_rad = pose_rad;
+    s->timeout_s = timeout_s;
+    s->ordered = ordered != 0;
+    return GSC_OK;
 }
 
 int gsc_server_pending(gsc_server* s) {

@@ -69,6 +69,7 @@ def test_null_and_invalid_arguments(L):
     assert L.gsc_pipeline(None, 1) == -1
     assert L.gsc_timing_stages(None, 1) == -1
     assert L.gsc_count_work(None, 1) == -1
+    assert L.gsc_server_policy(None, 0.0, 0.0, 0.0, 0) == -1
     L.gsc_destroy(None)
 
 
