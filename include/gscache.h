@@ -65,6 +65,10 @@ extern "C" {
 /* Cache depth guiding function H (eq. 4). */
 #define GSC_GUIDE_LINEAR 0 /* d = clamp(round_half_up(d_max (1 - r)), 1, d_max), r = misses/visible */
 #define GSC_GUIDE_FIXED 1  /* d = d_max every frame */
+/* Responses for accelerating and for staged motion (Section 7 names them,
+ * without formulas; these are integer readings of them): */
+#define GSC_GUIDE_EXP 2    /* d = clamp(d_max >> floor(8 r), 1, d_max): halved per eighth of update rate */
+#define GSC_GUIDE_STAGED 3 /* d = d_max if r < 1/8, max(1, d_max / 2) if r < 3/8, else 1 */
 
 typedef struct gsc_config {
     int32_t k;                  /* neural Gaussians per anchor (offsets), 1..16 */

@@ -22,6 +22,8 @@ import ctypes as C
 import math
 import os
 
+from fractions import Fraction
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -254,6 +256,22 @@ def render_gaussians(mu, cov, rgb, alpha, cam: dict, debug: bool = False):
 
 # ------------------------------------------------------- derived-Gaussian cache
 
+def guide_depth(guide: str, d_max: int, nx: int, nm: int) -> int:
+    """Next reuse depth from eq. 4, depth = H(|X'|/|X|), for nx > 0 visible
+    anchors of which nm were decoded this frame (the update rate r = nm/nx),
+    in exact rational arithmetic."""
+    r = Fraction(nm, nx)
+    if guide == "linear":
+        d = math.floor(d_max * (1 - r) + Fraction(1, 2))  # round half up
+    elif guide == "exp":
+        d = d_max // 2 ** math.floor(8 * r)
+    elif guide == "staged":
+        d = d_max if r < Fraction(1, 8) else (d_max // 2 if r < Fraction(3, 8) else 1)
+    else:
+        raise ValueError(guide)
+    return int(min(max(d, 1), d_max))
+
+
 class CacheSim:
     """Exact integer model of the computation cache with dynamic reuse depth
     (Section 4, Alg. 1, eq. 4), per viewer.
@@ -274,10 +292,18 @@ class CacheSim:
          d_{t+1} = clamp(round_half_up(D_max (1 - r)), 1, D_max), computed
          exactly as floor((2 D_max (|X|-|M|) + |X|) / (2 |X|)); unchanged
          when |X| = 0.  d_0 = D_max.
+    Other guiding functions H of eq. 4 (guide=): "fixed" keeps D_max;
+    "exp" and "staged" are readings of the exponential and staged responses
+    the quality evaluation (Section 7) names for accelerating and staged
+    motion, without formulas: exp halves D_max once per eighth of update
+    rate, d = D_max // 2**floor(8 r); staged steps from D_max (r < 1/8) to
+    D_max // 2 (r < 3/8) to 1; both clamped to [1, D_max].
     """
 
-    def __init__(self, n_anchors: int, capacity: int, d_max: int = 10, reuse: bool = True):
-        self.n, self.C, self.D, self.reuse = n_anchors, capacity, d_max, reuse
+    def __init__(self, n_anchors: int, capacity: int, d_max: int = 10, reuse: bool = True, guide: str = "linear"):
+        if guide not in ("linear", "fixed", "exp", "staged"):
+            raise ValueError(guide)
+        self.n, self.C, self.D, self.reuse, self.guide = n_anchors, capacity, d_max, reuse, guide
         self.slot_of = np.full(n_anchors, -1, np.int64)
         self.line_anchor = np.full(capacity, -1, np.int64)
         self.tau = np.zeros(capacity, np.int64)
@@ -326,9 +352,10 @@ class CacheSim:
         self.last_used[self.slot_of[vis]] = t
         # 5. depth
         nx, nm = len(vis), len(miss_ids)
-        if nx > 0:
-            dn = (2 * self.D * (nx - nm) + nx) // (2 * nx)
-            self.d = int(min(max(dn, 1), self.D))
+        if self.guide == "fixed":
+            self.d = self.D
+        elif nx > 0:
+            self.d = guide_depth(self.guide, self.D, nx, nm)
         self.t += 1
         return {"t": t, "d_used": d, "d_next": self.d, "hit": hit, "misses": miss_ids,
                 "n_visible": nx, "n_miss": nm, "evicted": evicted, "slot": self.slot_of[vis].copy()}

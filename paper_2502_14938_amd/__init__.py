@@ -20,7 +20,7 @@ ERRORS = {-1: "GSC_E_INVALID_ARG", -2: "GSC_E_NOT_LOADED", -3: "GSC_E_OOM", -4: 
           -5: "GSC_E_BUDGET", -6: "GSC_E_HIP", -7: "GSC_E_UNCHANGED", -8: "GSC_E_TIMEOUT", -9: "GSC_E_EXPIRED"}
 PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT = 1, 2, 4, 8
-GUIDE = {"linear": 0, "fixed": 1}
+GUIDE = {"linear": 0, "fixed": 1, "exp": 2, "staged": 3}
 DBG = {"visible": 0, "misses": 1, "gauss": 2, "derived": 3, "pairs": 4, "ranges": 5, "preproc": 6, "depth": 7}
 PRED_NPARAMS = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1  # 4673
 

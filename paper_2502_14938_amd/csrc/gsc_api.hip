@@ -336,7 +336,7 @@ int gsc_create(const gsc_config* cfg, void* stream, gsc_ctx** out) {
     if (cfg->d_max < 1 || cfg->d_max > 63) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: d_max must be in [1, 63]");
     if (cfg->precision < GSC_PREC_F32 || cfg->precision > GSC_PREC_FP8)
         return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: bad precision");
-    if (cfg->guide != GSC_GUIDE_LINEAR && cfg->guide != GSC_GUIDE_FIXED)
+    if (cfg->guide < GSC_GUIDE_LINEAR || cfg->guide > GSC_GUIDE_STAGED)
         return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: bad guide");
     if (cfg->max_width < 1 || cfg->max_height < 1 || cfg->max_width > 16384 || cfg->max_height > 16384)
         return fail(nullptr, GSC_E_INVALID_ARG, "gsc_create: max image size out of range");

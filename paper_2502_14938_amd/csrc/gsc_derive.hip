@@ -350,7 +350,15 @@ __device__ __forceinline__ void depth_update(Counters* cnt, int32_t dmax, int32_
         return;
     }
     if (nx <= 0) return;
-    int64_t d = (2ll * dmax * (nx - nm) + nx) / (2ll * nx);
+    int64_t d;
+    if (guide == GSC_GUIDE_EXP) {
+        const int64_t q = (8ll * nm) / nx;  // eighths of update rate
+        d = q >= 31 ? 0 : ((int64_t)dmax >> q);
+    } else if (guide == GSC_GUIDE_STAGED) {
+        d = 8ll * nm < nx ? dmax : (8ll * nm < 3ll * nx ? dmax / 2 : 1);
+    } else {  // linear: round_half_up(d_max (1 - r))
+        d = (2ll * dmax * (nx - nm) + nx) / (2ll * nx);
+    }
     cnt->depth = (int32_t)(d < 1 ? 1 : (d > dmax ? dmax : d));
 }
 

@@ -78,16 +78,19 @@ def walk(n, step=0.15, turn=0.02):
     return out
 
 
-def test_cache_sequence_matches_model(gs, tiny):
+@pytest.mark.parametrize("guide", ["linear", "exp", "staged"])
+def test_cache_sequence_matches_model(gs, tiny, guide):
     traj = walk(12)
-    r = gs.Renderer(k=tiny.k, reuse=True, d_max=10, max_width=128, max_height=96, cache_capacity=tiny.n)
+    r = gs.Renderer(k=tiny.k, reuse=True, d_max=10, guide=guide, max_width=128, max_height=96, cache_capacity=tiny.n)
     r.load(tiny)
-    sim = oracle.CacheSim(tiny.n, tiny.n, 10)
+    sim = oracle.CacheSim(tiny.n, tiny.n, 10, guide=guide)
     lines = {}
+    depths = []
     for i, (L, R) in enumerate(traj):
         iL, iR = gpu_frame(r, L, R)
         ref = oracle.render_frame(tiny, L, R, cache=sim, cache_lines=lines)
         st = r.stats()
+        depths.append(st["depth_next"])
         if ref["select_band"][ref["visible"]].any():
             continue
         assert st["n_visible"] == len(ref["visible"]), i
@@ -96,6 +99,7 @@ def test_cache_sequence_matches_model(gs, tiny):
         assert np.array_equal(r.debug("misses"), ref["cache"]["misses"]), i
         assert_image(iL, ref["left"])
         assert_image(iR, ref["right"])
+    assert len(set(depths)) > 1, depths  # the guide responded along the walk
 
 
 def pan(n, fov, step):

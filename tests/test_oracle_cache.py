@@ -11,6 +11,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 import oracle
 import synth
@@ -71,3 +72,27 @@ def test_cache_counts_and_depth_range():
         assert np.all(t - sim.tau[used] <= r["d_used"])
         # every visible anchor now owns a line that maps back to it
         assert np.all(sim.line_anchor[sim.slot_of[vis]] == vis)
+
+
+@pytest.mark.parametrize("guide,cases", [
+    # (nx, nm) -> next depth with D_max = 10, worked by hand
+    ("linear", [((100, 0), 10), ((100, 25), 8), ((100, 5), 10), ((100, 15), 9), ((100, 100), 1), ((3, 1), 7)]),
+    # halved per eighth of update rate: r = 0.12 -> 10, 0.13 -> 5, 0.25 -> 2, 0.375 -> 1, 1 -> 1
+    ("exp", [((100, 0), 10), ((100, 12), 10), ((100, 13), 5), ((100, 25), 2), ((8, 3), 1), ((100, 100), 1)]),
+    # steps at r = 1/8 and 3/8
+    ("staged", [((100, 12), 10), ((8, 1), 5), ((100, 13), 5), ((100, 37), 5), ((8, 3), 1), ((100, 38), 1)]),
+])
+def test_guide_functions_worked_values(guide, cases):
+    for (nx, nm), want in cases:
+        assert oracle.guide_depth(guide, 10, nx, nm) == want, (guide, nx, nm)
+
+
+@pytest.mark.parametrize("guide", ["linear", "exp", "staged"])
+def test_guide_functions_monotone_and_bounded(guide):
+    for D in (1, 2, 7, 10, 63):
+        prev = D
+        for nm in range(0, 201):
+            d = oracle.guide_depth(guide, D, 200, nm)
+            assert 1 <= d <= D and d <= prev, (guide, D, nm)
+            prev = d
+        assert oracle.guide_depth(guide, D, 200, 0) == D  # nothing decoded: full depth
