@@ -210,16 +210,17 @@ def quality_pass(torch, r, plain, traj, W, H):
     plain.reset_cache()
     r.count_work(True)  # blend visit counts for the roofline (same frames as the timed pass)
     a = [torch.zeros(3, H, W, device="cuda") for _ in range(4)]
-    ps, counts = [], []
+    ps, ss, counts = [], [], []
     for L, R in traj:
         r.frame(L, R, a[0], a[1])
         st = r.stats()
         if plain is not r:
             plain.frame(L, R, a[2], a[3])
             ps += [psnr_dev(torch, a[0], a[2]), psnr_dev(torch, a[1], a[3])]
+            ss += [r.ssim(a[0], a[2]), r.ssim(a[1], a[3])]  # on the device (gsc_ssim)
         counts.append(st)
     r.count_work(False)
-    return np.array(ps), counts
+    return np.array(ps), np.array(ss), counts
 
 
 def stage_bytes(counts, W, H, frames):
@@ -334,9 +335,10 @@ def run_frames(args):
     quality = None
     if not args.no_quality:
         ref = plain if plain is not None else (make_renderer(gs, scene, "plain", W, H, args) if form != "plain" else r)
-        ps, counts = quality_pass(torch, r, ref, traj, W, H)
+        ps, ss, counts = quality_pass(torch, r, ref, traj, W, H)
         if form != "plain":
             quality = {"psnr_db_min": round(float(ps.min()), 3), "psnr_db_mean": round(float(ps.mean()), 3),
+                       "ssim_min": round(float(ss.min()), 5), "ssim_mean": round(float(ss.mean()), 5),
                        "gate_40db": bool(ps.min() >= 40.0), "images": int(len(ps))}
     else:
         counts = []

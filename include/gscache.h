@@ -245,6 +245,17 @@ int gsc_count_work(gsc_ctx* ctx, int enable);
  * overlaps the stages of consecutive frames instead. */
 int gsc_pipeline(gsc_ctx* ctx, int enable);
 
+/* Mean SSIM of two device images a, b (float32 [channels, height, width],
+ * values in [0, 1]) into *out (host): the quality table's third metric
+ * (Table 4), as Wang et al. define it: an 11 x 11 Gaussian window (sigma
+ * 1.5, normalised), C1 = 0.01^2, C2 = 0.03^2, the map averaged over every
+ * window position inside the image and over channels.  Waits for the
+ * context's streams first (the images may come from a frame in flight) and
+ * at the end; allocates a small scratch buffer per call.  height and width
+ * at least 11, channels 1..65535 (GSC_E_INVALID_ARG otherwise). */
+int gsc_ssim(gsc_ctx* ctx, const float* a, const float* b, int32_t channels, int32_t height, int32_t width,
+             double* out);
+
 /* ---------------- stage timing -------------------------------------------
  * With timing on, every frame (gsc_derive + gsc_render_stereo) records HIP
  * events on the context's stream at its stage boundaries; gsc_timing_read

@@ -413,6 +413,46 @@ def psnr(img, ref) -> float:
     return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
 
 
+# SSIM (Table 4's third quality metric), as defined by Wang et al. (2004):
+# per channel, local means, variances and covariance under an 11 x 11
+# Gaussian window (sigma 1.5, weights normalised to sum 1), constants
+# C1 = (0.01 L)^2 and C2 = (0.03 L)^2 for dynamic range L = 1, the SSIM map
+# ((2 mu_x mu_y + C1)(2 s_xy + C2)) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2))
+# over every window position inside the image ("valid"), averaged over
+# positions and channels.  FP64.
+
+def ssim_window(size: int = 11, sigma: float = 1.5) -> np.ndarray:
+    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-x * x / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def _blur_valid(img: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Separable correlation of [H, W] with w (x) w over the valid region."""
+    n = len(w)
+    H, W = img.shape
+    rows = sum(w[i] * img[i:H - n + 1 + i, :] for i in range(n))
+    return sum(w[j] * rows[:, j:W - n + 1 + j] for j in range(n))
+
+
+def ssim(img, ref) -> float:
+    """Mean SSIM of two [C, H, W] images in [0, 1] (H, W >= 11)."""
+    a = np.asarray(img, np.float64)
+    b = np.asarray(ref, np.float64)
+    w = ssim_window()
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    vals = []
+    for ch in range(a.shape[0]):
+        x, y = a[ch], b[ch]
+        mx, my = _blur_valid(x, w), _blur_valid(y, w)
+        sxx = _blur_valid(x * x, w) - mx * mx
+        syy = _blur_valid(y * y, w) - my * my
+        sxy = _blur_valid(x * y, w) - mx * my
+        m = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+        vals.append(m)
+    return float(np.mean(vals))
+
+
 def max_abs(img, ref) -> float:
     return float(np.max(np.abs(np.asarray(img, np.float64) - np.asarray(ref, np.float64))))
 

@@ -112,6 +112,7 @@ SYMBOLS = {
     "gsc_timing_stages": ([C.c_void_p, C.c_uint32], C.c_int),
     "gsc_count_work": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_pipeline": ([C.c_void_p, C.c_int], C.c_int),
+    "gsc_ssim": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p], C.c_int),
     "gsc_timing_read": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gsc_server_last_error": ([C.c_void_p], C.c_char_p),
     "gsc_server_leave": ([C.c_void_p, C.c_int32], C.c_int),
@@ -283,6 +284,15 @@ class Renderer:
         stages up to its tile ranges.  A frame's images are complete only
         after sync() (or a later call that waits, such as stats())."""
         self._check(lib().gsc_pipeline(self.h, 1 if enable else 0))
+
+    def ssim(self, a, b) -> float:
+        """Mean SSIM of two device float32 [C, H, W] images (H, W >= 11)."""
+        assert a.is_cuda and b.is_cuda and a.shape == b.shape and a.dim() == 3
+        assert a.dtype == b.dtype and a.dtype.itemsize == 4 and a.is_contiguous() and b.is_contiguous()
+        out = C.c_double()
+        self._check(lib().gsc_ssim(self.h, _ptr(a), _ptr(b), int(a.shape[0]), int(a.shape[1]), int(a.shape[2]),
+                                   C.byref(out)))
+        return out.value
 
     def timing(self, enable=True, stages=None):
         """Record device time of every frame from now on (or stop): the frame

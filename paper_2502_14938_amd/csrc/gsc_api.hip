@@ -715,6 +715,33 @@ int gsc_pipeline(gsc_ctx* c, int enable) {
     return GSC_OK;
 }
 
+int gsc_ssim(gsc_ctx* c, const float* a, const float* b, int32_t channels, int32_t height, int32_t width,
+             double* out) {
+    if (!c || !a || !b || !out) return fail(c, GSC_E_INVALID_ARG, "gsc_ssim: null argument");
+    if (channels < 1 || channels > 65535 || height < 11 || width < 11 || height > 65536 || width > 65536)
+        return fail(c, GSC_E_INVALID_ARG, "gsc_ssim: images of 1..65535 channels, at least 11 x 11 pixels");
+    HIP_OR_FAIL(c, sync_all(c));  // the images may come from a frame still in flight
+    SsimWindow win;
+    double g[11], sum = 0.0;
+    for (int i = 0; i < 11; ++i) {
+        const double x = i - 5.0;
+        g[i] = std::exp(-x * x / (2.0 * 1.5 * 1.5));
+        sum += g[i];
+    }
+    for (int i = 0; i < 11; ++i) win.w[i] = g[i] / sum;
+    const int64_t nb = ssim_blocks(channels, height, width);
+    double* buf = nullptr;  // [0]: total, [1..nb]: per-block sums
+    HIP_OR_FAIL(c, hipMalloc((void**)&buf, (size_t)(nb + 1) * sizeof(double)));
+    hipError_t e = ssim_launch(a, b, channels, height, width, win, buf + 1, buf, c->stream);
+    double tot = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&tot, buf, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(c, e, "gsc_ssim");
+    *out = tot / ((double)channels * (double)(height - 10) * (double)(width - 10));
+    return GSC_OK;
+}
+
 int gsc_timing(gsc_ctx* c, int enable) {
     if (!c) return fail(nullptr, GSC_E_INVALID_ARG, "gsc_timing: null context");
     HIP_OR_FAIL(c, sync_all(c));

@@ -244,6 +244,17 @@ inline void mark(Marks* m, int i, hipStream_t st) {
 
 hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr);
 
+// Mean SSIM (gsc_metrics.hip): the normalised 11-tap Gaussian window, the
+// number of per-block partial sums for C channels of H x W (H, W >= 11),
+// and the launch writing the partials and their total (the sum of the map
+// over every window position and channel) on the device.
+struct SsimWindow {
+    double w[11];
+};
+int64_t ssim_blocks(int C, int H, int W);
+hipError_t ssim_launch(const float* a, const float* b, int C, int H, int W, const SsimWindow& win, double* partial,
+                       double* total, hipStream_t st);
+
 // Raster stage of a batch of segments.
 // count_work: the blend also counts its (pixel, Gaussian) visits and
 // contributions per tile (and writes per-pixel contributor counts when a

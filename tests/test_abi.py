@@ -70,6 +70,8 @@ def test_null_and_invalid_arguments(L):
     assert L.gsc_timing_stages(None, 1) == -1
     assert L.gsc_count_work(None, 1) == -1
     assert L.gsc_server_policy(None, 0.0, 0.0, 0.0, 0) == -1
+    out = C.c_double()
+    assert L.gsc_ssim(None, None, None, 3, 16, 16, C.byref(out)) == -1
     L.gsc_destroy(None)
 
 

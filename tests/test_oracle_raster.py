@@ -233,3 +233,46 @@ def test_psnr_and_maxabs_definitions():
     a = np.random.default_rng(0).uniform(0.1, 0.9, (3, 8, 8))
     assert abs(oracle.psnr(a + 0.01, a) - 40.0) < 1e-9
     assert abs(oracle.max_abs(a + 0.01, a) - 0.01) < 1e-12
+
+
+# ---------------------------------------------------------------- SSIM
+
+def test_ssim_identical_is_one():
+    rng = np.random.default_rng(3)
+    x = rng.random((3, 17, 23))
+    assert abs(oracle.ssim(x, x) - 1.0) < 1e-12
+
+
+def test_ssim_constant_images_closed_form():
+    # constant images: zero variances, so SSIM = (2ab + C1) / (a^2 + b^2 + C1) at every window
+    a, b = 0.3, 0.7
+    c1 = 1e-4
+    want = (2 * a * b + c1) / (a * a + b * b + c1)
+    got = oracle.ssim(np.full((2, 12, 15), a), np.full((2, 12, 15), b))
+    assert abs(got - want) < 1e-12
+
+
+def test_ssim_window_sums_to_one_and_is_gaussian():
+    w = oracle.ssim_window()
+    assert len(w) == 11 and abs(w.sum() - 1.0) < 1e-15
+    assert abs(w[6] / w[5] - math.exp(-1.0 / (2 * 1.5 ** 2))) < 1e-12
+
+
+def test_ssim_matches_direct_windows():
+    # brute force: every 11 x 11 window with the 2-D Gaussian weights, no separability
+    rng = np.random.default_rng(5)
+    x, y = rng.random((1, 13, 14)), rng.random((1, 13, 14))
+    w = oracle.ssim_window()
+    w2 = np.outer(w, w)
+    c1, c2 = 1e-4, 9e-4
+    vals = []
+    for i in range(13 - 10):
+        for j in range(14 - 10):
+            px, py = x[0, i:i + 11, j:j + 11], y[0, i:i + 11, j:j + 11]
+            mx, my = (w2 * px).sum(), (w2 * py).sum()
+            vx = (w2 * (px - mx) ** 2).sum()
+            vy = (w2 * (py - my) ** 2).sum()
+            cxy = (w2 * (px - mx) * (py - my)).sum()
+            vals.append(((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2)))
+    assert abs(oracle.ssim(x, y) - float(np.mean(vals))) < 1e-12
+    assert abs(oracle.ssim(x, y) - oracle.ssim(y, x)) < 1e-15
