@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", default="frames", choices=["frames", "serving"])
+    ap.add_argument("--mode", default="frames", choices=["frames", "serving", "guides"])
     ap.add_argument("--form", default="cached-bf16-learned", choices=sorted(FORMS))
     ap.add_argument("--threshold", type=float, default=0.9, help="learned reuse: re-derive when p(stale) > this")
     ap.add_argument("--d-max", type=int, default=10)
@@ -549,6 +549,50 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+# --------------------------------------------------------------------------- guide ablation
+
+def run_guides(args):
+    """Guiding functions of eq. 4 against a static depth on an accelerating
+    fly-through: the 300-frame rise resampled at s = (i / 299)^2, so the
+    camera starts almost still and ends moving ~2x faster than the uniform
+    rise.  Per guide: stereo frames/s, mean update rate (misses / visible),
+    depth range and PSNR against plain FP32 on every frame."""
+    import torch
+    import paper_2502_14938_amd as gs
+    import synth
+
+    torch.cuda.set_device(0)
+    scene = synth.city_scene()
+    W, H = synth.CITY_W, synth.CITY_H
+    dense = synth.city_flythrough(1200)
+    traj = [dense[round(((i / 299.0) ** 2) * 1199)] for i in range(300)]
+    plain = make_renderer(gs, scene, "plain", W, H, args)
+    a = [torch.zeros(3, H, W, device="cuda") for _ in range(4)]
+    rows = {}
+    for name, guide, d_max in (("static depth 10", "fixed", 10), ("static depth 3", "fixed", 3),
+                               ("linear", "linear", 10), ("exponential", "exp", 10), ("staged", "staged", 10)):
+        r = gs.Renderer(k=scene.k, d_max=d_max, guide=guide, max_width=W, max_height=H, reuse=True,
+                        precision="bf16")
+        r.load(scene)
+        ps, rate, depth = [], [], []
+        for L, R in traj:
+            r.frame(L, R, a[0], a[1])
+            st = r.stats()
+            plain.frame(L, R, a[2], a[3])
+            ps += [psnr_dev(torch, a[0], a[2]), psnr_dev(torch, a[1], a[3])]
+            rate.append(st["n_miss"] / max(1, st["n_visible"]))
+            depth.append(st["depth_used"])
+        total_s, _, _, _ = timed_pass(torch, r, traj, len(traj), 10, W, H, "guides:" + guide, stages=[])
+        rows[name] = {"fps": round(len(traj) / total_s, 1), "update_rate_mean": round(float(np.mean(rate)), 4),
+                      "depth_min": int(min(depth)), "depth_max": int(max(depth)),
+                      "psnr_db_min": round(float(np.min(ps)), 2), "psnr_db_mean": round(float(np.mean(ps)), 2)}
+        r.close()
+        print("guides: %s done" % name, file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "guides", "workload": "synthetic city 1M anchors, 300-frame fly-through rising "
+                      "2->300 m resampled at s = (i/299)^2 (accelerating), stereo 2048x1080, cache + BF16",
+                      "guides": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -557,6 +601,8 @@ def main():
         sys.exit(2)
     if args.mode == "serving":
         run_serving(args)
+    elif args.mode == "guides":
+        run_guides(args)
     else:
         run_frames(args)
 
