@@ -219,6 +219,10 @@ int gsc_reset_cache(gsc_ctx* ctx);
 #define GSC_DBG_PREPROC 6   /* float32 [n_gauss, 8]: mean2d.x, .y, conic a b c, alpha, depth,
                                tile count (as float) for eye */
 #define GSC_DBG_DEPTH 7     /* int32 [1]: current reuse depth */
+#define GSC_DBG_SORT_KEYS 8 /* uint32 [pairs of every image of the last raster batch]: the sorted
+                               tile keys (global tile ids, images in order), as the tile ranges read them */
+#define GSC_DBG_RAW_RANGES 9 /* int32 [global tiles, 2]: [start, end) of every tile in the sorted keys
+                               as the blend reads them ([0, 0) for a tile without pairs) */
 /* Copies at most cap elements (of the unit above: ints, floats or rows) to
  * host_dst and writes the full count to *n. */
 int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap, int64_t* n);
@@ -370,9 +374,11 @@ int64_t gsc_server_submit(gsc_server* s, int32_t viewer, const gsc_camera* left,
                           double t_arrival, float* out_left, float* out_right);
 /* Form one batch from the oldest queued request of each of up to 8 viewers
  * (oldest arrival first) and enqueue it: per viewer the derive stage on its
- * own cache, then one raster batch over all (viewer, eye) images ending in
- * one persistent blend launch.  Asynchronous; returns the number of
- * requests launched (0 when nothing is queued). */
+ * own cache, then one raster batch over all (viewer, eye) images, ending in
+ * one blend launch over every (viewer, eye, tile).  Asynchronous; returns
+ * the number of requests launched (0 when nothing is queued).  If enqueuing
+ * fails (GSC_E_HIP), the requests taken for the batch complete at once with
+ * status GSC_E_HIP. */
 int gsc_server_step(gsc_server* s);
 /* Completed requests since the last poll (non-blocking): writes up to cap
  * request ids, completion times (seconds on the host monotonic clock, taken

@@ -278,15 +278,16 @@ class CacheSim:
 
     Readings: a line holds one anchor's k derived Gaussians and the frame tau
     at which they were derived.  At frame t with depth d_t:
-      1. invalidate every line with t - tau > d_t (Alg. 1 'reach max cache
-         reuse depth');
+      1. invalidate every line with t - tau > d_t (Alg. 1: a line older than
+         the current reuse depth is no longer valid);
       2. a visible anchor hits iff it still holds a line (then 1 <= t - tau
          <= d_t) and reuse is on and the predictor does not mark it stale;
       3. misses (ascending anchor id) are re-derived with frame t's camera:
          an anchor that holds a line keeps its slot; the others take free
          slots in ascending slot order; if free slots are short, lines of
          anchors not visible now are evicted in ascending (last_used, anchor)
-         order ('outdated data ... evicted'); if still short -> capacity error;
+         order (Section 4: the scheduler picks stale lines to evict); if
+         still short -> capacity error;
       4. last_used <- t for every visible anchor's line, tau <- t for misses;
       5. linear guiding function (eq. 4, update rate r = |M|/|X|):
          d_{t+1} = clamp(round_half_up(D_max (1 - r)), 1, D_max), computed

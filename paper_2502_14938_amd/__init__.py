@@ -21,7 +21,8 @@ ERRORS = {-1: "GSC_E_INVALID_ARG", -2: "GSC_E_NOT_LOADED", -3: "GSC_E_OOM", -4: 
 PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT = 1, 2, 4, 8
 GUIDE = {"linear": 0, "fixed": 1, "exp": 2, "staged": 3}
-DBG = {"visible": 0, "misses": 1, "gauss": 2, "derived": 3, "pairs": 4, "ranges": 5, "preproc": 6, "depth": 7}
+DBG = {"visible": 0, "misses": 1, "gauss": 2, "derived": 3, "pairs": 4, "ranges": 5, "preproc": 6, "depth": 7,
+       "sort_keys": 8, "raw_ranges": 9}
 PRED_NPARAMS = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1  # 4673
 
 
@@ -268,7 +269,8 @@ class Renderer:
         shape, dt = {"visible": ((cnt,), np.int32), "misses": ((cnt,), np.int32), "gauss": ((cnt,), np.int32),
                      "derived": ((cnt, 13), np.float32), "pairs": ((cnt, 2), np.int32),
                      "ranges": ((cnt, 2), np.int32), "preproc": ((cnt, 8), np.float32),
-                     "depth": ((cnt,), np.int32)}[what]
+                     "depth": ((cnt,), np.int32), "sort_keys": ((cnt,), np.uint32),
+                     "raw_ranges": ((cnt, 2), np.int32)}[what]
         out = np.zeros(shape, dt)
         if cnt:
             self._check(L.gsc_debug_copy(self.h, code, eye, out.ctypes.data, cnt, C.byref(n)))

@@ -95,8 +95,6 @@ bool valid_camera(const gsc_camera& c) {
 }
 
 
-// Waits for the context's stream and, with two frames in flight, for the
-// blend stream.
 hipError_t sync_all(gsc_ctx* c) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess && c->blend_stream) e = hipStreamSynchronize(c->blend_stream);
@@ -721,14 +719,7 @@ int gsc_ssim(gsc_ctx* c, const float* a, const float* b, int32_t channels, int32
     if (channels < 1 || channels > 65535 || height < 11 || width < 11 || height > 65536 || width > 65536)
         return fail(c, GSC_E_INVALID_ARG, "gsc_ssim: images of 1..65535 channels, at least 11 x 11 pixels");
     HIP_OR_FAIL(c, sync_all(c));  // the images may come from a frame still in flight
-    SsimWindow win;
-    double g[11], sum = 0.0;
-    for (int i = 0; i < 11; ++i) {
-        const double x = i - 5.0;
-        g[i] = std::exp(-x * x / (2.0 * 1.5 * 1.5));
-        sum += g[i];
-    }
-    for (int i = 0; i < 11; ++i) win.w[i] = g[i] / sum;
+    const SsimWindow win = ssim_window();
     const int64_t nb = ssim_blocks(channels, height, width);
     double* buf = nullptr;  // [0]: total, [1..nb]: per-block sums
     HIP_OR_FAIL(c, hipMalloc((void**)&buf, (size_t)(nb + 1) * sizeof(double)));
@@ -956,6 +947,29 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
         case GSC_DBG_DEPTH: {
             count = 1;
             if (cap >= 1) ((int32_t*)dst)[0] = k.depth;
+            break;
+        }
+        case GSC_DBG_SORT_KEYS: {
+            if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
+            int32_t ns = 0;
+            HIP_OR_FAIL(c, hipMemcpy(&ns, R.n_sort, sizeof(int32_t), hipMemcpyDeviceToHost));
+            count = ns;
+            int64_t m = count < cap ? count : cap;
+            if (m <= 0) break;
+            if (R.pkey64[R.sorted_buf] && (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT)) {
+                std::vector<uint64_t> k64(m);
+                HIP_OR_FAIL(c, hipMemcpy(k64.data(), R.pkey64[R.sorted_buf], m * 8, hipMemcpyDeviceToHost));
+                for (int64_t i = 0; i < m; ++i) ((uint32_t*)dst)[i] = (uint32_t)(k64[i] >> 32);
+            } else {
+                HIP_OR_FAIL(c, hipMemcpy(dst, R.pkey[R.sorted_buf], m * 4, hipMemcpyDeviceToHost));
+            }
+            break;
+        }
+        case GSC_DBG_RAW_RANGES: {
+            if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
+            count = c->last_tab.total_tiles;
+            int64_t m = count < cap ? count : cap;
+            if (m > 0) HIP_OR_FAIL(c, hipMemcpy(dst, R.ranges, 2 * m * 4, hipMemcpyDeviceToHost));
             break;
         }
         default:

@@ -251,6 +251,7 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk = nullptr
 struct SsimWindow {
     double w[11];
 };
+SsimWindow ssim_window();
 int64_t ssim_blocks(int C, int H, int W);
 hipError_t ssim_launch(const float* a, const float* b, int C, int H, int W, const SsimWindow& win, double* partial,
                        double* total, hipStream_t st);

@@ -123,6 +123,9 @@ struct gsc_ctx {
 };
 
 namespace gsc {
+// Waits for the context's stream and, with two frames in flight, for the
+// blend stream.
+hipError_t sync_all(gsc_ctx* c);
 hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles);
 void free_explicit(gsc_ctx* c);
 void free_labels(gsc_ctx* c);

@@ -14,7 +14,10 @@
 //                 vector FMA runs at the non-packed FP32 rate); the block's
 //                 sum to its own slot
 //   k_ssim_total  one block adds the slots in a fixed order (deterministic)
+#include <cmath>
+
 #include "gsc_common.h"
+#include "gsc_ctx.h"
 
 namespace gsc {
 
@@ -99,6 +102,18 @@ __global__ __launch_bounds__(256) void k_ssim_total(const double* __restrict__ p
 }
 
 }  // namespace
+
+SsimWindow ssim_window() {
+    SsimWindow win;
+    double g[kWin], sum = 0.0;
+    for (int i = 0; i < kWin; ++i) {
+        const double x = i - 0.5 * (kWin - 1);
+        g[i] = std::exp(-x * x / (2.0 * 1.5 * 1.5));
+        sum += g[i];
+    }
+    for (int i = 0; i < kWin; ++i) win.w[i] = g[i] / sum;
+    return win;
+}
 
 int64_t ssim_blocks(int C, int H, int W) {
     const int64_t tx = (W - kWin + 1 + kTileS - 1) / kTileS, ty = (H - kWin + 1 + kTileS - 1) / kTileS;

@@ -9,9 +9,9 @@
 //   step     the oldest queued request of up to kMaxSeg/2 viewers (oldest
 //            first) form one batch: each viewer's derive stage (selection,
 //            cache schedule, derivation of misses, compose) on its own cache,
-//            then ONE raster batch over all (viewer, eye) images ending in
-//            one persistent blend launch; the host returns at once and the
-//            next step can be queued behind this one
+//            then ONE raster batch over all (viewer, eye) images, ending in
+//            one blend launch over every (viewer, eye, tile); the host
+//            returns at once and the next step can be queued behind this one
 //   poll     completions, timestamped on the host monotonic clock by a host
 //            function the stream runs when the batch's kernels are done
 #include <algorithm>
@@ -112,6 +112,20 @@ struct Batch {
 int sfail(gsc_server* s, int code, const std::string& msg) {
     if (s) s->err = msg;
     return code;
+}
+
+// A batch that failed to enqueue: the requests already taken off their
+// viewers' queues complete at once with GSC_E_HIP (so a caller polling for
+// them is answered), and the report goes back to the free list.
+int abort_batch(gsc_server* s, Batch* b, const std::string& msg) {
+    const double t = now_monotonic();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (int64_t id : b->ids) s->done.push_back({id, t, GSC_E_HIP});
+        s->free_reports.push_back(b->rep);
+    }
+    delete b;
+    return sfail(s, GSC_E_HIP, msg);
 }
 
 void on_batch_done(void* p) {
@@ -405,11 +419,13 @@ int gsc_server_step(gsc_server* s) {
         a.pred_w = c->pred_w;
         a.pred_wbf = c->pred_wbf;
         a.collect = 0;
+        b->ids.push_back(r.id);
+        b->viewer_of.push_back(i);
+        b->viewer_id.push_back(pick[i]);
+        b->t_arrival.push_back(r.t_arrival);
         hipError_t e = derive_frame(a, s->st);
-        if (e != hipSuccess) {
-            delete b;
-            return sfail(s, GSC_E_HIP, std::string("gsc_server_step: derive: ") + hipGetErrorString(e));
-        }
+        if (e != hipSuccess)
+            return abort_batch(s, b, std::string("gsc_server_step: derive: ") + hipGetErrorString(e));
         v.v.t += 1;
         for (int eye = 0; eye < 2; ++eye) {
             Seg& sg = tab.s[tab.n++];
@@ -424,23 +440,14 @@ int gsc_server_step(gsc_server* s) {
             sg.out_T = nullptr;
             sg.out_nc = nullptr;
         }
-        b->ids.push_back(r.id);
-        b->viewer_of.push_back(i);
-        b->viewer_id.push_back(pick[i]);
-        b->t_arrival.push_back(r.t_arrival);
-        if (hipMemcpyAsync(&rep->vc[i], v.v.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s->st) != hipSuccess) {
-            delete b;
-            return sfail(s, GSC_E_HIP, "gsc_server_step: counter copy");
-        }
+        if (hipMemcpyAsync(&rep->vc[i], v.v.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s->st) != hipSuccess)
+            return abort_batch(s, b, "gsc_server_step: counter copy");
     }
     tab.total_tiles = tiles;
     hipError_t e = raster_batch(tab, s->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, false, s->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&rep->rc, s->raster.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost, s->st);
-    if (e != hipSuccess) {
-        delete b;
-        return sfail(s, GSC_E_HIP, std::string("gsc_server_step: raster: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return abort_batch(s, b, std::string("gsc_server_step: raster: ") + hipGetErrorString(e));
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->in_flight += 1;
@@ -448,10 +455,11 @@ int gsc_server_step(gsc_server* s) {
     const int launched = (int)b->ids.size();
     e = hipLaunchHostFunc(s->st, on_batch_done, b);
     if (e != hipSuccess) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->in_flight -= 1;
-        delete b;
-        return sfail(s, GSC_E_HIP, "gsc_server_step: completion callback");
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->in_flight -= 1;
+        }
+        return abort_batch(s, b, "gsc_server_step: completion callback");
     }
     return launched;
 }

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from parity import assert_image, assert_pairs
+from parity import assert_image, assert_pairs, assert_ranges_from_keys
 
 pytestmark = pytest.mark.gpu
 
@@ -92,3 +92,20 @@ def test_large_footprints_match_oracle(gs, seed):
     assert ref["n_pairs"] > 20 * 400 * 0.2
     assert_image(img, ref)
     assert_pairs(pairs, ref, ref["pre"]["depth"])
+
+
+def test_many_tiles_two_pass_sort_and_ranges(gs):
+    # 640x360: 40 x 23 = 920 tiles, so the tile sort takes two radix passes
+    # (8 + 2 bits); the pair count is not a multiple of 1024, so the tile
+    # ranges see both their full 1024-key steps and the ragged tail
+    mu, cov, rgb, al = synth.random_gaussians(20000, seed=6, box=6.0, zc=9.0)
+    cam = synth.look_camera((0.1, -0.2, 0), (0.05, 0.02, 1), (0, -1, 0), 640, 360, math.radians(70))
+    img, T, nc, pairs, r = run(gs, mu, cov, rgb, al, cam)
+    keys = r.debug("sort_keys")
+    ranges = r.debug("raw_ranges")
+    ref = oracle.render_gaussians(mu, cov, rgb, al, cam, debug=True)
+    assert len(keys) == len(pairs) and len(pairs) % 1024 != 0 and len(pairs) > 100000, len(pairs)
+    assert_ranges_from_keys(keys, ranges)
+    assert_pairs(pairs, ref, ref["pre"]["depth"])
+    assert_image(img, ref)
+    r.close()
