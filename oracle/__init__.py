@@ -51,6 +51,7 @@ def _load():
         lib = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         lib.orc_threads.restype = C.c_int
+        lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_unified_camera.argtypes = [P, P, P]
         lib.orc_select.argtypes = [C.c_int64, P, P, P, P, C.c_double, P, P]
         lib.orc_select.restype = C.c_int64
@@ -100,6 +101,11 @@ def from_orc(c: OrcCamera) -> dict:
 def threads() -> int:
     """Host threads the oracle's parallel loops use."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n host threads from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def round_bf16(x: float) -> float:

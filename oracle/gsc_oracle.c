@@ -532,3 +532,13 @@ int orc_threads(void) {
     return 1;
 #endif
 }
+
+/* Sets the thread count of the parallel loops above (for timing the oracle
+   on a given number of host cores); n <= 0 leaves it unchanged. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
