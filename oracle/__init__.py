@@ -53,17 +53,17 @@ def _load():
         lib.orc_threads.restype = C.c_int
         lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_unified_camera.argtypes = [P, P, P]
-        lib.orc_select.argtypes = [C.c_int64, P, P, P, P, C.c_double, P, P]
+        lib.orc_select.argtypes = [C.c_int64, P, P, P, P, C.c_double, C.c_int, P, P, P]
         lib.orc_select.restype = C.c_int64
         lib.orc_derive.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int, P, P, C.c_int,
-                                   P, P, P, P, P]
+                                   C.c_double, P, P, P, P, P]
         lib.orc_preprocess.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, P, P]
         lib.orc_rect_min_q.argtypes = [C.c_double] * 9
         lib.orc_rect_min_q.restype = C.c_double
         lib.orc_tile_pairs.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int64, P, P, P]
         lib.orc_tile_pairs.restype = C.c_int64
         lib.orc_sort_pairs.argtypes = [C.c_int64, P, P, P, P]
-        lib.orc_blend.argtypes = [C.c_int, C.c_int] + [P] * 13
+        lib.orc_blend.argtypes = [C.c_int, C.c_int] + [P] * 13 + [C.c_double]
         lib.orc_round_bf16.argtypes = [C.c_double]
         lib.orc_round_bf16.restype = C.c_double
         lib.orc_round_e4m3.argtypes = [C.c_double]
@@ -126,14 +126,19 @@ def unified_camera(left: dict, right: dict) -> dict:
     return from_orc(u)
 
 
-def select(scene, ucam: dict):
-    """Anchor filtering (LOD + frustum).  Returns (ids ascending int32, band uint8[n])."""
+def select(scene, ucam: dict, fade: bool = False, weights: bool = False):
+    """Anchor filtering (LOD + frustum).  Returns (ids ascending int32, band
+    uint8[n]), and with weights=True also the per-anchor opacity weight
+    float64[n] of the fractional level transition (fade=True; all 1 without
+    it)."""
     lib = _load()
     pos = _c(scene.pos, np.float32); lev = _c(scene.level, np.uint8); rad = _c(scene.radius, np.float32)
     out = np.empty(scene.n, np.int32); band = np.empty(scene.n, np.uint8)
+    w = np.empty(scene.n, np.float64)
     u = to_orc(ucam)
-    m = lib.orc_select(scene.n, _p(pos), _p(lev), _p(rad), C.byref(u), float(scene.d_ref), _p(out), _p(band))
-    return out[:m].copy(), band
+    m = lib.orc_select(scene.n, _p(pos), _p(lev), _p(rad), C.byref(u), float(scene.d_ref), int(bool(fade)),
+                       _p(out), _p(band), _p(w))
+    return (out[:m].copy(), band, w) if weights else (out[:m].copy(), band)
 
 
 def _mlp_ptrs(scene):
@@ -149,7 +154,9 @@ def _mlp_ptrs(scene):
 
 def derive(scene, ids, pu, prec: int = 0) -> dict:
     """Section 3.1 eq. 3 (AnchorDecoder) for the anchors `ids` seen from p_u.
-    prec: 0 exact FP64, 1 bf16 emulation, 2 e4m3fn-weight emulation.
+    prec: 0 exact FP64, 1 bf16 emulation, 2 e4m3fn-weight emulation.  A scene
+    whose layer-1 weights have F + 4 columns takes the anchor-to-p_u distance
+    over scene.dist_unit as its last input.
     Returns arrays of m*k rows: mu, cov (xx xy xz yy yz zz), rgb, alpha, alpha_pre."""
     lib = _load()
     ids = _c(ids, np.int32)
@@ -160,8 +167,12 @@ def derive(scene, ids, pu, prec: int = 0) -> dict:
     pu = _c(pu, np.float64)
     pos = _c(scene.pos, np.float32); feat = _c(scene.feat, np.float32)
     scl = _c(scene.scale, np.float32); off = _c(scene.offsets, np.float32)
+    ni = scene.mlp["alpha"][0].shape[1]
+    assert ni in (scene.F + 3, scene.F + 4)
+    dist_unit = float(getattr(scene, "dist_unit", 0.0)) if ni == scene.F + 4 else 0.0
+    assert ni == scene.F + 3 or dist_unit > 0.0, "a distance input needs scene.dist_unit > 0"
     lib.orc_derive(m, _p(ids), _p(pos), _p(feat), _p(scl), _p(off), scene.F, scene.H, k, arr, _p(pu),
-                   int(prec), _p(out["mu"]), _p(out["cov"]), _p(out["rgb"]), _p(out["alpha"]),
+                   int(prec), dist_unit, _p(out["mu"]), _p(out["cov"]), _p(out["rgb"]), _p(out["alpha"]),
                    _p(out["alpha_pre"]))
     return out
 
@@ -223,7 +234,7 @@ def tile_ranges(sorted_tile, n_tiles: int):
     return st, en
 
 
-def blend(W, H, starts, ends, sorted_g, pre, alpha, rgb):
+def blend(W, H, starts, ends, sorted_g, pre, alpha, rgb, alpha_band: float = 1e-7):
     """Front-to-back alpha compositing per pixel (Section 3.1).  Returns the
     image, final transmittance, contributors, ambiguity band and the number
     of Gaussians each pixel visited (up to and including the one ending it)."""
@@ -234,11 +245,12 @@ def blend(W, H, starts, ends, sorted_g, pre, alpha, rgb):
     ne = np.zeros((H, W), np.int32)
     sg = _c(sorted_g, np.int32); alpha = _c(alpha, np.float64); rgb = _c(rgb, np.float64)
     lib.orc_blend(W, H, _p(_c(starts, np.int64)), _p(_c(ends, np.int64)), _p(sg), _p(pre["mean2d"]),
-                  _p(pre["conic"]), _p(alpha), _p(rgb), _p(pre["depth"]), _p(img), _p(T), _p(nc), _p(band), _p(ne))
+                  _p(pre["conic"]), _p(alpha), _p(rgb), _p(pre["depth"]), _p(img), _p(T), _p(nc), _p(band), _p(ne),
+                  float(alpha_band))
     return img, T, nc, band, ne
 
 
-def render_gaussians(mu, cov, rgb, alpha, cam: dict, debug: bool = False):
+def render_gaussians(mu, cov, rgb, alpha, cam: dict, debug: bool = False, alpha_band: float = 1e-7):
     """Rasterise explicit Gaussians for one camera: preprocess -> tile lists ->
     sort -> ranges -> blend.  Returns a dict with image [3,H,W], T, n_contrib,
     pixel band, and (if debug) the intermediate lists."""
@@ -252,7 +264,7 @@ def render_gaussians(mu, cov, rgb, alpha, cam: dict, debug: bool = False):
     st_tile, st_g = lt[order], lg[order]
     ntiles = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
     s, e = tile_ranges(st_tile, ntiles)
-    img, T, nc, band, ne = blend(W, H, s, e, st_g, pre, alpha, np.asarray(rgb, np.float64))
+    img, T, nc, band, ne = blend(W, H, s, e, st_g, pre, alpha, np.asarray(rgb, np.float64), alpha_band)
     out = {"image": img, "T": T, "n_contrib": nc, "band": band, "n_pairs": int(listed.sum()), "n_eval": ne}
     if debug:
         out.update(pre=pre, pairs_tile=tile, pairs_g=g, pairs_flags=fl, sorted_tile=st_tile,
@@ -370,14 +382,22 @@ class CacheSim:
 
 # ----------------------------------------------------------- whole frame
 
+# Pixel alpha band when opacities carry the fractional-LOD weight: the other
+# side computes the weight in float32 (absolute error ~2.4e-7 over the
+# octave), so a pixel alpha within 1e-6 of 1/255 is marginal.
+FADE_ALPHA_BAND = 1e-6
+
+
 def render_frame(scene, left: dict, right: dict, cache: CacheSim | None = None, cache_lines: dict | None = None,
-                 prec: int = 0, deredundancy: bool = True, stale=None, debug: bool = False):
+                 prec: int = 0, deredundancy: bool = True, stale=None, debug: bool = False, lod_fade: bool = False):
     """One stereo frame of the cache-centric pipeline (Alg. 1 with eqs. 5-6):
     unified camera -> selection -> cache schedule -> derive misses -> compose
     -> per-eye rasterisation.  `cache_lines` maps anchor id -> derived rows
     (k rows each) and persists across frames together with `cache`.
     With deredundancy=False each eye selects and derives with its own camera
-    (no cache)."""
+    (no cache).  lod_fade: the fractional level transition (select); each
+    kept anchor's Gaussians are rasterised with opacity alpha * w_a, while
+    the render buffer's mask and the cache keep the derived alpha."""
     out = {}
     if not deredundancy:
         imgs = []
@@ -388,7 +408,7 @@ def render_frame(scene, left: dict, right: dict, cache: CacheSim | None = None, 
             imgs.append(render_gaussians(der["mu"][G], der["cov"][G], der["rgb"][G], der["alpha"][G], eye))
         return {"left": imgs[0], "right": imgs[1]}
     U = unified_camera(left, right)
-    ids, sel_band = select(scene, U)
+    ids, sel_band, lod_w = select(scene, U, fade=lod_fade, weights=True)
     k = scene.k
     if cache is None:
         der = derive(scene, ids, U["pos"], prec)
@@ -403,10 +423,14 @@ def render_frame(scene, left: dict, right: dict, cache: CacheSim | None = None, 
                np.zeros((0,) + fresh[key].shape[1:]) for key in fresh}
     G = compose(len(ids), k, der["alpha"])
     mu, cov, rgb, al = der["mu"][G], der["cov"][G], der["rgb"][G], der["alpha"][G]
-    out["left"] = render_gaussians(mu, cov, rgb, al, left, debug)
-    out["right"] = render_gaussians(mu, cov, rgb, al, right, debug)
+    ab = 1e-7
+    if lod_fade:
+        al = al * lod_w[np.asarray(ids, np.int64)[G // k]]
+        ab = FADE_ALPHA_BAND
+    out["left"] = render_gaussians(mu, cov, rgb, al, left, debug, alpha_band=ab)
+    out["right"] = render_gaussians(mu, cov, rgb, al, right, debug, alpha_band=ab)
     out.update(unified=U, visible=ids, select_band=sel_band, G=G, cache=info,
-               mask_band=np.abs(der["alpha_pre"]) < 1e-6)
+               mask_band=np.abs(der["alpha_pre"]) < 1e-6, lod_w=lod_w)
     if debug:
         out["derived"] = der
     return out

@@ -115,13 +115,20 @@ void orc_unified_camera(const orc_camera* l, const orc_camera* r, orc_camera* u)
 
 /* ---------------------------------------------------- anchor selection */
 /* Keep anchor a iff
- *   (LOD)     level_a == 0  or  |x_a - p_u| <= d_ref * 2^-level_a, and
+ *   (LOD)     level_a == 0  or  |x_a - p_u| <= d_l = d_ref * 2^-level_a, and
  *   (frustum) its bounding sphere (x_a, rho_a) is not wholly outside any of
  *             the unified camera's four side planes or its near plane.
+ * With fade (the fractional level transition, a reading of the cited
+ * Octree-GS distance-driven LOD): a level-l anchor (l > 0) is kept iff
+ * |x_a - p_u| < 2 d_l, with the weight w_a = clamp(2 - |x_a - p_u| / d_l,
+ * 0, 1) on the opacities of its Gaussians: 1 up to d_l, falling linearly to
+ * 0 at 2 d_l, so a level comes in over the octave of distance before it is
+ * fully present instead of appearing at once.  Level 0: w = 1.  w_out (may
+ * be NULL) receives w for every anchor (1 without fade).
  * Output: the kept ids in ascending order; band[a] = 1 when either test's
  * margin is below 1e-6 relative. Returns the count. */
 int64_t orc_select(int64_t n, const float* pos, const uint8_t* level, const float* radius,
-                   const orc_camera* u, double d_ref, int32_t* out_ids, uint8_t* band) {
+                   const orc_camera* u, double d_ref, int fade, int32_t* out_ids, uint8_t* band, double* w_out) {
     double tx = tan(0.5 * u->fovx), ty = tan(0.5 * u->fovy);
     double nx = sqrt(1.0 + tx * tx), ny = sqrt(1.0 + ty * ty);
     uint8_t* keep = (uint8_t*)malloc(n > 0 ? (size_t)n : 1);
@@ -132,11 +139,15 @@ int64_t orc_select(int64_t n, const float* pos, const uint8_t* level, const floa
         double dist = norm3(v);
         double rho = radius[a];
         int lod_ok = 1, b = 0;
+        double w = 1.0;
         if (level[a] != 0) {
-            double lim = d_ref * ldexp(1.0, -(int)level[a]);
-            lod_ok = dist <= lim;
+            double dl = d_ref * ldexp(1.0, -(int)level[a]);
+            double lim = fade ? 2.0 * dl : dl;
+            lod_ok = fade ? dist < lim : dist <= lim;
             if (fabs(dist - lim) < 1e-6 * (lim + dist)) b = 1;
+            if (fade) w = fmin(fmax(2.0 - dist / dl, 0.0), 1.0);
         }
+        if (w_out) w_out[a] = w;
         double t[3];
         to_camera(u, x, t);
         double s[5];
@@ -165,6 +176,8 @@ int64_t orc_select(int64_t n, const float* pos, const uint8_t* level, const floa
 /* Section 3.1, eq. 3 with the documented readings: for anchor a seen from the
  * unified camera centre p_u,
  *   d = (x_a - p_u) / |x_a - p_u|,  z = [f_a ; d]                 (F + 3)
+ *   or, with a distance input (dist_unit > 0, the cited methods' optional
+ *   camera-distance feature), z = [f_a ; d ; |x_a - p_u| / dist_unit] (F + 4)
  *   per head (alpha c=1, color c=3, cov c=7):
  *       h = ReLU(W1 z + b1) (H),   o = W2 h + b2 (c k), output index j*c + ch
  *   alpha_j = tanh(o_alpha[j])
@@ -196,14 +209,16 @@ static void quantise_weights(const float* W, int rows, int cols, int prec, doubl
 
 void orc_derive(int64_t m, const int32_t* ids, const float* pos, const float* feat, const float* scale,
                 const float* offsets, int F, int H, int k, const float* const* mlp, const double* pu,
-                int prec, double* mu, double* cov, double* rgb, double* alpha, double* alpha_pre) {
+                int prec, double dist_unit, double* mu, double* cov, double* rgb, double* alpha,
+                double* alpha_pre) {
     const int C[3] = {1, 3, 7};
+    const int NI = dist_unit > 0.0 ? F + 4 : F + 3;  /* inputs per anchor */
     double* W1[3];
     double* W2[3];
     for (int h = 0; h < 3; ++h) {
-        W1[h] = (double*)malloc(sizeof(double) * H * (F + 3));
+        W1[h] = (double*)malloc(sizeof(double) * H * NI);
         W2[h] = (double*)malloc(sizeof(double) * C[h] * k * H);
-        quantise_weights(mlp[4 * h + 0], H, F + 3, prec, W1[h]);
+        quantise_weights(mlp[4 * h + 0], H, NI, prec, W1[h]);
         quantise_weights(mlp[4 * h + 2], C[h] * k, H, prec, W2[h]);
     }
 #pragma omp parallel for schedule(dynamic, 64)
@@ -212,19 +227,20 @@ void orc_derive(int64_t m, const int32_t* ids, const float* pos, const float* fe
         double x[3] = {pos[3 * a], pos[3 * a + 1], pos[3 * a + 2]};
         double v[3] = {x[0] - pu[0], x[1] - pu[1], x[2] - pu[2]};
         double nv = norm3(v);
-        double* z = (double*)malloc(sizeof(double) * (F + 3));
+        double* z = (double*)malloc(sizeof(double) * NI);
         double* hid = (double*)malloc(sizeof(double) * H);
         double* o[3];
         for (int f = 0; f < F; ++f) z[f] = feat[a * F + f];
         for (int c = 0; c < 3; ++c) z[F + c] = v[c] / nv;
-        if (prec) for (int f = 0; f < F + 3; ++f) z[f] = orc_round_bf16(z[f]);
+        if (NI == F + 4) z[F + 3] = nv / dist_unit;
+        if (prec) for (int f = 0; f < NI; ++f) z[f] = orc_round_bf16(z[f]);
         for (int h = 0; h < 3; ++h) {
             const float* b1 = mlp[4 * h + 1];
             const float* b2 = mlp[4 * h + 3];
             o[h] = (double*)malloc(sizeof(double) * C[h] * k);
             for (int r = 0; r < H; ++r) {
                 double acc = 0.0;
-                for (int c = 0; c < F + 3; ++c) acc += W1[h][r * (F + 3) + c] * z[c];
+                for (int c = 0; c < NI; ++c) acc += W1[h][r * NI + c] * z[c];
                 acc += b1[r];
                 hid[r] = acc > 0.0 ? acc : 0.0;
                 if (prec) hid[r] = orc_round_bf16(hid[r]);
@@ -476,13 +492,15 @@ void orc_sort_pairs(int64_t n, const int32_t* tile, const int32_t* g, const doub
  *   C += rgb_g alpha T;  T *= 1 - alpha.
  * Outputs planar RGB [3,H,W] (background 0), final T [H,W], and the number
  * of Gaussians added per pixel.  pix_band[p] = 1 when any decision at that
- * pixel is marginal (alpha vs 1/255 within 1e-7, the stop test within 1e-9,
+ * pixel is marginal (alpha vs 1/255 within alpha_band (1e-7; wider where the
+ * opacities carry a weight computed in float32 on the other side), the stop
+ * test within 1e-9,
  * or two consecutive added Gaussians whose depths are within 4 float32 ulps
  * so their order is not fixed by float32 keys). */
 void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end, const int32_t* sorted_g,
                const double* mean2d, const double* conic, const double* alpha, const double* rgb,
                const double* depth, double* out_rgb, double* out_T, int32_t* n_contrib, uint8_t* pix_band,
-               int32_t* n_eval) {
+               int32_t* n_eval, double alpha_band) {
     int ntx = (W + ORC_TILE - 1) / ORC_TILE;
     int64_t npx = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -502,7 +520,7 @@ void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end,
                 double q = cn[0] * dx * dx + 2.0 * cn[1] * dx * dy + cn[2] * dy * dy;
                 double a = alpha[g] * exp(-0.5 * q);
                 if (a > 0.99) a = 0.99;
-                if (fabs(a - 1.0 / 255.0) < 1e-7) bnd = 1;
+                if (fabs(a - 1.0 / 255.0) < alpha_band) bnd = 1;
                 if (a < 1.0 / 255.0) continue;
                 double tn = T * (1.0 - a);
                 if (fabs(tn - 1e-4) < 1e-9) bnd = 1;

@@ -46,6 +46,7 @@ class Scene:
     d_ref: float = 1.0e30
     l_max: int = 0
     meta: dict = field(default_factory=dict)
+    dist_unit: float = 0.0   # metres per unit of the MLP's distance input (layer 1 with F + 4 columns)
 
     @property
     def n(self) -> int:
@@ -67,20 +68,22 @@ class Scene:
         idx = np.asarray(idx)
         return Scene(self.pos[idx].copy(), self.level[idx].copy(), self.radius[idx].copy(),
                      self.feat[idx].copy(), self.scale[idx].copy(), self.offsets[idx].copy(),
-                     self.mlp, self.d_ref, self.l_max, dict(self.meta))
+                     self.mlp, self.d_ref, self.l_max, dict(self.meta), self.dist_unit)
 
 
-def glorot_mlp(F: int, H: int, k: int, seed: int = 0, quat_w_bias: float = 0.0) -> dict:
+def glorot_mlp(F: int, H: int, k: int, seed: int = 0, quat_w_bias: float = 0.0, dist_input: bool = False) -> dict:
     """Two-layer MLPs (F+3 -> H -> c*k) per head, Glorot-uniform weights, zero
     biases, drawn from PCG64(seed) in the order alpha.W1, alpha.W2, color.W1,
     color.W2, cov.W1, cov.W2.  quat_w_bias sets the bias of every quaternion-w
-    output of the cov head (output 7j+3)."""
+    output of the cov head (output 7j+3).  dist_input: layer 1 takes one more
+    input (F+4 columns, the camera-distance feature)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     mlp = {}
+    ni = F + 4 if dist_input else F + 3
     for name, c in HEADS:
-        fan1 = (F + 3, H)
+        fan1 = (ni, H)
         lim1 = math.sqrt(6.0 / (fan1[0] + fan1[1]))
-        W1 = rng.uniform(-lim1, lim1, size=(H, F + 3)).astype(np.float32)
+        W1 = rng.uniform(-lim1, lim1, size=(H, ni)).astype(np.float32)
         lim2 = math.sqrt(6.0 / (H + c * k))
         W2 = rng.uniform(-lim2, lim2, size=(c * k, H)).astype(np.float32)
         b1 = np.zeros(H, np.float32)
@@ -111,12 +114,33 @@ def tiny_scene(n: int = 2000, F: int = 32, H: int = 32, k: int = 10, seed: int =
                  d_ref=1.0e30, l_max=0, meta={"name": "tiny", "seed": seed})
 
 
+def tiny_lod_scene(n: int = 2000, F: int = 32, H: int = 32, k: int = 10, seed: int = 0, l_max: int = 3,
+                   d_ref: float = 40.0, dist_input: bool = False, dist_unit: float = 10.0) -> Scene:
+    """The tiny scene with octree levels 0..l_max (N_l proportional to 2^l,
+    drawn at random) and a LOD reference distance at the tiny camera's range
+    (anchors 10-20 m from the tiny pair; level l is kept within d_ref 2^-l:
+    40, 20, 10, 5 m), offset and base scales halving per level; optionally
+    the MLPs' distance input (distance / dist_unit)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = rng.uniform(-5.0, 5.0, size=(n, 3)).astype(np.float32)
+    feat = rng.standard_normal(size=(n, F)).astype(np.float32)
+    offsets = rng.uniform(-1.0, 1.0, size=(n, k, 3)).astype(np.float32)
+    w = 2.0 ** np.arange(l_max + 1)
+    level = rng.choice(l_max + 1, size=n, p=w / w.sum()).astype(np.uint8)
+    base = np.array([0.5, 0.5, 0.5, 0.25, 0.25, 0.25], np.float32)
+    scale = (base[None, :] * (0.5 ** level.astype(np.float32))[:, None]).astype(np.float32)
+    mlp = glorot_mlp(F, H, k, seed=seed, dist_input=dist_input)
+    return Scene(pos, level, _radius(scale, offsets), feat, scale, offsets, mlp, d_ref=d_ref, l_max=l_max,
+                 meta={"name": "tiny_lod", "seed": seed}, dist_unit=dist_unit if dist_input else 0.0)
+
+
 def city_scene(n: int = 1_000_000, F: int = 32, H: int = 32, k: int = 10, seed: int = 0,
                n_buildings: int = 3000, half_extent: float = 1000.0, l_max: int = 10,
-               d_ref: float = 2.0 ** 19) -> Scene:
+               d_ref: float = 2.0 ** 19, dist_input: bool = False) -> Scene:
     """Synthetic city: z-up ground plane over [-E, E]^2 plus random box
     buildings; anchors area-weighted over ground, roofs and walls, split into
-    octree levels 0..l_max with N_l proportional to 2^l."""
+    octree levels 0..l_max with N_l proportional to 2^l.  dist_input: the
+    MLPs take the camera distance in units of the half extent E."""
     rng = np.random.Generator(np.random.PCG64(seed))
     E = half_extent
     cx = rng.uniform(-E, E, n_buildings)
@@ -184,11 +208,12 @@ def city_scene(n: int = 1_000_000, F: int = 32, H: int = 32, k: int = 10, seed: 
     feat = rng.standard_normal(size=(n, F), dtype=np.float32)
     offsets = rng.uniform(-1.0, 1.0, size=(n, k, 3)).astype(np.float32)
     scale = scale.astype(np.float32)
-    mlp = glorot_mlp(F, H, k, seed=seed, quat_w_bias=1.0)
+    mlp = glorot_mlp(F, H, k, seed=seed, quat_w_bias=1.0, dist_input=dist_input)
     return Scene(pos.astype(np.float32), level, _radius(scale, offsets), feat, scale, offsets, mlp,
                  d_ref=d_ref, l_max=l_max,
                  meta={"name": "city", "seed": seed, "n_buildings": n_buildings,
-                       "surface_area_m2": a_total, "level_counts": counts.tolist()})
+                       "surface_area_m2": a_total, "level_counts": counts.tolist()},
+                 dist_unit=half_extent if dist_input else 0.0)
 
 
 # ----------------------------------------------------------------------------------------
