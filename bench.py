@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", default="frames", choices=["frames", "serving", "guides", "precision", "reuse"])
+    ap.add_argument("--mode", default="frames", choices=["frames", "serving", "guides", "precision", "reuse", "lod"])
     ap.add_argument("--form", default="cached-bf16-learned", choices=sorted(FORMS))
     ap.add_argument("--threshold", type=float, default=0.9, help="learned reuse: re-derive when p(stale) > this")
     ap.add_argument("--d-max", type=int, default=10)
@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--queue-pose-m", type=float, default=0.0, help="serving queue policy: pose gate, metres (0: off)")
     ap.add_argument("--queue-pose-deg", type=float, default=0.0, help="serving queue policy: pose gate, degrees (0: off)")
     ap.add_argument("--queue-ordered", action="store_true", help="serving queue policy: discard frames delivered late")
+    ap.add_argument("--overlap", action="store_true",
+                    help="serving: two batches in flight (a batch's blend overlaps the next batch's earlier stages)")
     return ap.parse_args()
 
 
@@ -408,7 +410,7 @@ def run_frames(args):
     total_s, lat, stages, frames = timed_pass(torch, r, traj, args.steps, args.warmup, W, H, "timed:" + form,
                                               stages=dom_stages, in_flight=args.frames_in_flight)
     fps = args.steps / total_s
-    timed_frames = ("frames %d-%d of the %d-frame fly-through" % (first, args.steps - 1, n_traj)
+    timed_frames = ("frames 0-%d of the %d-frame fly-through" % (args.steps - 1, n_traj)
                     if args.steps <= n_traj else
                     "the %d-frame fly-through repeated (%d frames)" % (n_traj, args.steps))
     full = None
@@ -563,6 +565,8 @@ def run_serving(args):
     form = args.form if not FORMS[args.form].get("predictor") else "cached-bf16"
     base = make_renderer(gs, scene, form, 2560, 1440, args)
     srv = gs.Server(base, int(args.budget_gb * (1 << 30)))
+    if args.overlap:
+        srv.overlap(True)
     srv.policy(pose_m=args.queue_pose_m, pose_rad=math.radians(args.queue_pose_deg),
                timeout_s=args.queue_timeout_ms * 1e-3, ordered=args.queue_ordered)
     # warm the kernels (one frame of the first viewer, separate server)
@@ -656,7 +660,7 @@ def run_serving(args):
                                   "{1280x720, 2048x1080, 2560x1440}, session starts Poisson (mean gap 0.25 s), frame "
                                   "requests Poisson at %.0f Hz per viewer, %d frames each"
                                   % (nv, args.rate, args.serving_frames),
-                      "form": form, "budget_gb": args.budget_gb},
+                      "form": form, "budget_gb": args.budget_gb, "batches_in_flight": 2 if args.overlap else 1},
            "latency_ms": {"p50": round(float(np.percentile(all_lat, 50)), 3),
                           "p99": round(float(np.percentile(all_lat, 99)), 3),
                           "max": round(float(all_lat.max()), 3)},
@@ -823,11 +827,13 @@ def run_reuse(args):
 # --------------------------------------------------------------------------- guide ablation
 
 def run_guides(args):
-    """Guiding functions of eq. 4 against a static depth on an accelerating
-    fly-through: the 300-frame rise resampled at s = (i / 299)^2, so the
-    camera starts almost still and ends moving ~2x faster than the uniform
-    rise.  Per guide: stereo frames/s, mean update rate (misses / visible),
-    depth range and PSNR against plain FP32 on every frame."""
+    """Guiding functions of eq. 4 against static depths on two trajectories:
+    the 300-frame rise resampled at s = (i / 299)^2 (accelerating: the camera
+    starts almost still and ends moving ~2x faster than the uniform rise),
+    and a staged walk (three 100-frame stages of 0.2 m + 0.3 deg, 1 m + 3 deg
+    and 3 m + 10 deg per frame), whose update rate crosses 1/8 and 3/8.  Per
+    guide: stereo frames/s, update rate (misses / visible) per stage, depth
+    range, and PSNR against plain FP32 on every frame."""
     import torch
     import paper_2502_14938_amd as gs
     import synth
@@ -836,32 +842,92 @@ def run_guides(args):
     scene = synth.city_scene()
     W, H = synth.CITY_W, synth.CITY_H
     dense = synth.city_flythrough(1200)
-    traj = [dense[round(((i / 299.0) ** 2) * 1199)] for i in range(300)]
+    trajs = {"accelerating rise": [dense[round(((i / 299.0) ** 2) * 1199)] for i in range(300)],
+             "staged walk": synth.city_staged_walk(300)}
     plain = make_renderer(gs, scene, "plain", W, H, args)
     a = [torch.zeros(3, H, W, device="cuda") for _ in range(4)]
-    rows = {}
-    for name, guide, d_max in (("static depth 10", "fixed", 10), ("static depth 3", "fixed", 3),
-                               ("linear", "linear", 10), ("exponential", "exp", 10), ("staged", "staged", 10)):
-        r = gs.Renderer(k=scene.k, d_max=d_max, guide=guide, max_width=W, max_height=H, reuse=True,
-                        precision="bf16")
-        r.load(scene)
-        ps, rate, depth = [], [], []
-        for L, R in traj:
-            r.frame(L, R, a[0], a[1])
-            st = r.stats()
-            plain.frame(L, R, a[2], a[3])
-            ps += [psnr_dev(torch, a[0], a[2]), psnr_dev(torch, a[1], a[3])]
-            rate.append(st["n_miss"] / max(1, st["n_visible"]))
-            depth.append(st["depth_used"])
-        total_s, _, _, _ = timed_pass(torch, r, traj, len(traj), 10, W, H, "guides:" + guide, stages=[])
-        rows[name] = {"fps": round(len(traj) / total_s, 1), "update_rate_mean": round(float(np.mean(rate)), 4),
-                      "depth_min": int(min(depth)), "depth_max": int(max(depth)),
-                      "psnr_db_min": round(float(np.min(ps)), 2), "psnr_db_mean": round(float(np.mean(ps)), 2)}
-        r.close()
-        print("guides: %s done" % name, file=sys.stderr, flush=True)
-    print(json.dumps({"mode": "guides", "workload": "synthetic city 1M anchors, 300-frame fly-through rising "
-                      "2->300 m resampled at s = (i/299)^2 (accelerating), stereo 2048x1080, cache + BF16",
-                      "guides": rows}), flush=True)
+    out = {}
+    for tname, traj in trajs.items():
+        rows = {}
+        n3 = len(traj) // 3
+        for name, guide, d_max in (("static depth 10", "fixed", 10), ("static depth 3", "fixed", 3),
+                                   ("linear", "linear", 10), ("exponential", "exp", 10), ("staged", "staged", 10)):
+            r = gs.Renderer(k=scene.k, d_max=d_max, guide=guide, max_width=W, max_height=H, reuse=True,
+                            precision="bf16")
+            r.load(scene)
+            ps, rate, depth = [], [], []
+            for L, R in traj:
+                r.frame(L, R, a[0], a[1])
+                st = r.stats()
+                plain.frame(L, R, a[2], a[3])
+                ps += [psnr_dev(torch, a[0], a[2]), psnr_dev(torch, a[1], a[3])]
+                rate.append(st["n_miss"] / max(1, st["n_visible"]))
+                depth.append(st["depth_used"])
+            total_s, _, _, _ = timed_pass(torch, r, traj, len(traj), 10, W, H, "guides:" + guide, stages=[])
+            rows[name] = {"fps": round(len(traj) / total_s, 1), "update_rate_mean": round(float(np.mean(rate)), 4),
+                          "update_rate_per_third": [round(float(np.mean(rate[i * n3:(i + 1) * n3])), 4)
+                                                    for i in range(3)],
+                          "depth_min": int(min(depth)), "depth_max": int(max(depth)),
+                          "psnr_db_min": round(float(np.min(ps)), 2), "psnr_db_mean": round(float(np.mean(ps)), 2)}
+            r.close()
+            print("guides: %s / %s done" % (tname, name), file=sys.stderr, flush=True)
+        out[tname] = rows
+    print(json.dumps({"mode": "guides", "workload": "synthetic city 1M anchors, stereo 2048x1080, cache + BF16; "
+                      "300-frame accelerating rise (s = (i/299)^2) and 300-frame staged walk",
+                      "guides": out}), flush=True)
+
+
+# --------------------------------------------------------------------------- Octree-GS fidelity
+
+PAPER_BUCKETS = {"other": ("schedule",), "anchor_decoder": ("derive", "compose"),
+                 "rasterizer": ("preprocess", "tall_spans", "depth_sort", "pair_scan", "dup_rows", "tall_list",
+                                "dup_big", "tile_sort", "ranges", "blend")}
+
+
+def run_lod(args):
+    """The paper's per-frame split (the kernel-duration figure of Section 7:
+    "Other" before the AnchorDecoder, the AnchorDecoder, the Rasterizer) on
+    the 300-frame city fly-through for a Scaffold-like configuration (integer
+    levels, MLP input [f; d_view]) and an Octree-GS-like one (the fractional
+    level transition and the MLPs' distance input), plain FP32 and cached
+    BF16.  "Other" is the selection over every anchor (level switching and
+    frustum test), compaction and the cache schedule; the AnchorDecoder is
+    the derivation and compose; the Rasterizer is everything after."""
+    import torch
+    import paper_2502_14938_amd as gs
+    import synth
+
+    torch.cuda.set_device(0)
+    W, H = synth.CITY_W, synth.CITY_H
+    traj = synth.city_flythrough(300)
+    out = {}
+    for cname, dist_input, fade in (("scaffold-like", False, False), ("octree-like", True, True)):
+        scene = synth.city_scene(dist_input=dist_input)
+        for form in ("plain", "cached-bf16"):
+            kw = dict(FORMS[form])
+            r = gs.Renderer(k=scene.k, d_max=args.d_max, max_width=W, max_height=H, lod_fade=fade, **kw)
+            r.load(scene)
+            _, _, st, frames = timed_pass(torch, r, traj, len(traj), args.warmup, W, H, "lod-stages:" + form)
+            t, lat, _, _ = timed_pass(torch, r, traj, len(traj), args.warmup, W, H, "lod:" + form, stages=[])
+            per = {k: v / max(1, frames) for k, v in st.items()}
+            oL = torch.zeros(3, H, W, device="cuda"); oR = torch.zeros(3, H, W, device="cuda")
+            r.reset_cache()
+            vis = []
+            for L, R_ in traj:
+                r.frame(L, R_, oL, oR)
+                vis.append(r.stats()["n_visible"])
+            r.close()
+            out["%s/%s" % (cname, form)] = {
+                "fps": round(len(traj) / t, 2), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                "ms_per_frame": {b: round(sum(per[k] for k in ks), 4) for b, ks in PAPER_BUCKETS.items()},
+                "visible_per_frame": round(float(np.mean(vis)))}
+            print("lod: %s/%s done" % (cname, form), file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "lod", "workload": "synthetic city 1M anchors, 300-frame fly-through rising 2->300 m, "
+                      "stereo 2048x1080 per eye; scaffold-like = integer levels, MLP input [f; d_view]; octree-like "
+                      "= fractional level transition + distance input [f; d_view; dist/1000 m]",
+                      "split": "other = selection + cache schedule; anchor_decoder = derivation + compose; "
+                               "rasterizer = preprocess ... blend (stage events, a separate pass)",
+                      "configs": out}), flush=True)
 
 
 def main():
@@ -878,6 +944,8 @@ def main():
         run_precision(args)
     elif args.mode == "reuse":
         run_reuse(args)
+    elif args.mode == "lod":
+        run_lod(args)
     else:
         run_frames(args)
 

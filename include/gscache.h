@@ -61,6 +61,14 @@ extern "C" {
                                      re-derived (only adds misses) */
 #define GSC_FLAG_FULL_KEY_SORT 8u /* sort full 64-bit (tile<<32 | depth) keys after duplication
                                      instead of pre-sorting depths per Gaussian; same order */
+#define GSC_FLAG_LOD_FADE 16u     /* fractional level transition (a reading of the distance-driven
+                                     levels of detail of Section 3.1, as in the cited Octree-GS):
+                                     an anchor of level l > 0 is selected while its distance to the
+                                     unified camera is below 2 d_l (d_l = d_ref 2^-l) and its
+                                     Gaussians are rasterised with opacity alpha * w, w =
+                                     clamp(2 - dist / d_l, 0, 1): full weight up to d_l, fading to
+                                     0 over the next octave of distance.  The cache and the render
+                                     buffer's alpha > 0 mask keep the derived alpha. */
 
 /* Cache depth guiding function H (eq. 4). */
 #define GSC_GUIDE_LINEAR 0 /* d = clamp(round_half_up(d_max (1 - r)), 1, d_max), r = misses/visible */
@@ -104,7 +112,12 @@ typedef struct gsc_camera {
  *   anchor derives), feat [n,F], scale [n,6] ([0:3] offset scale, [3:6]
  *   base Gaussian scale), offsets [n,k,3].
  * d_ref: LOD reference distance; an anchor of level l > 0 is used only
- * within d_ref * 2^-l of the unified camera. */
+ * within d_ref * 2^-l of the unified camera (2 d_ref 2^-l with
+ * GSC_FLAG_LOD_FADE).
+ * dist_unit: 0, or > 0 for MLPs that take the anchor's distance to the
+ * unified camera as an input after the view direction (the cited methods'
+ * optional camera-distance feature): layer 1 then reads [f; d_view;
+ * |x - p_u| / dist_unit] and W1[h] has F + 4 columns (see gsc_mlp). */
 typedef struct gsc_anchors {
     int64_t n;
     const float* pos;
@@ -115,13 +128,15 @@ typedef struct gsc_anchors {
     const float* offsets;
     double d_ref;
     int32_t is_device;
+    double dist_unit;
 } gsc_anchors;
 
 /* Derivation MLPs (eq. 3), host float32, row-major [out, in] like
  * torch.nn.Linear; head 0 = opacity (k outputs), 1 = colour (3k), 2 =
  * covariance (7k: 3 scale logits then quaternion w,x,y,z per Gaussian).
- * W1[h] is [hidden, F+3] (inputs: feature then view direction), W2[h] is
- * [c_h k, hidden]. */
+ * W1[h] is [hidden, F+3] (inputs: feature then view direction), or
+ * [hidden, F+4] when gsc_anchors.dist_unit > 0 (then the scaled distance),
+ * W2[h] is [c_h k, hidden]. */
 typedef struct gsc_mlp {
     const float* W1[3];
     const float* b1[3];
@@ -402,6 +417,17 @@ int gsc_server_pending(gsc_server* s);
  *     it with GSC_E_EXPIRED (its output buffers hold the render anyway).
  * Applies to later calls; queued requests keep their place. */
 int gsc_server_policy(gsc_server* s, double pose_m, double pose_rad, double timeout_s, int ordered);
+/* Two batches in flight (Section 5's asynchronous rendering of whole frames,
+ * on one GPU): with enable nonzero, a batch's blend runs on a stream of its
+ * own while the next batch's derive stages (selection, cache schedule,
+ * derivation, compose) and raster stages up to the tile ranges run on the
+ * server's stream, so a request that arrives while a batch is on the GPU
+ * starts its work beside that batch's blend.  Two raster buffer sets
+ * alternate by batch, so each admitted viewer counts its raster share twice
+ * against the budget.  Images are the same as with one batch at a time.
+ * Must be called before any viewer is admitted (else GSC_E_INVALID_ARG);
+ * synchronises the server's streams. */
+int gsc_server_overlap(gsc_server* s, int enable);
 /* Remove a viewer with no queued requests and free its buffers (waits for
  * outstanding batches). */
 int gsc_server_leave(gsc_server* s, int32_t viewer);

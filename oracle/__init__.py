@@ -63,7 +63,7 @@ def _load():
         lib.orc_tile_pairs.argtypes = [C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int64, P, P, P]
         lib.orc_tile_pairs.restype = C.c_int64
         lib.orc_sort_pairs.argtypes = [C.c_int64, P, P, P, P]
-        lib.orc_blend.argtypes = [C.c_int, C.c_int] + [P] * 13 + [C.c_double]
+        lib.orc_blend.argtypes = [C.c_int, C.c_int] + [P] * 13 + [C.c_double, P, P, P]
         lib.orc_round_bf16.argtypes = [C.c_double]
         lib.orc_round_bf16.restype = C.c_double
         lib.orc_round_e4m3.argtypes = [C.c_double]
@@ -234,19 +234,27 @@ def tile_ranges(sorted_tile, n_tiles: int):
     return st, en
 
 
-def blend(W, H, starts, ends, sorted_g, pre, alpha, rgb, alpha_band: float = 1e-7):
+def blend(W, H, starts, ends, sorted_g, pre, alpha, rgb, alpha_band: float = 1e-7, ghosts=None):
     """Front-to-back alpha compositing per pixel (Section 3.1).  Returns the
     image, final transmittance, contributors, ambiguity band and the number
-    of Gaussians each pixel visited (up to and including the one ending it)."""
+    of Gaussians each pixel visited (up to and including the one ending it).
+    ghosts: (starts, ends, g) per tile of the marginal pairs the tile test
+    left out; they are never composited, only flag the pixels where they
+    reach the alpha threshold."""
     lib = _load()
     npx = W * H
     img = np.zeros((3, H, W)); T = np.zeros((H, W)); nc = np.zeros((H, W), np.int32)
     band = np.zeros((H, W), np.uint8)
     ne = np.zeros((H, W), np.int32)
     sg = _c(sorted_g, np.int32); alpha = _c(alpha, np.float64); rgb = _c(rgb, np.float64)
+    if ghosts is not None:
+        gk = [_c(ghosts[0], np.int64), _c(ghosts[1], np.int64), _c(ghosts[2], np.int32)]
+        gp = [_p(x) for x in gk]
+    else:
+        gp = [None, None, None]
     lib.orc_blend(W, H, _p(_c(starts, np.int64)), _p(_c(ends, np.int64)), _p(sg), _p(pre["mean2d"]),
                   _p(pre["conic"]), _p(alpha), _p(rgb), _p(pre["depth"]), _p(img), _p(T), _p(nc), _p(band), _p(ne),
-                  float(alpha_band))
+                  float(alpha_band), *gp)
     return img, T, nc, band, ne
 
 
@@ -264,7 +272,12 @@ def render_gaussians(mu, cov, rgb, alpha, cam: dict, debug: bool = False, alpha_
     st_tile, st_g = lt[order], lg[order]
     ntiles = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
     s, e = tile_ranges(st_tile, ntiles)
-    img, T, nc, band, ne = blend(W, H, s, e, st_g, pre, alpha, np.asarray(rgb, np.float64), alpha_band)
+    ghost = fl == 2                                   # marginal, left out
+    go = np.argsort(tile[ghost], kind="stable")
+    gt, gg = tile[ghost][go], g[ghost][go]
+    gs_, ge_ = tile_ranges(gt, ntiles)
+    img, T, nc, band, ne = blend(W, H, s, e, st_g, pre, alpha, np.asarray(rgb, np.float64), alpha_band,
+                                 ghosts=(gs_, ge_, gg))
     out = {"image": img, "T": T, "n_contrib": nc, "band": band, "n_pairs": int(listed.sum()), "n_eval": ne}
     if debug:
         out.update(pre=pre, pairs_tile=tile, pairs_g=g, pairs_flags=fl, sorted_tile=st_tile,

@@ -385,10 +385,23 @@ double orc_rect_min_q(double mx, double my, double a, double b, double c, double
     return q;
 }
 
+/* Screen-position resolution of a float32 implementation at (mx, my) in a
+ * W x H image: two float32 ulps of the coordinate scale |mx| + |my| + W + H.
+ * A float32 pixel coordinate is rounded once itself, and the camera
+ * transform, the division by depth and the focal scaling before it round
+ * at scales no larger than that (far Gaussians near x = 2000 px resolve only
+ * ~1e-4 px).  A decision whose margin in q is below |grad q| * delta (at
+ * most 2 sqrt(q (a + c)) * delta, a + c bounding the conic's largest
+ * eigenvalue) can go either way in float32 and is marginal. */
+static double pos_delta(double mx, double my, int W, int H) {
+    return ldexp(fabs(mx) + fabs(my) + (double)W + (double)H, -23);
+}
+
 /* Candidate tiles come from the ellipse's bounding box (half extents
  * sqrt(tau * Sigma2D_xx), sqrt(tau * Sigma2D_yy)) padded by one pixel, so the
  * exact test alone decides.  Emission order: g ascending, tiles row-major.
- * flags: bit0 = listed, bit1 = |min q - tau| within 1e-5 relative (band).
+ * flags: bit0 = listed, bit1 = |min q - tau| within 1e-5 relative plus the
+ * change the float32 screen position allows (pos_delta) (band).
  * Pairs are written when listed or in band.  Returns the number written, or
  * the negative of the number needed when cap is too small. */
 static int64_t tiles_of(double mx, double my, const double* cn, const double* sg, double al, int W, int H,
@@ -404,6 +417,7 @@ static int64_t tiles_of(double mx, double my, const double* cn, const double* sg
     if (tx1 > ntx - 1) tx1 = ntx - 1;
     if (ty1 > nty - 1) ty1 = nty - 1;
     int64_t cnt = 0;
+    const double qband = 1e-5 * (tau + 1.0) + 2.0 * sqrt(tau * (cn[0] + cn[2])) * pos_delta(mx, my, W, H);
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
             double x0 = ORC_TILE * tx + 0.5, y0 = ORC_TILE * ty + 0.5;
@@ -411,7 +425,7 @@ static int64_t tiles_of(double mx, double my, const double* cn, const double* sg
             double y1 = (ORC_TILE * ty + ORC_TILE - 1 < H - 1 ? ORC_TILE * ty + ORC_TILE - 1 : H - 1) + 0.5;
             double q = orc_rect_min_q(mx, my, cn[0], cn[1], cn[2], x0, x1, y0, y1);
             int listed = q <= tau;
-            int bnd = fabs(q - tau) <= 1e-5 * (tau + 1.0);
+            int bnd = fabs(q - tau) <= qband;
             if (listed || bnd) {
                 if (tile && cnt < cap) {
                     tile[cnt] = ty * ntx + tx;
@@ -492,15 +506,30 @@ void orc_sort_pairs(int64_t n, const int32_t* tile, const int32_t* g, const doub
  *   C += rgb_g alpha T;  T *= 1 - alpha.
  * Outputs planar RGB [3,H,W] (background 0), final T [H,W], and the number
  * of Gaussians added per pixel.  pix_band[p] = 1 when any decision at that
- * pixel is marginal (alpha vs 1/255 within alpha_band (1e-7; wider where the
- * opacities carry a weight computed in float32 on the other side), the stop
- * test within 1e-9,
- * or two consecutive added Gaussians whose depths are within 4 float32 ulps
- * so their order is not fixed by float32 keys). */
+ * pixel is marginal: alpha vs 1/255 within alpha_band (1e-7; wider where the
+ * opacities carry a weight computed in float32 on the other side) plus
+ * alpha's change under the float32 screen-position resolution (pos_delta),
+ * or q vs 2 ln(255 alpha_g) within the tile test's band; the stop test within
+ * 1e-9 plus T times that change; two consecutive added Gaussians whose
+ * depths are within 4 float32 ulps so their order is not fixed by float32
+ * keys; or a marginal pair the tile test left out (ghost_*: per-tile ranges
+ * into ghost_g, may be NULL) reaching the threshold at the pixel. */
+/* Is the alpha threshold of Gaussian g at a pixel with quadratic form q
+ * marginal?  In q: alpha_g exp(-q/2) >= 1/255 <=> q <= tau = 2 ln(255
+ * alpha_g), the tile test's inequality at the pixel, with the tile test's
+ * band (1e-5 relative plus the float32 screen-position term). */
+static int alpha_q_marginal(double q, double al, const double* cn, double mx, double my, int W, int H) {
+    if (!(al > 0.0)) return 0;
+    double tau = 2.0 * log(255.0 * al);
+    double qband = 1e-5 * (fabs(tau) + 1.0) + 2.0 * sqrt(q * (cn[0] + cn[2])) * pos_delta(mx, my, W, H);
+    return fabs(q - tau) <= qband;
+}
+
 void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end, const int32_t* sorted_g,
                const double* mean2d, const double* conic, const double* alpha, const double* rgb,
                const double* depth, double* out_rgb, double* out_T, int32_t* n_contrib, uint8_t* pix_band,
-               int32_t* n_eval, double alpha_band) {
+               int32_t* n_eval, double alpha_band, const int64_t* ghost_start, const int64_t* ghost_end,
+               const int32_t* ghost_g) {
     int ntx = (W + ORC_TILE - 1) / ORC_TILE;
     int64_t npx = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -520,10 +549,14 @@ void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end,
                 double q = cn[0] * dx * dx + 2.0 * cn[1] * dx * dy + cn[2] * dy * dy;
                 double a = alpha[g] * exp(-0.5 * q);
                 if (a > 0.99) a = 0.99;
-                if (fabs(a - 1.0 / 255.0) < alpha_band) bnd = 1;
+                /* alpha's uncertainty from the float32 screen position */
+                double da = a * sqrt(q * (cn[0] + cn[2])) * pos_delta(mean2d[2 * g], mean2d[2 * g + 1], W, H);
+                if (fabs(a - 1.0 / 255.0) < alpha_band + da ||
+                    alpha_q_marginal(q, alpha[g], cn, mean2d[2 * g], mean2d[2 * g + 1], W, H))
+                    bnd = 1;
                 if (a < 1.0 / 255.0) continue;
                 double tn = T * (1.0 - a);
-                if (fabs(tn - 1e-4) < 1e-9) bnd = 1;
+                if (fabs(tn - 1e-4) < 1e-9 + T * da) bnd = 1;
                 if (tn < 1e-4) break;
                 float fd = (float)depth[g];
                 if (prev_depth >= 0.0 && fabs(depth[g] - prev_depth) <= 4.0 * (nextafterf(fd, INFINITY) - fd))
@@ -533,6 +566,19 @@ void orc_blend(int W, int H, const int64_t* tile_start, const int64_t* tile_end,
                 T = tn;
                 ++nc;
             }
+            /* marginal pairs the tile test left out: the other side may list
+             * them, and then composites them wherever alpha reaches 1/255 */
+            if (ghost_start)
+                for (int64_t i = ghost_start[tile]; i < ghost_end[tile] && !bnd; ++i) {
+                    int32_t g = ghost_g[i];
+                    double dx = px - mean2d[2 * g], dy = py - mean2d[2 * g + 1];
+                    const double* cn = conic + 3 * g;
+                    double q = cn[0] * dx * dx + 2.0 * cn[1] * dx * dy + cn[2] * dy * dy;
+                    double a = alpha[g] * exp(-0.5 * q);
+                    if (a >= 1.0 / 255.0 - alpha_band ||
+                        alpha_q_marginal(q, alpha[g], cn, mean2d[2 * g], mean2d[2 * g + 1], W, H))
+                        bnd = 1;
+                }
             int64_t p = (int64_t)v * W + u;
             for (int c = 0; c < 3; ++c) out_rgb[c * npx + p] = C[c];
             out_T[p] = T;

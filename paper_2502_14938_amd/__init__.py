@@ -19,7 +19,7 @@ GSC_E_UNCHANGED, GSC_E_TIMEOUT, GSC_E_EXPIRED = -7, -8, -9
 ERRORS = {-1: "GSC_E_INVALID_ARG", -2: "GSC_E_NOT_LOADED", -3: "GSC_E_OOM", -4: "GSC_E_CAPACITY",
           -5: "GSC_E_BUDGET", -6: "GSC_E_HIP", -7: "GSC_E_UNCHANGED", -8: "GSC_E_TIMEOUT", -9: "GSC_E_EXPIRED"}
 PREC = {"f32": 0, "bf16": 1, "fp8": 2}
-FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT = 1, 2, 4, 8
+FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT, FLAG_LOD_FADE = 1, 2, 4, 8, 16
 GUIDE = {"linear": 0, "fixed": 1, "exp": 2, "staged": 3}
 DBG = {"visible": 0, "misses": 1, "gauss": 2, "derived": 3, "pairs": 4, "ranges": 5, "preproc": 6, "depth": 7,
        "sort_keys": 8, "raw_ranges": 9}
@@ -47,7 +47,7 @@ class Camera(C.Structure):
 class Anchors(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("level", C.c_void_p), ("radius", C.c_void_p),
                 ("feat", C.c_void_p), ("scale", C.c_void_p), ("offsets", C.c_void_p), ("d_ref", C.c_double),
-                ("is_device", C.c_int32)]
+                ("is_device", C.c_int32), ("dist_unit", C.c_double)]
 
 
 class Mlp(C.Structure):
@@ -109,6 +109,7 @@ SYMBOLS = {
     "gsc_server_poll": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "gsc_server_pending": ([C.c_void_p], C.c_int),
     "gsc_server_policy": ([C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int], C.c_int),
+    "gsc_server_overlap": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing": ([C.c_void_p, C.c_int], C.c_int),
     "gsc_timing_stages": ([C.c_void_p, C.c_uint32], C.c_int),
     "gsc_count_work": ([C.c_void_p, C.c_int], C.c_int),
@@ -166,13 +167,14 @@ class Renderer:
 
     def __init__(self, k=10, d_max=10, guide="linear", precision="f32", reuse=False, deredundancy=True,
                  predictor=False, full_key_sort=False, max_width=2048, max_height=1080, cache_capacity=0,
-                 max_pairs=0, predictor_threshold=0.5, stream=None):
+                 max_pairs=0, predictor_threshold=0.5, lod_fade=False, stream=None):
         L = lib()
         cfg = Config()
         cfg.k, cfg.feat_dim, cfg.hidden, cfg.d_max = k, 32, 32, d_max
         cfg.guide, cfg.precision = GUIDE[guide], PREC[precision]
         cfg.flags = ((FLAG_DEREDUNDANCY if deredundancy else 0) | (FLAG_REUSE if reuse else 0) |
-                     (FLAG_PREDICTOR if predictor else 0) | (FLAG_FULL_KEY_SORT if full_key_sort else 0))
+                     (FLAG_PREDICTOR if predictor else 0) | (FLAG_FULL_KEY_SORT if full_key_sort else 0) |
+                     (FLAG_LOD_FADE if lod_fade else 0))
         cfg.predictor_threshold = predictor_threshold
         cfg.cache_capacity, cfg.max_width, cfg.max_height, cfg.max_pairs = cache_capacity, max_width, max_height, max_pairs
         self.cfg = cfg
@@ -213,6 +215,9 @@ class Renderer:
         a.pos, a.level, a.radius, a.feat, a.scale, a.offsets = [x.ctypes.data for x in arrs]
         a.d_ref = float(min(scene.d_ref, 1e30))
         a.is_device = 0
+        # a distance input: layer 1 has F + 4 columns and the scene its unit
+        n_in = np.asarray(scene.mlp["alpha"][0]).shape[1]
+        a.dist_unit = float(getattr(scene, "dist_unit", 0.0)) if n_in == scene.F + 4 else 0.0
         m = Mlp()
         keep = []
         for h, name in enumerate(("alpha", "color", "cov")):
@@ -430,6 +435,11 @@ class Server:
         host monotonic clock (time.monotonic()), display order."""
         self._check(lib().gsc_server_policy(self.h, float(pose_m), float(pose_rad), float(timeout_s),
                                             1 if ordered else 0))
+
+    def overlap(self, enable=True):
+        """Two batches in flight: each batch's blend overlaps the next batch's
+        earlier stages (call before admitting viewers)."""
+        self._check(lib().gsc_server_overlap(self.h, 1 if enable else 0))
 
     def step(self) -> int:
         return self._check(lib().gsc_server_step(self.h))

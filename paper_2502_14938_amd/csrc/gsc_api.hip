@@ -65,8 +65,9 @@ void unified_camera(const gsc_camera& l, const gsc_camera& r, gsc_camera& u) {
 }
 
 // Frustum planes of a camera in world space, inward: n.x + w >= -radius.
-DeriveCam derive_cam(const gsc_camera& c, float d_ref) {
+DeriveCam derive_cam(const gsc_camera& c, float d_ref, bool fade) {
     DeriveCam dc;
+    dc.fade = fade ? 1 : 0;
     double tx = std::tan(0.5 * c.fovx), ty = std::tan(0.5 * c.fovy);
     double nx = std::sqrt(1.0 + tx * tx), ny = std::sqrt(1.0 + ty * ty);
     double cam_n[5][3] = {{0.0, 0.0, 1.0},
@@ -87,6 +88,12 @@ DeriveCam derive_cam(const gsc_camera& c, float d_ref) {
     dc.d_ref = (float)d_ref;
     dc.fx = (float)(c.width / (2.0 * tx));
     return dc;
+}
+
+void seg_lod_fade(Seg& s, const Scene& sc, const gsc_camera& derive_camera) {
+    s.level = sc.level;
+    for (int i = 0; i < 3; ++i) s.upos[i] = (float)derive_camera.pos[i];  // as derive_cam rounds it
+    s.d_ref = sc.d_ref;
 }
 
 bool valid_camera(const gsc_camera& c) {
@@ -383,6 +390,8 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
         if (!mlp->W1[h] || !mlp->b1[h] || !mlp->W2[h] || !mlp->b2[h])
             return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: null weight");
     if (!(an->d_ref > 0)) return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: d_ref must be positive");
+    if (!(an->dist_unit >= 0) || !std::isfinite(an->dist_unit))
+        return fail(c, GSC_E_INVALID_ARG, "gsc_load_anchors: dist_unit must be 0 or positive");
     const int64_t n = an->n;
     const int k = c->cfg.k;
     free_all(c);
@@ -408,6 +417,7 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
     sc.n = n;
     sc.k = k;
     sc.d_ref = (float)an->d_ref;
+    sc.dist_unit = (float)an->dist_unit;
     int lmax = 0;
     for (int64_t a = 0; a < n; ++a) lmax = lev[a] > lmax ? lev[a] : lmax;
     sc.l_max = lmax;
@@ -435,7 +445,7 @@ int gsc_load_anchors(gsc_ctx* c, const gsc_anchors* an, const gsc_mlp* mlp) {
         return fail(c, GSC_E_OOM, "gsc_load_anchors: device allocation"); \
     }
     A_(sc.posr, n); A_(sc.level, n); A_(sc.feat, n * kF); A_(sc.scale, n * 6); A_(sc.offsets, n * k * 3);
-    HostFrags hf = pack_frags(*mlp, k);
+    HostFrags hf = pack_frags(*mlp, k, an->dist_unit > 0 ? kF + 4 : kF + 3);
     A_(sc.fr_l1_f32, hf.l1_f32.size()); A_(sc.fr_l2_f32, hf.l2_f32.size());
     A_(sc.fr_l1_bf16, hf.l1_bf16.size()); A_(sc.fr_l2_bf16, hf.l2_bf16.size());
     A_(sc.fr_l1_fp8, hf.l1_fp8.size()); A_(sc.fr_l2_fp8, hf.l2_fp8.size());
@@ -511,7 +521,7 @@ int gsc_derive(gsc_ctx* c) {
         a.sc = &c->scene;
         a.v = &c->view[vi];
         const gsc_camera& cam = c->nviews == 1 ? c->unified : c->eye[vi];
-        a.cam = derive_cam(cam, c->scene.d_ref);
+        a.cam = derive_cam(cam, c->scene.d_ref, (c->cfg.flags & GSC_FLAG_LOD_FADE) != 0);
         a.precision = c->cfg.precision;
         a.flags = c->cfg.flags;
         if (c->nviews == 2) a.flags &= ~(GSC_FLAG_REUSE | GSC_FLAG_PREDICTOR);
@@ -549,6 +559,7 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
         const bool direct = (c->cfg.flags & GSC_FLAG_REUSE) && c->nviews == 1 && v.C >= c->scene.n;
         s.anchor_pos = c->scene.posr; s.line_anchor = direct ? nullptr : v.line_anchor; s.k = c->scene.k;
         seg_camera(s, c->eye[e]);
+        if (c->cfg.flags & GSC_FLAG_LOD_FADE) seg_lod_fade(s, c->scene, c->nviews == 1 ? c->unified : c->eye[e]);
         s.tile_base = tiles;
         tiles += s.ntx * s.nty;
         s.out_rgb = outs[e];

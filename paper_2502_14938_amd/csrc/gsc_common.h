@@ -79,6 +79,11 @@ struct Seg {
     float* out_rgb;     // [3,H,W]
     float* out_T;       // [H,W] or nullptr
     int32_t* out_nc;    // [H,W] or nullptr
+    // fractional level transition (nullptr level: off): opacities of a
+    // level-l anchor's Gaussians scaled by clamp(2 - |x - p_u| / d_l, 0, 1)
+    const uint8_t* level;
+    float upos[3];      // unified camera centre p_u (as the selection uses it)
+    float d_ref;
 };
 
 struct SegTable {
@@ -93,6 +98,7 @@ struct DeriveCam {
     float planes[5][4];  // inward world planes n.x + w >= -radius keeps
     float d_ref;
     float fx;            // unified focal length (predictor feature)
+    int32_t fade;        // fractional level transition: keep level l > 0 while |x - p_u| < 2 d_l
 };
 
 // Scene on the device (shared by views).
@@ -100,6 +106,7 @@ struct Scene {
     int64_t n = 0;
     int k = 0;
     float d_ref = 0.f;
+    float dist_unit = 0.f;      // > 0: the MLPs' distance input is |x - p_u| / dist_unit
     int l_max = 0;
     float4* posr = nullptr;     // x, y, z, radius
     uint8_t* level = nullptr;

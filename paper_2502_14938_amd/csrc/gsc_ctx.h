@@ -47,7 +47,10 @@ hipError_t alloc_view(AllocSet& set, View& v, int64_t n, int64_t C, int k);
 hipError_t alloc_raster(AllocSet& set, Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles,
                         bool full_key);
 hipError_t reset_view(View& v, int64_t n, int dmax, hipStream_t st);
-DeriveCam derive_cam(const gsc_camera& c, float d_ref);
+DeriveCam derive_cam(const gsc_camera& c, float d_ref, bool fade);
+// The fractional level transition's inputs for a segment: the scene's levels
+// and d_ref, and the centre of the camera the view derives with.
+void seg_lod_fade(Seg& s, const Scene& sc, const gsc_camera& derive_camera);
 void unified_camera(const gsc_camera& l, const gsc_camera& r, gsc_camera& u);
 bool valid_camera(const gsc_camera& c);
 }  // namespace gsc

@@ -37,8 +37,9 @@ __device__ __forceinline__ void frame_begin(Counters* cnt, float* pu_hist, int32
 }
 
 // ------------------------------------------------------------- selection
-// Keep anchor a iff (level 0 or |x - p_u| <= d_ref 2^-level) and its bounding
-// sphere is not wholly outside any unified-frustum plane (4 sides + near).
+// Keep anchor a iff (level 0 or |x - p_u| <= d_ref 2^-level, or < 2 d_ref
+// 2^-level with the fractional level transition) and its bounding sphere is
+// not wholly outside any unified-frustum plane (4 sides + near).
 // Direct-mapped cache (line_anchor non-null: line a can only hold anchor a):
 // the invalidation of Alg. 1 is done here too, anchor a's line dropped when
 // its age exceeds the current depth (the depth is the previous frame's
@@ -61,7 +62,11 @@ __global__ __launch_bounds__(NT) void k_select_flags(const float4* __restrict__ 
         if (l != 0) {
             float vx = p.x - cam.pos[0], vy = p.y - cam.pos[1], vz = p.z - cam.pos[2];
             float lim = ldexpf(cam.d_ref, -l);
-            keep = vx * vx + vy * vy + vz * vz <= lim * lim;
+            float d2 = vx * vx + vy * vy + vz * vz;
+            // with the fractional transition a level stays until its weight
+            // clamp(2 - dist / d_l, 0, 1) reaches 0 (the weight is applied
+            // by the rasteriser's preprocess)
+            keep = cam.fade ? d2 < 4.f * lim * lim : d2 <= lim * lim;
         }
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
@@ -529,6 +534,7 @@ hipError_t derive_frame(const DeriveArgs& a, hipStream_t st, Marks* mk) {
         m.posr = sc.posr; m.feat = sc.feat; m.scale = sc.scale; m.offsets = sc.offsets; m.k = sc.k;
         m.visible = v.visible; m.misses = v.misses; m.vslot = v.vslot; m.L0 = v.L0; m.L1 = v.L1; m.L2 = v.L2;
         m.L3 = v.L3; m.line_mask = v.line_mask; m.cam_pos[0] = a.cam.pos[0]; m.cam_pos[1] = a.cam.pos[1]; m.cam_pos[2] = a.cam.pos[2];
+        m.inv_dist_unit = sc.dist_unit > 0.f ? 1.0f / sc.dist_unit : 0.f;
         m.n_miss = &cnt->n_miss; m.mode = a.precision;
         m.fr.l1_f32 = sc.fr_l1_f32; m.fr.l2_f32 = sc.fr_l2_f32; m.fr.l1_bf16 = sc.fr_l1_bf16;
         m.fr.l2_bf16 = sc.fr_l2_bf16; m.fr.l1_fp8 = sc.fr_l1_fp8; m.fr.l2_fp8 = sc.fr_l2_fp8;

@@ -27,13 +27,15 @@ struct MfmaFrags {
 };
 
 // Host: pack fragments for k Gaussians per anchor from row-major weights
-// W1[h] [32][35], W2[h] [c_h k][32], biases; returns host vectors to upload.
+// W1[h] [32][n_in] (n_in = 35, or 36 with the distance input, which takes
+// the padding column 35), W2[h] [c_h k][32], biases; returns host vectors to
+// upload.
 struct HostFrags {
     std::vector<float> l1_f32, l2_f32, b1, b2, s1, s2;
     std::vector<uint16_t> l1_bf16, l2_bf16, l1_fp8, l2_fp8;
     int n_at, n_ct, n_vt;
 };
-HostFrags pack_frags(const gsc_mlp& mlp, int k);
+HostFrags pack_frags(const gsc_mlp& mlp, int k, int n_in);
 
 struct MfmaDeriveArgs {
     const float4* posr;
@@ -50,6 +52,7 @@ struct MfmaDeriveArgs {
     float* L3;
     uint16_t* line_mask;  // [lines] bit j: Gaussian j has alpha > 0 (may be null)
     float cam_pos[3];
+    float inv_dist_unit;  // > 0: layer 1 takes |x - p_u| * inv_dist_unit as input 35
     const int32_t* n_miss;
     int mode;  // GSC_PREC_*
     MfmaFrags fr;

@@ -71,7 +71,7 @@ __device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x))
 
 }  // namespace
 
-HostFrags pack_frags(const gsc_mlp& mlp, int k) {
+HostFrags pack_frags(const gsc_mlp& mlp, int k, int n_in) {
     HostFrags f;
     const int c[3] = {1, 3, 7};
     f.n_at = (k + 15) / 16;
@@ -87,13 +87,13 @@ HostFrags pack_frags(const gsc_mlp& mlp, int k) {
         for (int r = 0; r < 32; ++r) {
             int row = h * 32 + r;
             double amax = 0.0;
-            for (int q = 0; q < 35; ++q) {
-                W1p[row * 48 + q] = mlp.W1[h][r * 35 + q];
+            for (int q = 0; q < n_in; ++q) {
+                W1p[row * 48 + q] = mlp.W1[h][r * n_in + q];
                 amax = std::fmax(amax, std::fabs(W1p[row * 48 + q]));
             }
             double s = amax > 0.0 ? amax / 448.0 : 1.0;
             f.s1[row] = (float)s;
-            for (int q = 0; q < 35; ++q) q1[row * 48 + q] = h_e4m3(W1p[row * 48 + q] / s);
+            for (int q = 0; q < n_in; ++q) q1[row * 48 + q] = h_e4m3(W1p[row * 48 + q] / s);
             f.b1[row] = mlp.b1[h][r];
         }
     // layer 2, padded [16 nt][32] per tile's head
@@ -119,7 +119,7 @@ HostFrags pack_frags(const gsc_mlp& mlp, int k) {
         for (int ks = 0; ks < 9; ++ks)
             for (int l = 0; l < 64; ++l) {
                 int row = hb * 16 + (l & 15), col = 4 * ks + (l >> 4);
-                f.l1_f32[(hb * 9 + ks) * 64 + l] = col < 35 ? (float)W1p[row * 48 + col] : 0.f;
+                f.l1_f32[(hb * 9 + ks) * 64 + l] = col < n_in ? (float)W1p[row * 48 + col] : 0.f;
             }
     f.l2_f32.assign(nt * 2 * 4 * 64, 0.f);
     for (int ot = 0; ot < nt; ++ot)
@@ -198,8 +198,11 @@ __global__ __launch_bounds__(NT) void k_derive_mfma(MfmaDeriveArgs a) {
             }
             const float4 x = a.posr[aid];
             float vx = x.x - a.cam_pos[0], vy = x.y - a.cam_pos[1], vz = x.z - a.cam_pos[2];
-            float inv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+            const float nv = sqrtf(vx * vx + vy * vy + vz * vz);
+            const float inv = 1.0f / nv;
             const float dv[3] = {vx * inv, vy * inv, vz * inv};
+            // the optional distance input (column 35; its weights are zero without it)
+            const float dn = a.inv_dist_unit > 0.f ? nv * a.inv_dist_unit : 0.f;
             const float* f = a.feat + (int64_t)aid * kF;
             // ---- layer 1: H^T = W1 Z^T, 6 tiles of 16 hidden units
             floatx4 acc[6];
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(NT) void k_derive_mfma(MfmaDeriveArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < 9; ++ks) {
                     int in = 4 * ks + q;
-                    float b = in < kF ? f[in] : (in < kF + 3 ? dv[in - kF] : 0.f);
+                    float b = in < kF ? f[in] : (in < kF + 3 ? dv[in - kF] : (in == kF + 3 ? dn : 0.f));
 #pragma unroll
                     for (int hb = 0; hb < 6; ++hb)
                         acc[hb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1f[hb * 9 + ks], b, acc[hb], 0, 0, 0);
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_derive_mfma(MfmaDeriveArgs a) {
                         z[0] = q == 0 ? dv[0] : 0.f;
                         z[1] = q == 0 ? dv[1] : 0.f;
                         z[2] = q == 0 ? dv[2] : 0.f;
-                        z[3] = 0.f;
+                        z[3] = q == 0 ? dn : 0.f;
                     }
                     shortx4 b = shortx4{d_bf16(z[0]), d_bf16(z[1]), d_bf16(z[2]), d_bf16(z[3])};
 #pragma unroll

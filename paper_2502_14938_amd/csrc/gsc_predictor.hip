@@ -351,6 +351,7 @@ int gsc_predictor_labels(gsc_ctx* c, float* X_out, uint8_t* y_out, int32_t* ids_
     m.visible = v.cand_id; m.misses = c->lab_iota; m.vslot = c->lab_iota;
     m.L0 = c->lab_L0; m.L1 = c->lab_L1; m.L2 = c->lab_L2; m.L3 = c->lab_L3; m.line_mask = nullptr;
     for (int i = 0; i < 3; ++i) m.cam_pos[i] = (float)c->unified.pos[i];
+    m.inv_dist_unit = sc.dist_unit > 0.f ? 1.0f / sc.dist_unit : 0.f;
     m.n_miss = &v.cnt->n_cand; m.mode = GSC_PREC_F32;
     m.fr.l1_f32 = sc.fr_l1_f32; m.fr.l2_f32 = sc.fr_l2_f32; m.fr.l1_bf16 = sc.fr_l1_bf16;
     m.fr.l2_bf16 = sc.fr_l2_bf16; m.fr.l1_fp8 = sc.fr_l1_fp8; m.fr.l2_fp8 = sc.fr_l2_fp8;

@@ -198,6 +198,16 @@ __device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
 constexpr int kSmallRows = 4;
 constexpr int kTallGroup = 8;     // tall entries whose metadata a wave loads together (k_dup_big)
 
+// Fractional level transition: weight clamp(2 - |x - p_u| / d_l, 0, 1) of a
+// level-l anchor's opacities (1 at level 0), the distance taken in FP32 as
+// the selection takes it.
+__device__ __forceinline__ float lod_fade_weight(float4 ap, int l, const Seg& s) {
+    if (l == 0) return 1.f;
+    const float vx = ap.x - s.upos[0], vy = ap.y - s.upos[1], vz = ap.z - s.upos[2];
+    const float d = sqrtf(vx * vx + vy * vy + vz * vz);
+    return fminf(fmaxf(2.f - d / ldexpf(s.d_ref, -l), 0.f), 1.f);
+}
+
 // Per-entry record, 4 x float4 (64 B, one cache line):
 //   A = (mean2d.x, mean2d.y, conic a, conic b)
 //   B = (conic c, alpha, r, g)
@@ -262,10 +272,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // mu - eye = (anchor - eye) + (mu - anchor): the first term in FP64
             // from the exact FP32 anchor, the second as stored
             double ax = 0.0, ay = 0.0, az = 0.0;
+            float lod_w = 1.f;
             if (s.anchor_pos) {
                 const int32_t an = s.line_anchor ? s.line_anchor[src / s.k] : (int32_t)(src / s.k);  // valid for every line in the buffer
-                const float4 ap = s.anchor_pos[an >= 0 ? an : 0];
+                const int32_t ai = an >= 0 ? an : 0;
+                const float4 ap = s.anchor_pos[ai];
                 ax = ap.x; ay = ap.y; az = ap.z;
+                if (s.level) lod_w = lod_fade_weight(ap, s.level[ai], s);
             }
             float vx = (float)((ax - s.pos[0]) + (double)l0.x);
             float vy = (float)((ay - s.pos[1]) + (double)l0.y);
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             float tx = s.R[0] * vx + s.R[1] * vy + s.R[2] * vz;
             float ty = s.R[3] * vx + s.R[4] * vy + s.R[5] * vz;
             float tz = s.R[6] * vx + s.R[7] * vy + s.R[8] * vz;
-            float alpha = l0.w;
+            float alpha = l0.w * lod_w;
             if (tz > s.znear && alpha >= kMinAlpha) {
                 // EWA: Jacobian of the perspective map (off-axis slope clamped)
                 float iz = 1.0f / tz;
@@ -373,6 +386,11 @@ struct DupArgs {
     const uint32_t* spans;   // row spans of the tall footprints
     int64_t span_cap;
 };
+
+// Kernel arguments (the segment table travels by value) stay within the
+// 4 KiB a launch carries.
+static_assert(sizeof(PreArgs) <= 4096 && sizeof(DupArgs) + 2 * sizeof(void*) <= 4096,
+              "raster kernel arguments exceed 4 KiB");
 
 // Pair emission.  Every entry owns the output range [offs[r], offs[r] +
 // count) (ranks in depth order; entry order with full keys), so entries can

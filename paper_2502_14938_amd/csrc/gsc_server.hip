@@ -12,6 +12,11 @@
 //            then ONE raster batch over all (viewer, eye) images, ending in
 //            one blend launch over every (viewer, eye, tile); the host
 //            returns at once and the next step can be queued behind this one
+//   overlap  two batches in flight: a batch's blend runs on a stream of its
+//            own while the next batch's derive stages and raster front run
+//            on the server's stream, over two raster buffer sets that
+//            alternate by batch (a set is reused once the blend that last
+//            read it has finished)
 //   poll     completions, timestamped on the host monotonic clock by a host
 //            function the stream runs when the batch's kernels are done
 #include <algorithm>
@@ -95,6 +100,16 @@ struct gsc_server {
     std::vector<BatchReport*> free_reports;
     std::vector<BatchReport*> all_reports;
     int64_t in_flight = 0;
+    // two batches in flight (gsc_server_overlap)
+    bool overlap = false;
+    hipStream_t blend_st = nullptr;
+    hipEvent_t front_done[2] = {nullptr, nullptr};
+    hipEvent_t blend_done[2] = {nullptr, nullptr};
+    hipEvent_t copies_done[2] = {nullptr, nullptr};
+    bool blend_pending[2] = {false, false};
+    AllocSet rmem2;
+    Raster raster2;
+    int64_t nbatch = 0;
 };
 
 namespace {
@@ -172,14 +187,24 @@ void viewer_share(const gsc_ctx* c, int32_t W, int32_t H, int64_t& entries, int6
     }
 }
 
-size_t viewer_bytes_of(const gsc_ctx* c, int32_t W, int32_t H) {
+// raster_sets: 2 with two batches in flight (each viewer holds a share of both)
+size_t viewer_bytes_of(const gsc_ctx* c, int32_t W, int32_t H, int raster_sets) {
     int64_t e, p, t;
     viewer_share(c, W, H, e, p, t);
     return view_bytes(c->scene.n, viewer_cache_lines(c), c->scene.k) + sizeof(Counters) +
-           raster_bytes(e, p, t, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
+           (size_t)raster_sets * raster_bytes(e, p, t, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
 }
 
-// Size the batch raster for the admitted viewers (stream must be idle).
+// Wait for everything the server enqueued (both streams).
+hipError_t server_sync(gsc_server* s) {
+    hipError_t e = hipStreamSynchronize(s->st);
+    if (e == hipSuccess && s->blend_st) e = hipStreamSynchronize(s->blend_st);
+    s->blend_pending[0] = s->blend_pending[1] = false;
+    return e;
+}
+
+// Size the batch raster (both sets with two batches in flight) for the
+// admitted viewers (streams must be idle).
 hipError_t resize_raster(gsc_server* s) {
     int64_t e = 0, p = 0, t = 0;
     for (auto& v : s->viewers)
@@ -193,12 +218,18 @@ hipError_t resize_raster(gsc_server* s) {
     if (e == s->r_entries && p == s->r_pairs && t == s->r_tiles) return hipSuccess;
     s->rmem.release();
     s->raster = Raster();
+    s->rmem2.release();
+    s->raster2 = Raster();
     s->r_entries = s->r_pairs = s->r_tiles = 0;
     if (e == 0) return hipSuccess;
-    hipError_t err = alloc_raster(s->rmem, s->raster, e, p, t, (s->ctx->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0);
+    const bool fk = (s->ctx->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0;
+    hipError_t err = alloc_raster(s->rmem, s->raster, e, p, t, fk);
+    if (err == hipSuccess && s->overlap) err = alloc_raster(s->rmem2, s->raster2, e, p, t, fk);
     if (err != hipSuccess) {
         s->rmem.release();
         s->raster = Raster();
+        s->rmem2.release();
+        s->raster2 = Raster();
         return err;
     }
     s->r_entries = e;
@@ -234,7 +265,7 @@ int gsc_server_create(gsc_ctx* ctx, int64_t budget_bytes, void* stream, gsc_serv
 
 void gsc_server_destroy(gsc_server* s) {
     if (!s) return;
-    (void)hipStreamSynchronize(s->st);
+    (void)server_sync(s);
     // completion host functions may still be returning on the runtime's thread
     for (int spin = 0; spin < 100000; ++spin) {
         {
@@ -247,7 +278,14 @@ void gsc_server_destroy(gsc_server* s) {
     for (auto& v : s->viewers)
         if (v) v->mem.release();
     s->rmem.release();
+    s->rmem2.release();
     for (BatchReport* r : s->all_reports) (void)hipHostFree(r);
+    for (int i = 0; i < 2; ++i) {
+        if (s->front_done[i]) (void)hipEventDestroy(s->front_done[i]);
+        if (s->blend_done[i]) (void)hipEventDestroy(s->blend_done[i]);
+        if (s->copies_done[i]) (void)hipEventDestroy(s->copies_done[i]);
+    }
+    if (s->blend_st) (void)hipStreamDestroy(s->blend_st);
     delete s;
 }
 
@@ -255,14 +293,14 @@ const char* gsc_server_last_error(const gsc_server* s) { return s ? s->err.c_str
 
 int64_t gsc_server_viewer_bytes(gsc_server* s, int32_t max_width, int32_t max_height) {
     if (!s || max_width < 1 || max_height < 1 || max_width > 16384 || max_height > 16384) return GSC_E_INVALID_ARG;
-    return (int64_t)viewer_bytes_of(s->ctx, max_width, max_height);
+    return (int64_t)viewer_bytes_of(s->ctx, max_width, max_height, s->overlap ? 2 : 1);
 }
 
 int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height) {
     if (!s) return GSC_E_INVALID_ARG;
     if (max_width < 1 || max_height < 1 || max_width > 16384 || max_height > 16384)
         return sfail(s, GSC_E_INVALID_ARG, "gsc_server_admit: image size out of range");
-    const size_t bytes = viewer_bytes_of(s->ctx, max_width, max_height);
+    const size_t bytes = viewer_bytes_of(s->ctx, max_width, max_height, s->overlap ? 2 : 1);
     if (s->used + bytes > (size_t)s->budget)
         return sfail(s, GSC_E_BUDGET, "gsc_server_admit: viewer does not fit the device-memory budget now");
     int32_t id = -1;
@@ -282,7 +320,7 @@ int gsc_server_admit(gsc_server* s, int32_t max_width, int32_t max_height) {
     v->bytes = bytes;
     viewer_share(s->ctx, max_width, max_height, v->entries, v->pairs, v->tiles);
     const gsc_ctx* c = s->ctx;
-    if (hipStreamSynchronize(s->st) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_admit: stream failed");
+    if (server_sync(s) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_admit: stream failed");
     if (alloc_view(v->mem, v->v, c->scene.n, viewer_cache_lines(c), c->scene.k) != hipSuccess) {
         v->mem.release();
         return sfail(s, GSC_E_OOM, "gsc_server_admit: device allocation");
@@ -410,7 +448,7 @@ int gsc_server_step(gsc_server* s) {
         DeriveArgs a;
         a.sc = &c->scene;
         a.v = &v.v;
-        a.cam = derive_cam(r.unified, c->scene.d_ref);
+        a.cam = derive_cam(r.unified, c->scene.d_ref, (c->cfg.flags & GSC_FLAG_LOD_FADE) != 0);
         a.precision = c->cfg.precision;
         a.flags = c->cfg.flags;
         a.d_max = c->cfg.d_max;
@@ -434,6 +472,7 @@ int gsc_server_step(gsc_server* s) {
             sg.anchor_pos = c->scene.posr; sg.line_anchor = direct ? nullptr : v.v.line_anchor; sg.k = c->scene.k;
             sg.G = v.v.G; sg.nG = &v.v.cnt->n_gauss; sg.nG_host = 0;
             seg_camera(sg, r.eye[eye]);
+            if (c->cfg.flags & GSC_FLAG_LOD_FADE) seg_lod_fade(sg, c->scene, r.unified);
             sg.tile_base = tiles;
             tiles += sg.ntx * sg.nty;
             sg.out_rgb = r.out[eye];
@@ -444,16 +483,36 @@ int gsc_server_step(gsc_server* s) {
             return abort_batch(s, b, "gsc_server_step: counter copy");
     }
     tab.total_tiles = tiles;
-    hipError_t e = raster_batch(tab, s->raster, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, false, s->st);
+    // two batches in flight: this batch's raster set was last read by the
+    // blend two batches back, which must finish before the preprocess
+    // rewrites it; this batch's blend then runs on the blend stream
+    const int set = s->overlap ? (int)(s->nbatch & 1) : 0;
+    Raster& R = set ? s->raster2 : s->raster;
+    hipError_t e = hipSuccess;
+    if (s->overlap && s->blend_pending[set]) e = hipStreamWaitEvent(s->st, s->blend_done[set], 0);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&rep->rc, s->raster.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost, s->st);
+        e = raster_batch(tab, R, (c->cfg.flags & GSC_FLAG_FULL_KEY_SORT) != 0, false, s->st, nullptr,
+                         s->overlap ? s->blend_st : nullptr, s->overlap ? s->front_done[set] : nullptr);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&rep->rc, R.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost, s->st);
+    hipStream_t done_st = s->st;
+    if (e == hipSuccess && s->overlap) {
+        // completion after the blend and after the counter copies on the
+        // server's stream
+        e = hipEventRecord(s->blend_done[set], s->blend_st);
+        if (e == hipSuccess) s->blend_pending[set] = true;
+        if (e == hipSuccess) e = hipEventRecord(s->copies_done[set], s->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->blend_st, s->copies_done[set], 0);
+        done_st = s->blend_st;
+    }
     if (e != hipSuccess) return abort_batch(s, b, std::string("gsc_server_step: raster: ") + hipGetErrorString(e));
+    s->nbatch += 1;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->in_flight += 1;
     }
     const int launched = (int)b->ids.size();
-    e = hipLaunchHostFunc(s->st, on_batch_done, b);
+    e = hipLaunchHostFunc(done_st, on_batch_done, b);
     if (e != hipSuccess) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -489,6 +548,25 @@ int gsc_server_policy(gsc_server* s, double pose_m, double pose_rad, double time
     return GSC_OK;
 }
 
+int gsc_server_overlap(gsc_server* s, int enable) {
+    if (!s) return GSC_E_INVALID_ARG;
+    for (auto& v : s->viewers)
+        if (v) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_overlap: set before admitting viewers");
+    if (server_sync(s) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_overlap: stream failed");
+    if (enable && !s->blend_st) {
+        if (hipStreamCreateWithFlags(&s->blend_st, hipStreamNonBlocking) != hipSuccess)
+            return sfail(s, GSC_E_HIP, "gsc_server_overlap: stream creation");
+        for (int i = 0; i < 2; ++i)
+            if (hipEventCreateWithFlags(&s->front_done[i], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s->blend_done[i], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s->copies_done[i], hipEventDisableTiming) != hipSuccess)
+                return sfail(s, GSC_E_HIP, "gsc_server_overlap: event creation");
+    }
+    s->overlap = enable != 0;
+    s->nbatch = 0;
+    return GSC_OK;
+}
+
 int gsc_server_pending(gsc_server* s) {
     if (!s) return GSC_E_INVALID_ARG;
     int64_t q = 0;
@@ -503,7 +581,7 @@ int gsc_server_leave(gsc_server* s, int32_t viewer) {
     Viewer* v = viewer_at(s, viewer);
     if (!v) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_leave: no such viewer");
     if (!v->queue.empty()) return sfail(s, GSC_E_INVALID_ARG, "gsc_server_leave: viewer has queued requests");
-    if (hipStreamSynchronize(s->st) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_leave: stream failed");
+    if (server_sync(s) != hipSuccess) return sfail(s, GSC_E_HIP, "gsc_server_leave: stream failed");
     s->used -= v->bytes;
     v->mem.release();
     s->viewers[viewer].reset();

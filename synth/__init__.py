@@ -300,6 +300,28 @@ def city_walk(frames: int = 600, seed: int = 1, start=(-500.0, -500.0, 10.0), ya
     return out
 
 
+def city_staged_walk(frames: int = 300, start=(-500.0, -500.0, 30.0), yaw0: float = 45.0, pitch: float = -15.0,
+                     stages=((0.2, 0.3), (1.0, 3.0), (3.0, 10.0)), width=CITY_W, height=CITY_H):
+    """Walk in equal stages of constant speed, each (step m, yaw turn deg)
+    per frame: slow, medium, fast (staged speed changes).  The update rate of
+    the cache rises from stage to stage."""
+    p = np.array(start, np.float64)
+    yaw = float(yaw0)
+    fovx = CITY_FOVX
+    fovy = 2.0 * math.atan(math.tan(fovx / 2.0) * height / width)
+    out = []
+    for i in range(frames):
+        step, turn = stages[min(len(stages) - 1, i * len(stages) // frames)]
+        fwd = np.array([math.cos(math.radians(pitch)) * math.cos(math.radians(yaw)),
+                        math.cos(math.radians(pitch)) * math.sin(math.radians(yaw)),
+                        math.sin(math.radians(pitch))])
+        out.append(stereo_pair(p.copy(), fwd, (0.0, 0.0, 1.0), width, height, fovx, fovy))
+        p[0] += step * math.cos(math.radians(yaw))
+        p[1] += step * math.sin(math.radians(yaw))
+        yaw += turn
+    return out
+
+
 SERVING_RESOLUTIONS = ((1280, 720), (2048, 1080), (2560, 1440))
 
 

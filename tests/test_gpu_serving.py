@@ -7,7 +7,12 @@
   * admission against the device-memory budget: refused when it does not
     fit, admitted after a viewer leaves;
   * completion times come after submission; a batch that runs out of cache
-    lines reports GSC_E_CAPACITY for its requests.
+    lines reports GSC_E_CAPACITY for its requests;
+  * a mixed batch on the city scene at the serving resolutions (1280x720,
+    2048x1080 and 2560x1440 per eye, each viewer on its own walk and cache),
+    two batches in flight, against the FP64 oracle with its cache model,
+    every frame and eye;
+  * with two batches in flight the images are the same as with one.
 """
 import math
 import time
@@ -15,7 +20,9 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import synth
+from parity import assert_image
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -50,11 +57,14 @@ def scene_renderer(gs, scene, **kw):
     return r
 
 
-def serve(gs, scene_r, viewers, budget=1 << 34, order="interleaved"):
+def serve(gs, scene_r, viewers, budget=1 << 34, order="interleaved", overlap=False):
     """viewers: list of (W, H, frames). Submits every frame (interleaved over
     viewers, arrival times increasing), steps until all complete; returns the
-    images per viewer and the completion records."""
+    images per viewer and the completion records.  overlap: two batches in
+    flight."""
     srv = gs.Server(scene_r, budget)
+    if overlap:
+        srv.overlap(True)
     ids, outs, arrive = [], [], {}
     for W, H, _ in viewers:
         vid = srv.admit(W, H)
@@ -88,14 +98,15 @@ def serve(gs, scene_r, viewers, budget=1 << 34, order="interleaved"):
     return outs, done, arrive, req
 
 
-def test_alone_equals_mix_equals_single_viewer_path(gs, tiny):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_alone_equals_mix_equals_single_viewer_path(gs, tiny, overlap):
     torch.cuda.set_device(0)
     viewers = [(W, H, walk(6, W, H, seed=10 + i)) for i, (W, H) in enumerate(SIZES[:3])]
     base = scene_renderer(gs, tiny)
-    mixed, done, arrive, req = serve(gs, base, viewers)
+    mixed, done, arrive, req = serve(gs, base, viewers, overlap=overlap)
     assert all(s == 0 for _, _, s in done)
     for i, v in enumerate(viewers):
-        alone, d1, _, _ = serve(gs, base, [v])
+        alone, d1, _, _ = serve(gs, base, [v], overlap=overlap)
         assert all(s == 0 for _, _, s in d1)
         ref = scene_renderer(gs, tiny)
         W, H, frames = v
@@ -110,10 +121,11 @@ def test_alone_equals_mix_equals_single_viewer_path(gs, tiny):
             assert float(mixed[i][t][0].min()) >= 0.0  # every pixel written
 
 
-def test_more_viewers_than_a_batch(gs, tiny):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_more_viewers_than_a_batch(gs, tiny, overlap):
     viewers = [(SIZES[i % 4][0], SIZES[i % 4][1], walk(3, *SIZES[i % 4], seed=40 + i)) for i in range(11)]
     base = scene_renderer(gs, tiny)
-    outs, done, arrive, req = serve(gs, base, viewers)
+    outs, done, arrive, req = serve(gs, base, viewers, overlap=overlap)
     assert len(done) == sum(len(f) for _, _, f in viewers)
     assert all(s == 0 for _, _, s in done)
     for rid, t, s in done:
@@ -136,6 +148,11 @@ def test_budget_admission(gs, tiny):
     probe = gs.Server(base, 1 << 40)
     vb = probe.viewer_bytes(128, 96)
     assert vb > 0 and probe.viewer_bytes(160, 112) >= vb
+    probe.overlap(True)                    # two raster sets: a larger share per viewer
+    assert probe.viewer_bytes(128, 96) > vb
+    probe.admit(128, 96)
+    with pytest.raises(gs.GscError):       # only before viewers are admitted
+        probe.overlap(False)
     probe.close()
     srv = gs.Server(base, int(1.5 * vb))
     a = srv.admit(128, 96)
@@ -169,3 +186,23 @@ def test_capacity_overflow_reported(gs, tiny):
     (W, H) = SIZES[0]
     outs, done, _, _ = serve(gs, base, [(W, H, walk(2, W, H, seed=5))])
     assert [s for _, _, s in done] == [gs.GSC_E_CAPACITY] * 2
+
+
+def test_mixed_city_batch_matches_oracle(gs):
+    city = synth.city_scene()
+    base = gs.Renderer(k=city.k, reuse=True, max_width=2560, max_height=1440)
+    base.load(city)
+    viewers = [(W, H, synth.city_walk(3, seed=100 + i, start=(-500.0 + 150.0 * i, -520.0 + 90.0 * i, 10.0 + 6.0 * i),
+                                      width=W, height=H))
+               for i, (W, H) in enumerate(synth.SERVING_RESOLUTIONS)]
+    outs, done, _, _ = serve(gs, base, viewers, budget=64 << 30, overlap=True)  # the serving config's budget
+    base.close()
+    assert all(s == 0 for _, _, s in done)
+    for i, (W, H, frames) in enumerate(viewers):
+        sim = oracle.CacheSim(city.n, city.n, 10)
+        lines = {}
+        for t, (L, R) in enumerate(frames):
+            ref = oracle.render_frame(city, L, R, cache=sim, cache_lines=lines)
+            for eye, key in ((0, "left"), (1, "right")):
+                rep = assert_image(outs[i][t][eye].cpu().numpy(), ref[key])
+                print("\nviewer %d (%dx%d) frame %d %s: %s" % (i, W, H, t, key, rep))

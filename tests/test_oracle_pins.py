@@ -213,3 +213,89 @@ def test_compose_hand_built_table():
     assert G.tolist() == [0, 7, 8, 9, 10]
     assert oracle.compose(0, 3, np.zeros(0)).tolist() == []
     assert oracle.compose(2, 1, np.array([-1.0, -2.0])).tolist() == []
+
+
+# ---------------------------------------------------------------- float32 position bands
+# A decision of the tile test or of the pixel alpha threshold is marginal
+# when its margin in q is within what a float32 screen position allows: two
+# float32 ulps of |mx| + |my| + W + H times |grad q| (bounded by
+# 2 sqrt(q (a + c))), on top of the 1e-5 relative band of the tile test and
+# the 1e-7 alpha band of the pixel test.  Pinned by the same geometry placed
+# near the image origin and near x = 2000 px: the same margin is decided in
+# the first case and marginal in the second.
+
+def _one_gaussian(mx, my, alpha, W, H):
+    pre = {"mean2d": np.array([[mx, my]], np.float64), "conic": np.array([[1.0, 0.0, 1.0]]),
+           "sigma2d": np.array([[1.0, 0.0, 1.0]]), "keep": np.ones(1, np.uint8)}
+    return pre, np.array([alpha])
+
+
+@pytest.mark.parametrize("x_tile,W,marginal", [(1, 64, False), (125, 2048, True)])
+def test_tile_band_grows_with_the_screen_coordinate(x_tile, W, marginal):
+    alpha = 0.5
+    tau = 2.0 * math.log(255.0 * alpha)
+    margin = 2e-3                      # q at tile (x_tile, 0) is tau - margin: listed
+    x0 = 16 * x_tile + 0.5             # left pixel-centre column of the tile
+    mx = x0 - math.sqrt(tau - margin)
+    pre, al = _one_gaussian(mx, 8.0, alpha, W, 64)
+    tile, g, fl = oracle.tile_pairs(pre, al, W, 64)
+    row0 = {int(t): int(f) for t, f in zip(tile, fl) if t < W // 16}
+    assert row0[x_tile] & 1 == 1                         # listed
+    assert bool(row0[x_tile] & 2) == marginal
+    delta = 2.0 ** -23 * (abs(mx) + 8.0 + W + 64)
+    band = 1e-5 * (tau + 1.0) + 2.0 * math.sqrt(tau * 2.0) * delta
+    assert (margin <= band) == marginal
+
+
+@pytest.mark.parametrize("px,W,marginal", [(20, 64, False), (2000, 2048, True)])
+def test_pixel_alpha_band_grows_with_the_screen_coordinate(px, W, marginal):
+    # one Gaussian whose alpha at the pixel centre (px + 0.5, 8.5) is 1/255
+    # times (1 + 1e-3): composited by the exact arithmetic
+    alpha = 0.5
+    a_px = (1.0 / 255.0) * (1.0 + 1e-3)
+    q = 2.0 * math.log(alpha / a_px)
+    mx = px + 0.5 - math.sqrt(q)
+    pre, al = _one_gaussian(mx, 8.5, alpha, W, 16)
+    pre["depth"] = np.array([5.0])
+    ntiles = (W // 16) * 1
+    t = px // 16
+    starts = np.zeros(ntiles, np.int64); ends = np.zeros(ntiles, np.int64)
+    ends[t] = 1
+    starts[t + 1:] = 1; ends[t + 1:] = 1
+    img, T, nc, band, ne = oracle.blend(W, 16, starts, ends, np.array([0], np.int32), pre, al,
+                                        np.array([[1.0, 1.0, 1.0]]))
+    assert nc[8, px] == 1 and abs(img[0, 8, px] - a_px) < 1e-15
+    assert bool(band[8, px]) == marginal
+    da = a_px * math.sqrt(q * 2.0) * 2.0 ** -23 * (abs(mx) + 8.5 + W + 16)
+    assert (a_px - 1.0 / 255.0 < 1e-7 + da) == marginal
+
+
+def test_marginal_pair_left_out_flags_the_pixels_it_reaches():
+    """A Gaussian whose minimum q over a tile exceeds its threshold by less
+    than the tile test's band is left out of that tile, but the other side
+    may list it and composite it where its alpha reaches 1/255: the pixel at
+    the minimum is flagged, a pixel where q is well above the threshold is
+    not, and neither image value changes."""
+    alpha = 0.5
+    tau = 2.0 * math.log(255.0 * alpha)
+    W, H = 64, 16
+    x0 = 16 * 1 + 0.5                           # tile (1, 0): pixel centres from x = 16.5
+    mx = x0 - math.sqrt(tau + 1e-6)             # min q over the tile = tau + 1e-6 (in band, unlisted)
+    pre, al = _one_gaussian(mx, 8.5, alpha, W, H)
+    pre["depth"] = np.array([5.0])
+    tile, g, fl = oracle.tile_pairs(pre, al, W, H)
+    fl_t = {int(t): int(f) for t, f in zip(tile, fl)}
+    assert fl_t[1] == 2                          # marginal, not listed
+    listed = (fl & 1) == 1
+    ntiles = W // 16
+    s, e = oracle.tile_ranges(tile[listed], ntiles)
+    order = np.argsort(tile[listed], kind="stable")
+    sg = g[listed][order]
+    gs_, ge_ = oracle.tile_ranges(tile[fl == 2], ntiles)
+    img0, _, _, band0, _ = oracle.blend(W, H, s, e, sg, pre, al, np.array([[1.0, 1.0, 1.0]]))
+    img1, _, _, band1, _ = oracle.blend(W, H, s, e, sg, pre, al, np.array([[1.0, 1.0, 1.0]]),
+                                        ghosts=(gs_, ge_, g[fl == 2].astype(np.int32)))
+    assert np.array_equal(img0, img1)
+    assert band1[8, 16] == 1 and band0[8, 16] == 0    # the pixel at the minimum
+    assert band1[8, 31] == 0                          # q far above the threshold
+    assert band1[0, 16] == 0                          # q above by (8 px)^2 * c
