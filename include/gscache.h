@@ -216,6 +216,29 @@ int gsc_render_stereo(gsc_ctx* ctx, float* left_chw, float* right_chw, float* le
 int gsc_render_gaussians(gsc_ctx* ctx, const gsc_gaussians* g, const gsc_camera* cam, float* out_chw,
                          float* out_T, int32_t* out_ncontrib);
 
+/* Allocation-free variant of gsc_render_gaussians, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  No context: the intermediate buffers
+ * (the Gaussians' staged copy, per-Gaussian records, sort keys, tile pairs,
+ * ranges, counters) live in one static device array of the library (48 MiB,
+ * held by each device that loads the library until the process ends), and
+ * the call allocates nothing.  Same kernels and results as
+ * gsc_render_gaussians (depth pre-sorted pairs, no work counting).
+ * g: device arrays as for gsc_render_gaussians, n <= GSC_NOALLOC_MAX_GAUSSIANS;
+ * cam: host, width and height <= GSC_NOALLOC_MAX_SIDE; out_chw [3,H,W] and
+ * out_T [H,W] (may be NULL): caller-owned device float32; status (device,
+ * may be NULL) receives the overflow bits after the kernels run (0, or bit0
+ * when more than GSC_NOALLOC_MAX_PAIRS tile pairs were needed and the excess
+ * dropped).  stream: hipStream_t (NULL = default stream); asynchronous.
+ * Sizes beyond the maxima return GSC_E_INVALID_ARG before any device work.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (other streams, other host threads) race. */
+#define GSC_NOALLOC_MAX_GAUSSIANS 65536
+#define GSC_NOALLOC_MAX_PAIRS (1 << 21)
+#define GSC_NOALLOC_MAX_SIDE 2048
+int gsc_render_gaussians_noalloc(const gsc_gaussians* g, const gsc_camera* cam, float* out_chw, float* out_T,
+                                 int32_t* status, void* stream);
+
 /* Wait for the stream, then report GSC_E_CAPACITY if the last frame
  * overflowed a capacity, else GSC_OK. */
 int gsc_sync(gsc_ctx* ctx);

@@ -86,6 +86,7 @@ SYMBOLS = {
     "gsc_derive": ([C.c_void_p], C.c_int),
     "gsc_render_stereo": ([C.c_void_p] * 5, C.c_int),
     "gsc_render_gaussians": ([C.c_void_p] * 6, C.c_int),
+    "gsc_render_gaussians_noalloc": ([C.c_void_p] * 6, C.c_int),
     "gsc_sync": ([C.c_void_p], C.c_int),
     "gsc_get_stats": ([C.c_void_p, C.c_void_p], C.c_int),
     "gsc_reset_cache": ([C.c_void_p], C.c_int),
@@ -135,6 +136,27 @@ def lib():
             f.restype = res
         _lib = L
     return _lib
+
+
+NOALLOC_MAX_GAUSSIANS, NOALLOC_MAX_PAIRS, NOALLOC_MAX_SIDE = 65536, 1 << 21, 2048
+
+
+def render_gaussians_noalloc(mu, cov, rgb, alpha, cam: dict, out, T=None, status=None, stream=None):
+    """gsc_render_gaussians_noalloc: the raster-only render of explicit
+    Gaussians on the library's static device buffer (no allocation, no
+    context); `status` (int32 device tensor, optional) receives the overflow
+    bits.  Asynchronous on `stream` (default: torch's current stream)."""
+    g = Gaussians()
+    g.n = int(alpha.shape[0])
+    for t in (mu, cov, rgb, alpha):
+        assert t.is_cuda and t.is_contiguous() and t.dtype.itemsize == 4
+    g.mu, g.cov, g.rgb, g.alpha = mu.data_ptr(), cov.data_ptr(), rgb.data_ptr(), alpha.data_ptr()
+    c = camera(cam)
+    st = stream if stream is not None else _current_stream()
+    L = lib()
+    rc = L.gsc_render_gaussians_noalloc(C.byref(g), C.byref(c), _ptr(out), _ptr(T), _ptr(status), st)
+    if rc != GSC_OK:
+        raise GscError(rc, (L.gsc_last_error(None) or b"").decode())
 
 
 def camera(cam: dict) -> Camera:

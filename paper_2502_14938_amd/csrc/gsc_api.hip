@@ -37,6 +37,8 @@ int hip_fail(gsc_ctx* c, hipError_t e, const char* where) {
 
 namespace gsc {
 
+int global_fail(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+
 // --------------------------------------------------------- unified camera
 // Binocular stereo de-redundancy (Section 4, eqs. 5-6), in double precision.
 
@@ -166,28 +168,6 @@ hipError_t view_layout(View& v, int64_t n, int64_t C, int k, Fn&& A) {
     return hipSuccess;
 }
 
-// Buffers of one raster batch.
-template <class Fn>
-hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key, Fn&& A) {
-    hipError_t e;
-#define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
-    A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
-    A_(r.big_list, max_entries); A_(r.tall_cnt, max_entries / 256 + 1); A_(r.tall_off, max_entries / 256 + 1);
-    A_(r.tall_list, max_entries);
-    A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
-    A_(r.pt_dense, max_entries); A_(r.pt_rowcnt, max_entries); A_(r.pt_rowoff, max_entries);
-    A_(r.spans, 2 * max_entries); A_(r.rowmap, 2 * max_entries);
-    A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
-    A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
-    A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
-    if (full_key) { A_(r.pkey64[0], max_pairs); A_(r.pkey64[1], max_pairs); }
-    A_(r.ranges, 2 * max_tiles); A_(r.tile_eval, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks);
-    A_(r.block_sums, kScanBlocks);
-    A_(r.n_sort, 1); A_(r.cnt, 1);
-#undef A_
-    return hipSuccess;
-}
-
 struct ByteCounter {
     size_t bytes = 0;
     template <typename T>
@@ -267,6 +247,15 @@ __global__ void k_pack_explicit(const float* __restrict__ mu, const float* __res
     }
 }
 
+hipError_t pack_explicit(const gsc_gaussians& g, float4* L0, float4* L1, float4* L2, float* L3, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    int64_t blocks = (g.n + 255) / 256;
+    if (blocks > kGridBlocks) blocks = kGridBlocks;
+    hipLaunchKernelGGL(k_pack_explicit, dim3((unsigned)blocks), dim3(256), 0, st, g.mu, g.cov, g.rgb, g.alpha, g.n,
+                       L0, L1, L2, L3);
+    return hipGetLastError();
+}
+
 hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles) {
     int64_t need = g.n > 1 ? g.n : 1;
     if (c->xg_cap < need || c->xraster.max_tiles < ntiles) {
@@ -288,13 +277,7 @@ hipError_t explicit_gaussians(gsc_ctx* c, const gsc_gaussians& g, int64_t ntiles
         }
         c->xg_cap = cap;
     }
-    if (g.n > 0) {
-        int64_t blocks = (g.n + 255) / 256;
-        if (blocks > kGridBlocks) blocks = kGridBlocks;
-        hipLaunchKernelGGL(k_pack_explicit, dim3((unsigned)blocks), dim3(256), 0, c->stream, g.mu, g.cov, g.rgb,
-                           g.alpha, g.n, c->xg.L0, c->xg.L1, c->xg.L2, c->xg.L3);
-    }
-    return hipGetLastError();
+    return pack_explicit(g, c->xg.L0, c->xg.L1, c->xg.L2, c->xg.L3, c->stream);
 }
 
 // Event set of the frame being issued (nullptr when timing is off).

@@ -40,6 +40,33 @@ inline hipError_t halloc(AllocSet& set, T** p, int64_t count) {
     return e;
 }
 
+// Buffers of one raster batch.
+template <class Fn>
+hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key, Fn&& A) {
+    hipError_t e;
+#define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
+    A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
+    A_(r.big_list, max_entries); A_(r.tall_cnt, max_entries / 256 + 1); A_(r.tall_off, max_entries / 256 + 1);
+    A_(r.tall_list, max_entries);
+    A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
+    A_(r.pt_dense, max_entries); A_(r.pt_rowcnt, max_entries); A_(r.pt_rowoff, max_entries);
+    A_(r.spans, 2 * max_entries); A_(r.rowmap, 2 * max_entries);
+    A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
+    A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
+    A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
+    if (full_key) { A_(r.pkey64[0], max_pairs); A_(r.pkey64[1], max_pairs); }
+    A_(r.ranges, 2 * max_tiles); A_(r.tile_eval, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks);
+    A_(r.block_sums, kScanBlocks);
+    A_(r.n_sort, 1); A_(r.cnt, 1);
+#undef A_
+    return hipSuccess;
+}
+
+// Explicit Gaussians (public arrays) into the four line arrays, on st.
+hipError_t pack_explicit(const gsc_gaussians& g, float4* L0, float4* L1, float4* L2, float* L3, hipStream_t st);
+// Set the thread's context-free error message (gsc_last_error(NULL)).
+int global_fail(int code, const std::string& msg);
+
 // Exact device bytes alloc_view / alloc_raster will take (admission planning).
 size_t view_bytes(int64_t n, int64_t C, int k);
 size_t raster_bytes(int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key);

@@ -89,3 +89,30 @@ def test_struct_sizes_match_header():
         got = list(map(int, subprocess.check_output([exe]).split()))
     want = [C.sizeof(x) for x in (gs.Config, gs.Camera, gs.Anchors, gs.Mlp, gs.Gaussians, gs.FrameStats)]
     assert got == want
+
+
+def test_noalloc_entry_rejects_sizes_beyond_its_maxima(L):
+    """The allocation-free entry checks its arguments before any device work
+    (so these run without a GPU); its maxima match the header's."""
+    import paper_2502_14938_amd as gs
+    src = open(HEADER).read()
+    for name, val in (("GSC_NOALLOC_MAX_GAUSSIANS", gs.NOALLOC_MAX_GAUSSIANS),
+                      ("GSC_NOALLOC_MAX_PAIRS", gs.NOALLOC_MAX_PAIRS), ("GSC_NOALLOC_MAX_SIDE", gs.NOALLOC_MAX_SIDE)):
+        m = re.search(r"#define %s \(?([0-9]+)(?: << ([0-9]+))?\)?" % name, src)
+        assert m, name
+        assert (int(m.group(1)) << int(m.group(2) or 0)) == val, name
+    assert L.gsc_render_gaussians_noalloc(None, None, None, None, None, None) == -1
+    g = gs.Gaussians()
+    g.n = gs.NOALLOC_MAX_GAUSSIANS + 1
+    g.mu = g.cov = g.rgb = g.alpha = 16  # never dereferenced: the size check comes first
+    cam = gs.camera({"R": [1, 0, 0, 0, 1, 0, 0, 0, 1], "pos": [0, 0, 0], "fovx": 1.0, "fovy": 1.0, "width": 64,
+                     "height": 64, "znear": 0.2})
+    out = C.c_void_p(16)
+    assert L.gsc_render_gaussians_noalloc(C.byref(g), C.byref(cam), out, None, None, None) == -1
+    assert b"GSC_NOALLOC_MAX_GAUSSIANS" in L.gsc_last_error(None)
+    g.n = -1
+    assert L.gsc_render_gaussians_noalloc(C.byref(g), C.byref(cam), out, None, None, None) == -1
+    g.n = 10
+    cam.width = gs.NOALLOC_MAX_SIDE + 1
+    assert L.gsc_render_gaussians_noalloc(C.byref(g), C.byref(cam), out, None, None, None) == -1
+    assert b"GSC_NOALLOC_MAX_SIDE" in L.gsc_last_error(None)
