@@ -530,6 +530,7 @@ int gsc_render_stereo(gsc_ctx* c, float* left_chw, float* right_chw, float* left
     SegTable tab;
     std::memset(&tab, 0, sizeof(tab));
     tab.n = 2;
+    tab.paired = c->nviews == 1 ? 1 : 0;  // both eyes read one view's buffer
     int tiles = 0;
     float* outs[2] = {left_chw, right_chw};
     float* Ts[2] = {left_T, right_T};
@@ -889,9 +890,10 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
                 for (int64_t i = 0; i < m; ++i) val[i] = val[i] < (uint32_t)ne ? ord[val[i]] : 0xffffffffu;
             }
             int32_t* o = (int32_t*)dst;
+            const uint32_t stride = r.entry_stride > 1 ? (uint32_t)r.entry_stride : 1u;
             for (int64_t i = 0; i < m; ++i) {
                 o[2 * i] = tile_of[i];
-                o[2 * i + 1] = (int32_t)(val[i] - (uint32_t)r.entry_base[eye]);
+                o[2 * i + 1] = (int32_t)((val[i] - (uint32_t)r.entry_base[eye]) / stride);
             }
             (void)total;
             break;
@@ -921,19 +923,27 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
         case GSC_DBG_PREPROC: {
             if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
             if (eye >= c->last_tab.n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: no such eye");
-            int64_t b0 = r.entry_base[eye], b1 = r.entry_base[eye + 1];
-            count = b1 - b0;
+            // the eye's entries: from entry_base[eye] with the layout's stride
+            const int64_t stride = r.entry_stride > 1 ? r.entry_stride : 1;
+            const int64_t b0 = r.entry_base[eye];
+            if (stride > 1) {  // the pair (eye & ~1, eye | 1) holds 2 entries per Gaussian
+                const int q = eye & ~1;
+                count = (r.entry_base[q + 2] - r.entry_base[q]) / 2;
+            } else {
+                count = r.entry_base[eye + 1] - b0;
+            }
             int64_t m = count < cap ? count : cap;
             if (m <= 0) break;
-            std::vector<float4> rr(4 * m);
-            std::vector<uint32_t> nt(m);
-            HIP_OR_FAIL(c, hipMemcpy(rr.data(), R.rec + 4 * b0, m * 64, hipMemcpyDeviceToHost));
-            HIP_OR_FAIL(c, hipMemcpy(nt.data(), R.ntiles + b0, m * 4, hipMemcpyDeviceToHost));
+            const int64_t span = (m - 1) * stride + 1;
+            std::vector<float4> rr(4 * span);
+            std::vector<uint32_t> nt(span);
+            HIP_OR_FAIL(c, hipMemcpy(rr.data(), R.rec + 4 * b0, span * 64, hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(c, hipMemcpy(nt.data(), R.ntiles + b0, span * 4, hipMemcpyDeviceToHost));
             float* o = (float*)dst;
             for (int64_t i = 0; i < m; ++i) {
-                const float4& A = rr[4 * i];
-                const float4& B = rr[4 * i + 1];
-                float row[8] = {A.x, A.y, A.z, A.w, B.x, B.y, 0.f, (float)nt[i]};
+                const float4& A = rr[4 * i * stride];
+                const float4& B = rr[4 * i * stride + 1];
+                float row[8] = {A.x, A.y, A.z, A.w, B.x, B.y, 0.f, (float)nt[i * stride]};
                 std::memcpy(o + 8 * i, row, sizeof(row));
             }
             break;

@@ -48,7 +48,8 @@ struct Counters {
 // Device counters of one raster batch.
 struct RasterCounters {
     int32_t n_entries;            // total (segment, Gaussian) entries
-    int32_t entry_base[kMaxSeg + 1];
+    int32_t entry_base[kMaxSeg + 1];  // entry of Gaussian 0 of each segment (total last)
+    int32_t entry_stride;             // 2 with paired segments, else 1
     int32_t n_pairs;              // total tile pairs (all segments)
     int32_t n_chunks;             // chunks of 256 depth ranks (tall-entry lists)
     int32_t n_tall;               // tall entries (more than 4 tile rows) with tiles
@@ -86,9 +87,15 @@ struct Seg {
     float d_ref;
 };
 
+// paired: segments 2p and 2p+1 are the two eyes of one view (the same render
+// buffer and cache lines), and their entries interleave, entry = base_p +
+// 2 g + eye, so both eyes of a Gaussian are projected by neighbouring lanes
+// from one read of its line; otherwise segment q's entries are contiguous.
 struct SegTable {
     int32_t n;
     int32_t total_tiles;
+    int32_t paired;
+    int32_t pad;
     Seg s[kMaxSeg];
 };
 

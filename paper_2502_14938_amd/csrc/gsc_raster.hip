@@ -36,18 +36,45 @@ __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * block
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
 
-// Segment -> first entry, from the segments' device counts (every block of
-// k_preprocess computes it; block 0 publishes it for the later kernels).
+// Segment -> entry of its Gaussian 0, from the segments' device counts
+// (every block of k_preprocess computes it; block 0 publishes it for the
+// later kernels); base[n] is the total.  Paired segments interleave: the
+// pair's base, +1 for the second eye, stride 2.
+__device__ __forceinline__ int32_t seg_count(const Seg& s) { return s.nG ? *s.nG : s.nG_host; }
+
 __device__ __forceinline__ int32_t entry_bases(const SegTable& tab, int64_t max_entries, int32_t* base,
                                                bool& over) {
     int32_t acc = 0;
-    for (int q = 0; q < tab.n; ++q) {
-        base[q] = acc;
-        acc += tab.s[q].nG ? *tab.s[q].nG : tab.s[q].nG_host;
+    if (tab.paired) {
+        for (int q = 0; q + 1 < tab.n; q += 2) {
+            base[q] = acc;
+            base[q + 1] = acc + 1;
+            acc += 2 * seg_count(tab.s[q]);
+        }
+    } else {
+        for (int q = 0; q < tab.n; ++q) {
+            base[q] = acc;
+            acc += seg_count(tab.s[q]);
+        }
     }
     base[tab.n] = acc;
     over = acc > max_entries;
     return over ? (int32_t)max_entries : acc;
+}
+
+// Entry e -> (segment si, Gaussian g of that segment).
+__device__ __forceinline__ void locate_entry(const SegTable& tab, const int32_t* base, int64_t e, int& si,
+                                             int64_t& g) {
+    si = 0;
+    if (tab.paired) {
+        while (si + 2 < tab.n && e >= base[si + 2]) si += 2;
+        const int64_t off = e - base[si];
+        si += (int)(off & 1);
+        g = off >> 1;
+    } else {
+        while (si + 1 < tab.n && e >= base[si + 1]) ++si;
+        g = e - base[si];
+    }
 }
 
 // Minimum of q(d) = a dx^2 + 2 b dx dy + c dy^2 over the closed rectangle
@@ -240,6 +267,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         s_ne = entry_bases(p.tab, p.max_entries, s_base, over);
         if (blockIdx.x == 0) {  // this batch's counters, for the later kernels
             for (int q = 0; q <= p.tab.n; ++q) p.rc->entry_base[q] = s_base[q];
+            p.rc->entry_stride = p.tab.paired ? 2 : 1;
             p.rc->overflow = over ? 2 : 0;
             p.rc->n_entries = s_ne;
             p.rc->n_echunks = (s_ne + NT - 1) / NT;
@@ -263,9 +291,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         int y0 = 0, y1 = -1;
         uint32_t spans[kSmallRows] = {0xffffu, 0xffffu, 0xffffu, 0xffffu};
         if (valid) {
-            while (si + 1 < p.tab.n && e >= s_base[si + 1]) ++si;
+            int64_t g;
+            locate_entry(p.tab, s_base, e, si, g);
             const Seg& s = p.tab.s[si];
-            int64_t g = e - s_base[si];
             int64_t src = s.G ? (int64_t)s.G[g] : g;
             float4 l0 = s.L0[src], l1 = s.L1[src], l2 = s.L2[src];
             lb = s.L3[src];

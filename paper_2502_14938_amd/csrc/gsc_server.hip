@@ -440,6 +440,7 @@ int gsc_server_step(gsc_server* s) {
 
     SegTable tab;
     std::memset(&tab, 0, sizeof(tab));
+    tab.paired = 1;  // each viewer's two eyes read its one view
     int tiles = 0;
     for (int i = 0; i < (int)pick.size(); ++i) {
         Viewer& v = *s->viewers[pick[i]];
