@@ -584,6 +584,10 @@ template <bool kFull>
 __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_list) {
     __shared__ uint32_t s_ex[NT / 64][64];     // pairs before each of the wave's current 64 rows
     __shared__ uint32_t s_first[NT / 64][64];  // global tile id of each row's first listed tile
+    __shared__ uint32_t s_out[NT / 64][64];    // output position of each row's first pair (combined rows)
+    __shared__ uint32_t s_lim[NT / 64][64];    // pairs each row may write (combined rows)
+    __shared__ uint32_t s_e[NT / 64][64];      // entry of each row (combined rows)
+    __shared__ uint32_t s_low[NT / 64][64];    // depth bits of each row's entry (combined rows, full keys)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t nb = d.rc->n_tall;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -609,6 +613,54 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
         }
         const int64_t left = (nb - b0 + nwaves - 1) / nwaves;  // entries of this wave from b0 on
         const int ng = left < kTallGroup ? (int)left : kTallGroup;
+        // rows of the group's entries: when they fit one wave, every row of
+        // every entry goes to its own lane and the group's pairs are written
+        // in one pass (most tall footprints are a few tiles wide)
+        const uint32_t nrows = lane < ng ? (mrows >> 16) - (mrows & 0xffff) + 1u : 0u;
+        uint32_t rtot;
+        const uint32_t rbase = wave_excl_scan(nrows, rtot);
+        if (rtot <= 64u) {
+            // lane l: row l of the concatenation; its entry gi is the last
+            // group lane whose first row is <= l
+            int gi = 0;
+#pragma unroll
+            for (int g2 = 1; g2 < kTallGroup; ++g2)
+                if (g2 < ng && (uint32_t)__shfl(rbase, g2, 64) <= (uint32_t)lane) gi = g2;
+            const bool live = (uint32_t)lane < rtot;
+            const uint32_t g_rb = __shfl(rbase, gi, 64), g_rows = __shfl(mrows, gi, 64);
+            const uint32_t g_e = __shfl(me, gi, 64), g_cnt = __shfl(mcnt, gi, 64), g_seg = __shfl(mseg, gi, 64);
+            const uint32_t g_o = __shfl(mo, gi, 64), g_sp0 = __shfl(msp0, gi, 64), g_low = __shfl(mlow, gi, 64);
+            const int ri = lane - (int)g_rb;
+            uint32_t sp = 0xffffu;
+            if (live && (int64_t)g_sp0 + ri < d.span_cap) sp = d.spans[(int64_t)g_sp0 + ri];
+            const int lo = sp & 0xffff, hi = sp >> 16;
+            uint32_t tot;
+            const uint32_t ex = wave_excl_scan(live && hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
+            const uint32_t in_entry = ex - (uint32_t)__shfl(ex, (int)g_rb, 64);  // pairs of the entry before this row
+            const Seg& s = d.tab.s[g_seg];
+            s_ex[w][lane] = ex;
+            s_first[w][lane] = (uint32_t)(s.tile_base + ((int)(g_rows & 0xffff) + ri) * s.ntx + lo);
+            s_out[w][lane] = g_o + in_entry;
+            s_lim[w][lane] = g_cnt > in_entry ? g_cnt - in_entry : 0u;  // pairs the entry's count allows
+            s_e[w][lane] = g_e;
+            s_low[w][lane] = g_low;
+            __builtin_amdgcn_wave_barrier();
+            const int last = (int)rtot - 1;
+            for (uint32_t j = lane; j < tot; j += 64) {
+                int lo2 = 0, hi2 = last;
+                while (lo2 < hi2) {
+                    const int mid = (lo2 + hi2 + 1) >> 1;
+                    if (s_ex[w][mid] <= j) lo2 = mid;
+                    else hi2 = mid - 1;
+                }
+                const uint32_t k = j - s_ex[w][lo2];
+                if (k < s_lim[w][lo2])
+                    put_pair<kFull>(d, (int64_t)s_out[w][lo2] + k, s_first[w][lo2] + k, s_e[w][lo2],
+                                    (uint64_t)s_low[w][lo2]);
+            }
+            __builtin_amdgcn_wave_barrier();  // before the next group overwrites the arrays
+            continue;
+        }
         // the first 64 rows' spans of every entry of the group, loads in flight together
         uint32_t pre[kTallGroup];
 #pragma unroll
