@@ -591,6 +591,13 @@ def run_serving(args):
     launched = completed = 0
     total = sum(len(v["arrivals"]) for v in wl)
     waits_admission = 0
+    host_ms = {"admit": [], "leave": [], "step": []}  # host time inside the server calls
+
+    def timed_call(kind, fn, *a):
+        t = time.perf_counter()
+        r = fn(*a)
+        host_ms[kind].append(1e3 * (time.perf_counter() - t))
+        return r
     t0 = time.monotonic()
     last_progress = t0
     while completed < total:
@@ -599,7 +606,7 @@ def run_serving(args):
         for v in range(nv):
             if vid[v] is None and wl[v]["start"] <= now:
                 W, H = wl[v]["res"]
-                vid[v] = srv.admit(W, H)
+                vid[v] = timed_call("admit", srv.admit, W, H)
                 if vid[v] is None:
                     waits_admission += 1
             if vid[v] is None:
@@ -619,13 +626,13 @@ def run_serving(args):
                     pool[v].append(bufs)
                     completed += 1
                     if nxt[v] == len(arr) and outstanding[v] == 0:
-                        srv.leave(vid[v])
+                        timed_call("leave", srv.leave, vid[v])
                     continue
                 req[rid] = (v, f, t0 + arr[f], bufs)
                 outstanding[v] += 1
         # keep one batch running and one queued behind it
         if launched - completed <= args.viewers:
-            n = srv.step()
+            n = timed_call("step", srv.step)
             launched += n
             busy = busy or n > 0
         for rid, t_done, status in srv.poll(1024):
@@ -641,7 +648,7 @@ def run_serving(args):
             pool[v].append(bufs)
             completed += 1
             if nxt[v] == len(wl[v]["arrivals"]) and outstanding[v] == 0:
-                srv.leave(vid[v])
+                timed_call("leave", srv.leave, vid[v])
         if time.monotonic() - last_progress > 20.0:
             print("serving: %d/%d frames done" % (completed, total), file=sys.stderr, flush=True)
             last_progress = time.monotonic()
@@ -670,6 +677,8 @@ def run_serving(args):
            "served_stereo_frames_per_s": round((total - sum(dropped.values())) / wall, 2),
            "offered_per_s": round(nv * args.rate, 1),
            "wall_s": round(wall, 2), "admission_retries": waits_admission,
+           "host_call_ms": {k: {"calls": len(x), "max": round(max(x), 3) if x else 0.0,
+                                "total": round(sum(x), 1)} for k, x in host_ms.items()},
            "queue_policy": {"timeout_ms": args.queue_timeout_ms, "pose_m": args.queue_pose_m,
                             "pose_deg": args.queue_pose_deg, "ordered": bool(args.queue_ordered)},
            "dropped": dropped}

@@ -204,7 +204,12 @@ hipError_t server_sync(gsc_server* s) {
 }
 
 // Size the batch raster (both sets with two batches in flight) for the
-// admitted viewers (streams must be idle).
+// admitted viewers (streams must be idle).  The sets only grow while
+// viewers remain (a leave keeps them; they go when the last viewer leaves):
+// freeing and re-allocating tens of GB stalls the host for up to ~0.6 s,
+// which the other viewers' queued frames would wait out.  The budget still
+// counts each admitted viewer's share, and the kept size is one the budget
+// allowed when it was allocated.
 hipError_t resize_raster(gsc_server* s) {
     int64_t e = 0, p = 0, t = 0;
     for (auto& v : s->viewers)
@@ -216,6 +221,7 @@ hipError_t resize_raster(gsc_server* s) {
     e = std::min<int64_t>(e, ((int64_t)1 << 31) - 1);
     p = std::min<int64_t>(p, ((int64_t)1 << 31) - 1);
     if (e == s->r_entries && p == s->r_pairs && t == s->r_tiles) return hipSuccess;
+    if (e > 0 && e <= s->r_entries && p <= s->r_pairs && t <= s->r_tiles) return hipSuccess;  // fits
     s->rmem.release();
     s->raster = Raster();
     s->rmem2.release();
