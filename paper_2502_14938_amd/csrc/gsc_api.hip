@@ -964,6 +964,10 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
                 std::vector<uint64_t> k64(m);
                 HIP_OR_FAIL(c, hipMemcpy(k64.data(), R.pkey64[R.sorted_buf], m * 8, hipMemcpyDeviceToHost));
                 for (int64_t i = 0; i < m; ++i) ((uint32_t*)dst)[i] = (uint32_t)(k64[i] >> 32);
+            } else if (R.key16) {
+                std::vector<uint16_t> k16(m);
+                HIP_OR_FAIL(c, hipMemcpy(k16.data(), R.pkey[R.sorted_buf], m * 2, hipMemcpyDeviceToHost));
+                for (int64_t i = 0; i < m; ++i) ((uint32_t*)dst)[i] = k16[i];
             } else {
                 HIP_OR_FAIL(c, hipMemcpy(dst, R.pkey[R.sorted_buf], m * 4, hipMemcpyDeviceToHost));
             }

@@ -198,6 +198,7 @@ struct Raster {
     RasterCounters* cnt = nullptr;
     RasterCounters* cnt_host = nullptr;
     int sorted_buf = 0;         // which pkey/pval buffer holds the sorted pairs
+    bool key16 = false;         // the last batch's tile keys were 16-bit (pkey read as uint16_t)
     const uint32_t* order = nullptr;  // depth rank -> entry (null: pair values are entries)
     size_t bytes = 0;
 };
@@ -225,6 +226,9 @@ hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st,
                           const uint32_t* gsrc = nullptr, uint32_t* gout = nullptr);
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
+// 16-bit keys (tile ids of batches with at most 65,536 tiles).
+hipError_t radix_sort_u16(uint16_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
 
 

@@ -406,7 +406,8 @@ struct DupArgs {
     const uint32_t* offs;    // pair offset per rank (per entry in full-key mode)
     const float4* rec;
     const uint32_t* dkey;    // depth key per entry (full-key mode)
-    uint32_t* key32;         // global tile id (depth-presorted mode)
+    uint32_t* key32;         // global tile id (depth-presorted mode, more than 65,536 tiles)
+    uint16_t* key16;         // global tile id (depth-presorted mode, at most 65,536 tiles)
     uint64_t* key64;         // (global tile << 32 | depth bits) (full-key mode)
     uint32_t* val;           // entry id
     int64_t max_pairs;
@@ -438,6 +439,7 @@ template <bool kFull>
 __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t, uint32_t e, uint64_t low) {
     if (q >= d.max_pairs) return;
     if (kFull) d.key64[q] = ((uint64_t)t << 32) | low;
+    else if (d.key16) d.key16[q] = (uint16_t)t;
     else d.key32[q] = t;
     d.val[q] = e;
 }
@@ -796,7 +798,7 @@ __global__ __launch_bounds__(NT) void k_ranges(const K* __restrict__ keys, const
     // each lane takes RQ consecutive keys (a wave 64 RQ, coalesced), two such
     // steps in flight; neighbours across lanes come from the adjacent lanes,
     // the wave's two end lanes read theirs
-    constexpr int RQ = 4, US = 4;
+    constexpr int RQ = sizeof(K) == 2 ? 8 : 4, US = 4;  // 16 bytes of keys per lane (32 for 64-bit keys)
     const int64_t n = *n_sort;
     const int lane = threadIdx.x & 63;
     const int64_t wave = gtid() >> 6, nwaves = gstride() >> 6;
@@ -1074,7 +1076,12 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         mark(mk, 7, st);
-        da.order = r.dval[which]; da.offs = r.offs; da.key32 = r.pkey[0]; da.key64 = nullptr; da.val = r.pval[0];
+        // tile keys in 16 bits when the batch's global tile ids fit
+        const bool k16 = tab.total_tiles <= 65536;
+        uint16_t* pk16[2] = {reinterpret_cast<uint16_t*>(r.pkey[0]), reinterpret_cast<uint16_t*>(r.pkey[1])};
+        da.order = r.dval[which]; da.offs = r.offs; da.key64 = nullptr; da.val = r.pval[0];
+        da.key32 = k16 ? nullptr : r.pkey[0];
+        da.key16 = k16 ? pk16[0] : nullptr;
         hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
         mark(mk, 8, st);
         e = tall_list(r, st);
@@ -1084,18 +1091,26 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         mark(mk, 10, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
-        e = radix_sort_u32(r.pkey, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st);
+        e = k16 ? radix_sort_u16(pk16, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st)
+                : radix_sort_u32(r.pkey, r.pval, r.n_sort, 0, 0, tile_bits, r.hist, r.block_sums, &pw, st);
         if (e != hipSuccess) return e;
         mark(mk, 11, st);
         r.sorted_buf = pw;
-        hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey[pw], r.n_sort, 0,
-                           r.ranges, (uint32_t)tab.total_tiles);
+        r.key16 = k16;
+        if (k16)
+            hipLaunchKernelGGL(k_ranges<uint16_t>, grid_fit(k_ranges<uint16_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st,
+                               pk16[pw], r.n_sort, 0, r.ranges, (uint32_t)tab.total_tiles);
+        else
+            hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st,
+                               r.pkey[pw], r.n_sort, 0, r.ranges, (uint32_t)tab.total_tiles);
     } else {
         mark(mk, 6, st);  // no per-Gaussian depth pass in this mode
         e = scan_u32(r.ntiles, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         mark(mk, 7, st);
-        da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key64 = r.pkey64[0]; da.val = r.pval[0];
+        da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key16 = nullptr; da.key64 = r.pkey64[0];
+        da.val = r.pval[0];
+        r.key16 = false;
         hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
         mark(mk, 8, st);
         e = tall_list(r, st);

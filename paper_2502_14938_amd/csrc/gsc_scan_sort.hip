@@ -345,6 +345,12 @@ hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n
     return radix_sort_impl<uint32_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, gsrc, gout);
 }
 
+hipError_t radix_sort_u16(uint16_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
+                          int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
+    return radix_sort_impl<uint16_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, nullptr,
+                                     nullptr);
+}
+
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
     return radix_sort_impl<uint64_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, nullptr,

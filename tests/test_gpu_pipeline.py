@@ -167,3 +167,33 @@ def test_reuse_off_equals_plain(gs, tiny):
         b.reset_cache()
         y = gpu_frame(b, L, R)
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_wide_stereo_frame_with_32bit_tile_keys(gs, tiny):
+    """A 4096x2160 stereo frame holds 2 x 34,560 = 69,120 global tiles, more
+    than 16-bit tile keys address: the pairs keep 32-bit keys and the tile
+    sort takes three passes (8 + 8 + 1 bits).  Sorted pairs and images
+    against the oracle; frames of fewer tiles use 16-bit keys (every other
+    test here)."""
+    from parity import assert_pairs_large, excluded_codes
+    W, H = 4096, 2160
+    # from 60 m the cube's footprints stay a few tile rows tall (within the
+    # renderer's default row-span and pair capacities at this size)
+    L, R = synth.stereo_pair((0.0, 0.0, -60.0), (0.0, 0.0, 1.0), (0, -1, 0), W, H, math.radians(60),
+                             2 * math.atan(math.tan(math.radians(30)) * H / W))
+    r = gs.Renderer(k=tiny.k, max_width=W, max_height=H)
+    r.load(tiny)
+    iL, iR = gpu_frame(r, L, R)
+    vis, G = r.debug("visible"), r.debug("gauss")
+    pairs = [r.debug("pairs", 0), r.debug("pairs", 1)]
+    keys = r.debug("sort_keys")
+    r.close()
+    assert len(keys) == len(pairs[0]) + len(pairs[1]) and np.all(np.diff(keys.astype(np.int64)) >= 0)
+    ref = oracle.render_frame(tiny, L, R, debug=True)
+    codes_g = assert_visible_and_buffer(vis, G, ref, tiny.k)
+    codes_o = gauss_codes(ref["G"], ref["visible"], tiny.k)
+    ex = excluded_codes(ref, tiny.k)
+    for eye, key in ((0, "left"), (1, "right")):
+        assert_pairs_large(pairs[eye], codes_g, ref[key], codes_o, ex, ref[key]["pre"]["depth"])
+    assert_image(iL, ref["left"])
+    assert_image(iR, ref["right"])
