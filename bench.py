@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", default="frames", choices=["frames", "serving", "guides", "precision", "reuse", "lod"])
+    ap.add_argument("--mode", default="frames", choices=["frames", "serving", "guides", "precision", "reuse", "lod",
+                                                         "tiny"])
     ap.add_argument("--form", default="cached-bf16-learned", choices=sorted(FORMS))
     ap.add_argument("--threshold", type=float, default=0.9, help="learned reuse: re-derive when p(stale) > this")
     ap.add_argument("--d-max", type=int, default=10)
@@ -939,6 +940,80 @@ def run_lod(args):
                       "configs": out}), flush=True)
 
 
+# --------------------------------------------------------------------------- tiny scene
+
+def run_tiny(args):
+    """The tiny plain scene (2,000 anchors in a 10 m cube, k = 10, one
+    256x256 stereo pair per frame) on a 60-frame orbit at 15 m: stereo
+    frames/s of plain FP32, BF16 derivation, and the cache with BF16
+    derivation, and the FP64 oracle on every frame (all host cores, one core
+    on frame 0): per-image max-abs of plain FP32 outside the oracle's bands,
+    and every form's PSNR against the oracle."""
+    import torch
+    import paper_2502_14938_amd as gs
+    import synth
+    import oracle
+
+    torch.cuda.set_device(0)
+    scene = synth.tiny_scene()
+    W = H = 256
+    traj = []
+    for i in range(60):
+        a = 2.0 * math.pi * i / 60.0
+        head = (15.0 * math.sin(a), 0.0, -15.0 * math.cos(a))
+        traj.append(synth.stereo_pair(head, (-math.sin(a), 0.0, math.cos(a)), (0, -1, 0), W, H, math.radians(60)))
+    out = {}
+    imgs = {}
+    for form in ("plain", "bf16", "cached-bf16"):
+        r = gs.Renderer(k=scene.k, d_max=args.d_max, max_width=W, max_height=H, **FORMS[form])
+        r.load(scene)
+        t, lat, _, _ = timed_pass(torch, r, traj, len(traj), args.warmup, W, H, "tiny:" + form, stages=[])
+        out[form] = {"fps": round(len(traj) / t, 1), "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 4)}
+        r.reset_cache()
+        oL = torch.zeros(3, H, W, device="cuda"); oR = torch.zeros(3, H, W, device="cuda")
+        imgs[form] = []
+        for L, R_ in traj:
+            r.frame(L, R_, oL, oR)
+            imgs[form].append((oL.cpu().numpy(), oR.cpu().numpy()))
+        r.close()
+    cores = host_cores()
+    oracle.set_threads(cores)
+    per, worst_unflagged, ps = [], 0.0, []
+    ps_f = {"bf16": [], "cached-bf16": []}
+    for i, (L, R_) in enumerate(traj):
+        t0 = time.perf_counter()
+        ref = oracle.render_frame(scene, L, R_)
+        per.append(time.perf_counter() - t0)
+        for e, key in ((0, "left"), (1, "right")):
+            a = imgs["plain"][i][e].astype(np.float64)
+            d = np.abs(a - ref[key]["image"]).max(0)
+            worst_unflagged = max(worst_unflagged, float(d[ref[key]["band"] == 0].max()))
+            ps.append(oracle.psnr(imgs["plain"][i][e], ref[key]["image"]))
+            for f in ps_f:
+                ps_f[f].append(oracle.psnr(imgs[f][i][e], ref[key]["image"]))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.render_frame(scene, *traj[0])
+    one = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    print(json.dumps({"mode": "tiny", "workload": "tiny plain scene: 2,000 anchors in a 10 m cube, 32-dim features, "
+                      "k = 10, stereo 256x256 per eye, 60-frame orbit at 15 m",
+                      "gpu": out,
+                      "plain_fp32_vs_oracle": {"max_abs_unflagged": float("%.3g" % worst_unflagged),
+                                               "psnr_db_min": round(float(min(ps)), 2),
+                                               "psnr_db_mean": round(float(np.mean(ps)), 2), "images": len(ps)},
+                      **{f.replace("-", "_") + "_vs_oracle": {"psnr_db_min": round(float(min(v)), 2),
+                                                               "psnr_db_mean": round(float(np.mean(v)), 2)}
+                         for f, v in ps_f.items()},
+                      "cpu_baseline": {"value": round(1.0 / float(np.median(per)), 3), "unit": "stereo frames/s",
+                                       "cores": oracle.threads(), "kind": "oracle",
+                                       "sample": "every frame of the orbit (60), plain FP64 method",
+                                       "s_per_frame_median": round(float(np.median(per)), 4),
+                                       "s_per_frame_max": round(float(np.max(per)), 4),
+                                       "one_core_s_per_frame": round(one, 4)}}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -955,6 +1030,8 @@ def main():
         run_reuse(args)
     elif args.mode == "lod":
         run_lod(args)
+    elif args.mode == "tiny":
+        run_tiny(args)
     else:
         run_frames(args)
 
