@@ -655,7 +655,7 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->depth_used = k.depth_used;
     st->depth_next = k.depth;
     st->overflow = ((r.overflow & 7) ? 1 : 0) | (k.overflow & 2);
-    st->n_tall = r.n_tall;
+    st->n_tall = r.n_tall_e;
     size_t bytes = c->scene.bytes + c->view[0].bytes + c->view[1].bytes + c->raster.bytes + c->raster2.bytes + c->xg_bytes;
     st->device_bytes = (int64_t)bytes;
     if (c->rendered && !c->explicit_render && c->last_count_work && c->last_tab.total_tiles > 0) {

@@ -51,13 +51,11 @@ struct RasterCounters {
     int32_t entry_base[kMaxSeg + 1];  // entry of Gaussian 0 of each segment (total last)
     int32_t entry_stride;             // 2 with paired segments, else 1
     int32_t n_pairs;              // total tile pairs (all segments)
-    int32_t n_chunks;             // chunks of 256 depth ranks (tall-entry lists)
-    int32_t n_tall;               // tall entries (more than 4 tile rows) with tiles
     int32_t n_echunks;            // chunks of 256 entries (preprocess tall lists)
     int32_t n_tall_e;             // tall entries found by the preprocess
     int32_t n_rows;               // their tile rows (stored spans)
     int32_t overflow;             // bit0: pair capacity, bit1: entries, bit2: tall-row spans
-    int32_t pad;
+    int32_t n_gpairs;             // entries / 2: the depth sort's length when the eyes share it
 };
 
 // One (viewer, eye) image of a raster batch; passed by value in kernel args.
@@ -168,11 +166,8 @@ struct View {
 // Raster batch buffers.
 struct Raster {
     int64_t max_entries = 0, max_pairs = 0, max_tiles = 0;
-    float4* rec = nullptr;      // [4 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count), spans
-    int32_t* big_list = nullptr;  // tall entries (ranks), listed in their chunk's 256 slots
-    int32_t* tall_cnt = nullptr;  // [max_entries / 256 + 1] tall entries per chunk of 256 ranks
-    uint32_t* tall_off = nullptr; // [max_entries / 256 + 1] their exclusive prefix
-    int32_t* tall_list = nullptr; // [max_entries] tall entries (ranks), dense
+    float4* rec = nullptr;      // [4 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count),
+                                // spans (tall footprints: first stored span, output offset)
     int32_t* pt_list = nullptr;   // [max_entries] tall entries (entry ids) in their chunk's slots
     int32_t* pt_cnt = nullptr;    // [max_entries / 256 + 1] per chunk of entries
     uint32_t* pt_off = nullptr;   // [max_entries / 256 + 1]
@@ -181,6 +176,7 @@ struct Raster {
     uint32_t* pt_rowoff = nullptr;  // [max_entries] first stored span of each
     uint32_t* spans = nullptr;    // [span_cap] row spans of the tall footprints (lo | hi << 16)
     int32_t* rowmap = nullptr;    // [span_cap] footprint (dense index) of each stored span
+    uint32_t* rowpre = nullptr;   // [span_cap] pairs of the footprint's rows before each stored span
     int64_t span_cap = 0;
     uint32_t* ntiles = nullptr; // tile count per entry
     uint32_t* scnt = nullptr;   // tile count per depth rank
@@ -199,6 +195,7 @@ struct Raster {
     RasterCounters* cnt_host = nullptr;
     int sorted_buf = 0;         // which pkey/pval buffer holds the sorted pairs
     bool key16 = false;         // the last batch's tile keys were 16-bit (pkey read as uint16_t)
+    bool shared_depth = false;  // this batch's eyes of a view share one depth sort
     const uint32_t* order = nullptr;  // depth rank -> entry (null: pair values are entries)
     size_t bytes = 0;
 };
@@ -221,10 +218,14 @@ hipError_t compact_u32(const uint32_t* flags, const int32_t* n_dev, int64_t n_ho
 // *n_dev (device) or n_host.  Returns in *which the buffer index (0/1)
 // holding the result.  hist: [256 * kSortBlocks], block_sums: scan scratch.
 // With gout, the last pass writes gout[i] = gsrc[sorted value i] in place of
-// the sorted keys (which are then not produced).
+// the sorted keys (which are then not produced).  With gout and pairs, each
+// value v stands for the two elements 2v, 2v+1: the last pass writes, for
+// sorted position i, vals[2i + h] = 2v + h and gout[2i + h] = gsrc[2v + h]
+// (h = 0, 1), so the result holds 2n values (the value buffers must hold
+// them).
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st,
-                          const uint32_t* gsrc = nullptr, uint32_t* gout = nullptr);
+                          const uint32_t* gsrc = nullptr, uint32_t* gout = nullptr, bool pairs = false);
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st);
 // 16-bit keys (tile ids of batches with at most 65,536 tiles).

@@ -8,7 +8,9 @@
 //   depth radix pass   stable sort of entries by float32 depth (the low 32
 //                      bits of the (tile | depth) key, applied per Gaussian
 //                      before duplication); the last pass also lays the tile
-//                      counts out in depth order
+//                      counts out in depth order.  When a view's two eyes
+//                      share its rotation, one key per Gaussian orders both
+//                      eyes' entries (half the keys)
 //   scan + k_dup_rows / k_dup_big
 //                      one (global tile id, entry) pair per covered tile,
 //                      emitted in depth order (LDS-staged, coalesced)
@@ -21,6 +23,7 @@
 // With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
 // key and are sorted after duplication instead; the order is the same.
 #include <cmath>
+#include <cstring>
 
 #include "gsc_common.h"
 
@@ -59,7 +62,8 @@ __device__ __forceinline__ int32_t entry_bases(const SegTable& tab, int64_t max_
     }
     base[tab.n] = acc;
     over = acc > max_entries;
-    return over ? (int32_t)max_entries : acc;
+    // (paired: whole pairs only, so both eyes' entries of a Gaussian stay together)
+    return over ? (int32_t)(tab.paired ? (max_entries & ~(int64_t)1) : max_entries) : acc;
 }
 
 // Entry e -> (segment si, Gaussian g of that segment).
@@ -219,11 +223,10 @@ __device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
     return eb;
 }
 
-// Footprints taller than this many tile rows are counted by the whole wave
-// (lanes split the rows) and emitted one wave per entry; shorter ones keep
-// their row spans in the record and are emitted from them.
+// Footprints taller than this many tile rows get one thread per row for
+// their spans (k_tall_rows) and are emitted row by row (k_dup_big); shorter
+// ones keep their row spans in the record and are emitted from them.
 constexpr int kSmallRows = 4;
-constexpr int kTallGroup = 8;     // tall entries whose metadata a wave loads together (k_dup_big)
 
 // Fractional level transition: weight clamp(2 - |x - p_u| / d_l, 0, 1) of a
 // level-l anchor's opacities (1 at level 0), the distance taken in FP32 as
@@ -254,6 +257,7 @@ struct PreArgs {
     int32_t* ranges;     // [2 * tiles] cleared here for this batch's ranges
     int64_t n_ranges;
     int64_t max_entries;
+    int32_t shared_depth;  // paired eyes of one rotation: one depth key per Gaussian
 };
 
 // (at most 128 VGPRs: four waves per SIMD to cover the chain of dependent
@@ -270,6 +274,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             p.rc->entry_stride = p.tab.paired ? 2 : 1;
             p.rc->overflow = over ? 2 : 0;
             p.rc->n_entries = s_ne;
+            p.rc->n_gpairs = s_ne >> 1;
             p.rc->n_echunks = (s_ne + NT - 1) / NT;
         }
     }
@@ -393,8 +398,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             p.rec[kRec * e + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
                                               __uint_as_float(spans[2]), __uint_as_float(spans[3]));
             p.ntiles[e] = count;
-            p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
-            p.dval[e] = (uint32_t)e;
+            if (!p.shared_depth) {
+                p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
+                p.dval[e] = (uint32_t)e;
+            }
+        }
+        if (p.shared_depth) {
+            // The eyes' entries 2j, 2j+1 sit in neighbouring lanes.  With one
+            // rotation for both eyes their view depths differ by a constant,
+            // so one key orders both: the left eye's depth when that eye
+            // draws the Gaussian, else the right eye's.
+            const bool draws = valid && (count || tall);
+            const uint32_t mine = draws ? __float_as_uint(depth) : 0u;
+            const uint32_t other = (uint32_t)__shfl_xor((int)mine, 1);
+            const int odraws = __shfl_xor((int)draws, 1);
+            if (valid && !(e & 1)) {
+                p.dkey[e >> 1] = draws ? mine : (odraws ? other : 0u);
+                p.dval[e >> 1] = (uint32_t)(e >> 1);
+            }
         }
     }
 }
@@ -404,7 +425,7 @@ struct DupArgs {
     RasterCounters* rc;
     const uint32_t* order;   // depth rank -> entry (depth-presorted mode)
     const uint32_t* offs;    // pair offset per rank (per entry in full-key mode)
-    const float4* rec;
+    float4* rec;             // (k_dup_rows stores a tall entry's output offset in D.y)
     const uint32_t* dkey;    // depth key per entry (full-key mode)
     uint32_t* key32;         // global tile id (depth-presorted mode, more than 65,536 tiles)
     uint16_t* key16;         // global tile id (depth-presorted mode, at most 65,536 tiles)
@@ -428,13 +449,10 @@ static_assert(sizeof(PreArgs) <= 4096 && sizeof(DupArgs) + 2 * sizeof(void*) <= 
 //                preprocess stored give each pair's tile; a wave writes its 64
 //                entries' pairs together, lane j taking pairs j, j + 64, ...
 //                of their concatenation (consecutive lanes, consecutive
-//                slots), so the stores coalesce; taller entries are listed
-//                in their chunk's slots (the chunk of 256 ranks a block
-//                step covers, count per chunk; no atomics);
-//   k_dup_big    one wave per tall entry of the dense list (chunk lists
-//                joined by a scan of their counts): the row spans that
-//                k_tall_rows stored, then the entry's pairs written together,
-//                lane j taking pairs j, j + 64, ... (coalesced stores).
+//                slots), so the stores coalesce; for a taller entry it
+//                stores the output offset in the record instead;
+//   k_dup_big    the taller entries' stored rows, 64 to a wave, whatever
+//                entries they belong to (below).
 template <bool kFull>
 __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t, uint32_t e, uint64_t low) {
     if (q >= d.max_pairs) return;
@@ -444,10 +462,9 @@ __device__ __forceinline__ void put_pair(const DupArgs& d, int64_t q, uint32_t t
     d.val[q] = e;
 }
 
-// Pairs to sort (clamped to the capacity; overflow flagged) and the chunk
-// count of the emission's tall lists; run by one thread of k_dup_rows.
+// Pairs to sort (clamped to the capacity; overflow flagged); run by one
+// thread of k_dup_rows.
 __device__ __forceinline__ void pairs_clamp(RasterCounters* rc, int32_t* n_sort, int64_t max_pairs) {
-    rc->n_chunks = (rc->n_entries + NT - 1) / NT;
     int32_t n = rc->n_pairs;
     if ((int64_t)n > max_pairs) {
         rc->overflow |= 1;
@@ -457,8 +474,7 @@ __device__ __forceinline__ void pairs_clamp(RasterCounters* rc, int32_t* n_sort,
 }
 
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict__ big_list,
-                                                 int32_t* __restrict__ tall_cnt) {
+__global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
     // per thread (entry): pairs before each row's end, first tile id of each row
     __shared__ uint32_t s_cum[kSmallRows][NT];
     __shared__ uint32_t s_first[kSmallRows][NT];
@@ -466,13 +482,11 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
     __shared__ uint32_t s_out[NT];    // output offset of the entry
     __shared__ uint32_t s_e[NT];      // entry id
     __shared__ uint32_t s_low[NT];    // depth bits (full-key mode)
-    __shared__ uint32_t s_wtall[NT / 64];
     if (blockIdx.x == 0 && threadIdx.x == 0) pairs_clamp(d.rc, d.n_sort, d.max_pairs);
     const int64_t ne = d.rc->n_entries;
     const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
         const int64_t r = base + threadIdx.x;
-        bool is_big = false;
         uint32_t n_here = 0;
         uint32_t cum[kSmallRows] = {0u, 0u, 0u, 0u}, first[kSmallRows] = {0u, 0u, 0u, 0u};
         if (r < ne) {
@@ -480,7 +494,7 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
             // record's count / rows word and its spans together
             const uint32_t e = kFull ? (uint32_t)r : d.order[r];
             const uint32_t out_at = d.offs[r];
-            const float4* rp = d.rec + kRec * (int64_t)e;
+            float4* rp = d.rec + kRec * (int64_t)e;
             const float4 C = rp[2];
             const float4 D = rp[3];
             const uint32_t cnt = __float_as_uint(C.w);
@@ -488,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
                 const uint32_t rows = __float_as_uint(C.y);
                 const int y0 = rows & 0xffff, y1 = rows >> 16;
                 if (y1 - y0 + 1 > kSmallRows) {
-                    is_big = true;
+                    rp[3].y = __uint_as_float(out_at);  // for k_dup_big
                 } else {
                     const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
                                                      __float_as_uint(D.w)};
@@ -515,22 +529,7 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
         }
         uint32_t tot;
         s_start[threadIdx.x] = wave_excl_scan(n_here, tot);
-        // tall entries of this chunk of 256 ranks go to the chunk's own slots
-        // of the list (no atomics; their order is irrelevant)
-        const uint64_t m = __ballot(is_big);
-        if (lane == 0) s_wtall[threadIdx.x >> 6] = (uint32_t)__popcll(m);
-        __syncthreads();
-        const int64_t chunk = base / NT;
-        if (is_big) {
-            uint32_t at = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            for (int q = 0; q < (int)(threadIdx.x >> 6); ++q) at += s_wtall[q];
-            big_list[chunk * NT + at] = (int32_t)r;
-        }
-        if (threadIdx.x == 0) {
-            uint32_t n = 0;
-            for (int q = 0; q < NT / 64; ++q) n += s_wtall[q];
-            tall_cnt[chunk] = (int32_t)n;
-        }
+        __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
         // the wave's pairs in rank order, lane j taking pairs j, j + 64, ...:
         // consecutive lanes write consecutive slots of one entry's range
         for (uint32_t j = lane; j < tot; j += 64) {
@@ -548,26 +547,23 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d, int32_t* __restrict_
             const uint32_t before = row ? s_cum[row - 1][t] : 0u;
             put_pair<kFull>(d, (int64_t)s_out[t] + k, s_first[row][t] + (k - before), s_e[t], s_low[t]);
         }
-        __syncthreads();  // LDS is rewritten by the next step
+        __builtin_amdgcn_wave_barrier();  // before the next step rewrites the wave's LDS
     }
 }
 
-// Dense list of the tall entries: chunk c's entries at tall_off[c] + i;
-// with rowcnt, also the tile rows of each (entry ids listed).
-__global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ big_list,
-                                                     const int32_t* __restrict__ tall_cnt,
-                                                     const uint32_t* __restrict__ tall_off, const int32_t* n_chunks,
-                                                     int32_t* __restrict__ tall_list, const float4* __restrict__ rec,
+// Dense list of the tall entries the preprocess listed per chunk of 256
+// entries: chunk c's entries at off[c] + i, and the tile rows of each.
+__global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ list, const int32_t* __restrict__ cnt,
+                                                     const uint32_t* __restrict__ off, const int32_t* n_chunks,
+                                                     int32_t* __restrict__ dense, const float4* __restrict__ rec,
                                                      uint32_t* __restrict__ rowcnt) {
     const int64_t nc = *n_chunks;
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x)
-        if ((int32_t)threadIdx.x < tall_cnt[c]) {
-            const int32_t x = big_list[c * NT + threadIdx.x];
-            tall_list[tall_off[c] + threadIdx.x] = x;
-            if (rowcnt) {
-                const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)x + 2].y);
-                rowcnt[tall_off[c] + threadIdx.x] = (rows >> 16) - (rows & 0xffff) + 1;
-            }
+        if ((int32_t)threadIdx.x < cnt[c]) {
+            const int32_t x = list[c * NT + threadIdx.x];
+            dense[off[c] + threadIdx.x] = x;
+            const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)x + 2].y);
+            rowcnt[off[c] + threadIdx.x] = (rows >> 16) - (rows & 0xffff) + 1;
         }
 }
 
@@ -582,142 +578,68 @@ __global__ __launch_bounds__(NT) void k_tall_rowmap(const uint32_t* __restrict__
     }
 }
 
+// One wave per 64 consecutive stored rows of the tall footprints (a
+// footprint's rows are consecutive, and so are their output ranges): each
+// lane takes one row (its span, first tile and output offset: the entry's
+// offset, stored by k_dup_rows, plus the pairs of its earlier rows, stored
+// by k_tall_count), then the wave writes the 64 rows' pairs together, lane j
+// taking pairs j, j + 64, ... (consecutive lanes, consecutive slots within a
+// row).  A large footprint's rows spread over as many waves as they fill.
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_list) {
-    __shared__ uint32_t s_ex[NT / 64][64];     // pairs before each of the wave's current 64 rows
-    __shared__ uint32_t s_first[NT / 64][64];  // global tile id of each row's first listed tile
-    __shared__ uint32_t s_out[NT / 64][64];    // output position of each row's first pair (combined rows)
-    __shared__ uint32_t s_lim[NT / 64][64];    // pairs each row may write (combined rows)
-    __shared__ uint32_t s_e[NT / 64][64];      // entry of each row (combined rows)
-    __shared__ uint32_t s_low[NT / 64][64];    // depth bits of each row's entry (combined rows, full keys)
+__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_e,
+                                                const uint32_t* __restrict__ rowoff, const int32_t* __restrict__ rowmap,
+                                                const uint32_t* __restrict__ rowpre) {
+    __shared__ uint32_t s_ex[NT / 64][64];     // pairs before each of the wave's 64 rows
+    __shared__ uint32_t s_first[NT / 64][64];  // global tile id of each row's first tile
+    __shared__ uint32_t s_out[NT / 64][64];    // output position of each row's first pair
+    __shared__ uint32_t s_e[NT / 64][64];      // entry of each row
+    __shared__ uint32_t s_low[NT / 64][64];    // depth bits of each row's entry (full keys)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t nb = d.rc->n_tall;
+    int64_t nr = d.rc->n_rows;
+    if (nr > d.span_cap) nr = d.span_cap;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    // wave w emits list entries w, w + nwaves, w + 2 nwaves, ... (heavy
-    // footprints cluster in the list; striding spreads them over the waves),
-    // loading the metadata of its next kTallGroup entries together, one per
-    // lane, then emitting them in turn
-    for (int64_t b0 = wave; b0 < nb; b0 += nwaves * kTallGroup) {
-        uint32_t me = 0, mo = 0, mcnt = 0, mrows = 0, mseg = 0, msp0 = 0, mlow = 0;
-        const int64_t bl = b0 + (int64_t)lane * nwaves;
-        if (lane < kTallGroup && bl < nb) {
-            const int64_t r = tall_list[bl];
-            me = kFull ? (uint32_t)r : d.order[r];
-            mo = d.offs[r];
-            const float4* rp = d.rec + kRec * (int64_t)me;
-            const float4 C = rp[2];
-            mcnt = __float_as_uint(C.w);
-            mrows = __float_as_uint(C.y);
-            mseg = __float_as_uint(C.z);
-            msp0 = __float_as_uint(rp[3].x);  // first stored span (k_tall_count)
-            mlow = kFull ? d.dkey[me] : 0u;
-        }
-        const int64_t left = (nb - b0 + nwaves - 1) / nwaves;  // entries of this wave from b0 on
-        const int ng = left < kTallGroup ? (int)left : kTallGroup;
-        // rows of the group's entries: when they fit one wave, every row of
-        // every entry goes to its own lane and the group's pairs are written
-        // in one pass (most tall footprints are a few tiles wide)
-        const uint32_t nrows = lane < ng ? (mrows >> 16) - (mrows & 0xffff) + 1u : 0u;
-        uint32_t rtot;
-        const uint32_t rbase = wave_excl_scan(nrows, rtot);
-        if (rtot <= 64u) {
-            // lane l: row l of the concatenation; its entry gi is the last
-            // group lane whose first row is <= l
-            int gi = 0;
-#pragma unroll
-            for (int g2 = 1; g2 < kTallGroup; ++g2)
-                if (g2 < ng && (uint32_t)__shfl(rbase, g2, 64) <= (uint32_t)lane) gi = g2;
-            const bool live = (uint32_t)lane < rtot;
-            const uint32_t g_rb = __shfl(rbase, gi, 64), g_rows = __shfl(mrows, gi, 64);
-            const uint32_t g_e = __shfl(me, gi, 64), g_cnt = __shfl(mcnt, gi, 64), g_seg = __shfl(mseg, gi, 64);
-            const uint32_t g_o = __shfl(mo, gi, 64), g_sp0 = __shfl(msp0, gi, 64), g_low = __shfl(mlow, gi, 64);
-            const int ri = lane - (int)g_rb;
-            uint32_t sp = 0xffffu;
-            if (live && (int64_t)g_sp0 + ri < d.span_cap) sp = d.spans[(int64_t)g_sp0 + ri];
+    for (int64_t q0 = wave * 64; q0 < nr; q0 += nwaves * 64) {
+        const int64_t q = q0 + lane;
+        uint32_t np = 0, first = 0, out = 0, e = 0, low = 0;
+        if (q < nr) {
+            const uint32_t sp = d.spans[q];
             const int lo = sp & 0xffff, hi = sp >> 16;
-            uint32_t tot;
-            const uint32_t ex = wave_excl_scan(live && hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
-            const uint32_t in_entry = ex - (uint32_t)__shfl(ex, (int)g_rb, 64);  // pairs of the entry before this row
-            const Seg& s = d.tab.s[g_seg];
-            s_ex[w][lane] = ex;
-            s_first[w][lane] = (uint32_t)(s.tile_base + ((int)(g_rows & 0xffff) + ri) * s.ntx + lo);
-            s_out[w][lane] = g_o + in_entry;
-            s_lim[w][lane] = g_cnt > in_entry ? g_cnt - in_entry : 0u;  // pairs the entry's count allows
-            s_e[w][lane] = g_e;
-            s_low[w][lane] = g_low;
-            __builtin_amdgcn_wave_barrier();
-            const int last = (int)rtot - 1;
-            for (uint32_t j = lane; j < tot; j += 64) {
-                int lo2 = 0, hi2 = last;
-                while (lo2 < hi2) {
-                    const int mid = (lo2 + hi2 + 1) >> 1;
-                    if (s_ex[w][mid] <= j) lo2 = mid;
-                    else hi2 = mid - 1;
-                }
-                const uint32_t k = j - s_ex[w][lo2];
-                if (k < s_lim[w][lo2])
-                    put_pair<kFull>(d, (int64_t)s_out[w][lo2] + k, s_first[w][lo2] + k, s_e[w][lo2],
-                                    (uint64_t)s_low[w][lo2]);
-            }
-            __builtin_amdgcn_wave_barrier();  // before the next group overwrites the arrays
-            continue;
-        }
-        // the first 64 rows' spans of every entry of the group, loads in flight together
-        uint32_t pre[kTallGroup];
-#pragma unroll
-        for (int gi = 0; gi < kTallGroup; ++gi) {
-            const uint32_t rows = __shfl(mrows, gi, 64);
-            const int64_t q = (int64_t)__shfl(msp0, gi, 64) + lane;
-            const bool ok = gi < ng && lane <= (int)(rows >> 16) - (int)(rows & 0xffff) && q < d.span_cap;
-            pre[gi] = ok ? d.spans[q] : 0xffffu;
-        }
-        for (int gi = 0; gi < ng; ++gi) {
-            const uint32_t e = __shfl(me, gi, 64);
-            const uint32_t cnt = __shfl(mcnt, gi, 64);
-            const uint32_t rows = __shfl(mrows, gi, 64);
-            const int y0 = rows & 0xffff, y1 = rows >> 16;
-            const Seg& s = d.tab.s[__shfl(mseg, gi, 64)];
-            const uint64_t low = (uint64_t)__shfl(mlow, gi, 64);
-            const int64_t o = __shfl(mo, gi, 64);
-            const int64_t sp0 = __shfl(msp0, gi, 64);
-            uint32_t run = 0;
-            for (int chunk = y0; chunk <= y1; chunk += 64) {
-                // one row per lane: its stored span, then the rows' pair prefix
-                int lo = 0, hi = -1;
-                const int64_t q = sp0 + (chunk - y0) + lane;
-                uint32_t sp = 0xffffu;
-                if (chunk == y0) {
-#pragma unroll
-                    for (int g2 = 0; g2 < kTallGroup; ++g2) sp = g2 == gi ? pre[g2] : sp;
-                } else if (chunk + lane <= y1 && q < d.span_cap) {
-                    sp = d.spans[q];
-                }
-                lo = sp & 0xffff;
-                hi = sp >> 16;
-                uint32_t tot;
-                const uint32_t ex = wave_excl_scan(hi >= lo ? (uint32_t)(hi - lo + 1) : 0u, tot);
-                s_ex[w][lane] = ex;
-                s_first[w][lane] = (uint32_t)(s.tile_base + (chunk + lane) * s.ntx + lo);
-                __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
-                // the rows' pairs together: lane j takes pairs j, j + 64, ... and
-                // finds its row as the last one whose prefix is <= j (rows without
-                // pairs share the next row's prefix, so the last one has pairs)
-                const int last = y1 - chunk < 63 ? y1 - chunk : 63;  // rows past it hold the total
-                for (uint32_t j = lane; j < tot; j += 64) {
-                    int lo2 = 0, hi2 = last;
-                    while (lo2 < hi2) {
-                        const int mid = (lo2 + hi2 + 1) >> 1;
-                        if (s_ex[w][mid] <= j) lo2 = mid;
-                        else hi2 = mid - 1;
-                    }
-                    const uint32_t wpos = run + j;
-                    if (wpos < cnt) put_pair<kFull>(d, o + wpos, s_first[w][lo2] + (j - s_ex[w][lo2]), e, low);
-                }
-                __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
-                run += tot;
+            if (hi >= lo) {
+                const int32_t f = rowmap[q];
+                e = (uint32_t)tall_e[f];
+                const float4* rp = d.rec + kRec * (int64_t)e;
+                const float4 C = rp[2];
+                const Seg& s = d.tab.s[__float_as_uint(C.z)];
+                const int y = (int)(__float_as_uint(C.y) & 0xffffu) + (int)(q - (int64_t)rowoff[f]);
+                np = (uint32_t)(hi - lo + 1);
+                first = (uint32_t)(s.tile_base + y * s.ntx + lo);
+                out = __float_as_uint(rp[3].y) + rowpre[q];
+                low = kFull ? d.dkey[e] : 0u;
             }
         }
+        uint32_t tot;
+        const uint32_t ex = wave_excl_scan(np, tot);
+        s_ex[w][lane] = ex;
+        s_first[w][lane] = first;
+        s_out[w][lane] = out;
+        s_e[w][lane] = e;
+        s_low[w][lane] = low;
+        __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
+        // lane j's row: the last one whose prefix is <= j (rows without pairs
+        // share the next row's prefix, rows past the end hold the total)
+        for (uint32_t j = lane; j < tot; j += 64) {
+            int lo2 = 0, hi2 = 63;
+            while (lo2 < hi2) {
+                const int mid = (lo2 + hi2 + 1) >> 1;
+                if (s_ex[w][mid] <= j) lo2 = mid;
+                else hi2 = mid - 1;
+            }
+            const uint32_t k = j - s_ex[w][lo2];
+            put_pair<kFull>(d, (int64_t)s_out[w][lo2] + k, s_first[w][lo2] + k, s_e[w][lo2],
+                            (uint64_t)s_low[w][lo2]);
+        }
+        __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
     }
 }
 
@@ -745,14 +667,14 @@ __global__ __launch_bounds__(NT) void k_tall_rows(SegTable tab, const int32_t* _
     }
 }
 
-// One thread per tall footprint: its tile count from the stored spans; the
-// record keeps the offset of its first span (in the spans slot D.x) for
-// the emission.
+// One thread per tall footprint: its tile count from the stored spans, and
+// for each stored row the pairs of the footprint's earlier rows (rowpre);
+// the record keeps the offset of its first span (in the spans slot D.x).
 __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ tall_e, const uint32_t* __restrict__ rowoff,
                                                    const uint32_t* __restrict__ rowcnt,
                                                    const uint32_t* __restrict__ spans, const RasterCounters* rc,
                                                    int64_t cap, float4* __restrict__ rec, uint32_t* __restrict__ ntiles,
-                                                   uint32_t* __restrict__ dkey) {
+                                                   uint32_t* __restrict__ dkey, uint32_t* __restrict__ rowpre) {
     const int64_t n = rc->n_tall_e;
     for (int64_t i = gtid(); i < n; i += gstride()) {
         const int64_t e = tall_e[i];
@@ -765,6 +687,7 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int lo = sp[u] & 0xffff, hi = sp[u] >> 16;
+                if (q0 + u < r1) rowpre[q0 + u] = count;
                 count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
             }
         }
@@ -772,7 +695,7 @@ __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ t
         rp[2].w = __uint_as_float(count);
         rp[3].x = __uint_as_float((uint32_t)r0);
         ntiles[e] = count;
-        if (!count) dkey[e] = 0u;
+        if (!count && dkey) dkey[e] = 0u;  // (no per-entry keys when the eyes share the depth sort)
     }
 }
 
@@ -1015,6 +938,16 @@ void seg_camera(Seg& s, const gsc_camera& c) {
     s.nty = (c.height + kTile - 1) / kTile;
 }
 
+// Paired eyes whose FP32 rotations are equal bit for bit see every point at
+// view depths that differ by one constant per view (the eye offset along the
+// shared optical axis), so one depth order serves both eyes up to rounding.
+static bool eyes_share_rotation(const SegTable& tab) {
+    if (!tab.paired || tab.n < 2 || (tab.n & 1)) return false;
+    for (int q = 0; q + 1 < tab.n; q += 2)
+        if (std::memcmp(tab.s[q].R, tab.s[q + 1].R, sizeof(tab.s[q].R)) != 0) return false;
+    return true;
+}
+
 // Tall footprints (more than kSmallRows tile rows): dense list of the
 // entries k_preprocess listed per chunk, offsets of their rows, one thread
 // per row for the exact spans, then each footprint's count.
@@ -1032,18 +965,8 @@ hipError_t tall_spans(const SegTable& tab, Raster& r, hipStream_t st) {
     hipLaunchKernelGGL(k_tall_rows, grid_fit(k_tall_rows, r.span_cap), dim3(NT), 0, st, tab, r.pt_dense, r.pt_rowoff,
                        r.rowmap, r.rec, rc, r.spans, r.span_cap);
     hipLaunchKernelGGL(k_tall_count, grid_fit(k_tall_count, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.pt_rowoff,
-                       r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles, r.dkey[0]);
-    return hipGetLastError();
-}
-
-// Offsets of the chunks' tall entries and their dense list.
-hipError_t tall_list(Raster& r, hipStream_t st) {
-    RasterCounters* rc = r.cnt;
-    hipError_t e = scan_u32(reinterpret_cast<const uint32_t*>(r.tall_cnt), r.tall_off, &rc->n_chunks, 0, &rc->n_tall,
-                            r.block_sums, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.big_list, r.tall_cnt, r.tall_off,
-                       &rc->n_chunks, r.tall_list, nullptr, nullptr);
+                       r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles,
+                       r.shared_depth ? nullptr : r.dkey[0], r.rowpre);
     return hipGetLastError();
 }
 
@@ -1055,6 +978,8 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
     pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_tiles;
     pa.max_entries = r.max_entries;
+    r.shared_depth = !full_key_sort && eyes_share_rotation(tab);
+    pa.shared_depth = r.shared_depth ? 1 : 0;
     hipLaunchKernelGGL(k_preprocess, grid_fit(k_preprocess, r.max_entries), dim3(NT), 0, st, pa);
     mark(mk, 4, st);
     hipError_t e0 = tall_spans(tab, r, st);
@@ -1068,9 +993,11 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     if (!full_key_sort) {
         // low 32 key bits (depth) first, per Gaussian
         int which = 0;
-        // the last pass also lays the tile counts out in depth order (scnt)
-        e = radix_sort_u32(r.dkey, r.dval, &rc->n_entries, 0, 0, 32, r.hist, r.block_sums, &which, st, r.ntiles,
-                           r.scnt);
+        // the last pass also lays the tile counts out in depth order (scnt);
+        // with a shared sort it sorts the Gaussians and lays out both eyes'
+        // entries of each at neighbouring ranks
+        e = radix_sort_u32(r.dkey, r.dval, r.shared_depth ? &rc->n_gpairs : &rc->n_entries, 0, 0, 32, r.hist,
+                           r.block_sums, &which, st, r.ntiles, r.scnt, r.shared_depth);
         if (e != hipSuccess) return e;
         mark(mk, 6, st);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
@@ -1082,12 +1009,11 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         da.order = r.dval[which]; da.offs = r.offs; da.key64 = nullptr; da.val = r.pval[0];
         da.key32 = k16 ? nullptr : r.pkey[0];
         da.key16 = k16 ? pk16[0] : nullptr;
-        hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
+        hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da);
         mark(mk, 8, st);
-        e = tall_list(r, st);
-        if (e != hipSuccess) return e;
-        mark(mk, 9, st);
-        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.tall_list);
+        mark(mk, 9, st);  // (no kernel in the tall-list stage: k_dup_big reads the stored rows)
+        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, r.span_cap), dim3(NT), 0, st, da,
+                           r.pt_dense, r.pt_rowoff, r.rowmap, r.rowpre);
         mark(mk, 10, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
@@ -1111,12 +1037,11 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key16 = nullptr; da.key64 = r.pkey64[0];
         da.val = r.pval[0];
         r.key16 = false;
-        hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da, r.big_list, r.tall_cnt);
+        hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da);
         mark(mk, 8, st);
-        e = tall_list(r, st);
-        if (e != hipSuccess) return e;
         mark(mk, 9, st);
-        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, (int64_t)kGridBlocks * NT), dim3(NT), 0, st, da, r.tall_list);
+        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, r.span_cap), dim3(NT), 0, st, da,
+                           r.pt_dense, r.pt_rowoff, r.rowmap, r.rowpre);
         mark(mk, 10, st);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);

@@ -175,13 +175,40 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ keys, c
         hist[(int64_t)q * gridDim.x + blockIdx.x] = h[0][q] + h[1][q] + h[2][q] + h[3][q];
 }
 
-// kGather (last pass only): instead of the keys, write gout[pos] =
-// gsrc[value] (a per-value quantity wanted in sorted order).
-template <typename K, int BITS, bool kGather>
+// Exclusive scan of each digit's per-block counts (digit-major rows of
+// kSortBlocks counts, one block per digit, in place); tot[d] = the digit's
+// total.  The scatter adds the digit bases (a scan of the totals) itself.
+static_assert(kSortBlocks % NT == 0, "digit rows split evenly over the threads");
+__global__ __launch_bounds__(NT) void k_radix_digit_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot) {
+    constexpr int PER = kSortBlocks / NT;
+    __shared__ uint32_t wsum[NT / 64];
+    uint32_t* row = hist + (int64_t)blockIdx.x * kSortBlocks + threadIdx.x * PER;
+    uint32_t v[PER], s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        v[i] = row[i];
+        s += v[i];
+    }
+    uint32_t all;
+    uint32_t e = block_excl_scan(s, wsum, all);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        row[i] = e;
+        e += v[i];
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = all;
+}
+
+// kGather (last pass only): 1 = instead of the keys, write gout[pos] =
+// gsrc[value] (a per-value quantity wanted in sorted order); 2 = the same
+// for the two elements 2 value, 2 value + 1 each value stands for, at
+// positions 2 pos, 2 pos + 1 of vout and gout.
+template <typename K, int BITS, int kGather>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       const int32_t* n_dev, int64_t n_host, int shift,
                                                       const uint32_t* __restrict__ offs,
+                                                      const uint32_t* __restrict__ dtot,
                                                       const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gout) {
     constexpr int bits = BITS;
     __shared__ uint32_t cnt[4][256];
@@ -196,7 +223,12 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
     const int64_t n = count_of(n_dev, n_host);
     chunk_of(n, SORT_TILE, b0, b1);
     if (b0 >= b1) return;
-    if (threadIdx.x < nbins) run[threadIdx.x] = offs[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    {
+        // digit base (earlier digits' totals) + this block's prefix within the digit
+        uint32_t all;
+        const uint32_t dbase = block_excl_scan(threadIdx.x < nbins ? dtot[threadIdx.x] : 0u, wsum, all);
+        if (threadIdx.x < nbins) run[threadIdx.x] = dbase + offs[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    }
     const uint64_t lt = (1ull << lane) - 1ull;
     for (int64_t base = b0; base < b1; base += SORT_TILE) {
         for (int i = threadIdx.x; i < 4 * 256; i += NT) (&cnt[0][0])[i] = 0u;
@@ -269,6 +301,11 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
             const uint32_t pos = run[d] + (uint32_t)i - texcl[d];
             if ((int64_t)pos >= n) continue;  // never, for consistent counts; keeps writes in bounds
             const uint32_t v = sval[i];
+            if (kGather == 2) {
+                reinterpret_cast<uint2*>(gout)[pos] = reinterpret_cast<const uint2*>(gsrc)[v];
+                reinterpret_cast<uint2*>(vout)[pos] = make_uint2(2u * v, 2u * v + 1u);
+                continue;
+            }
             if (kGather) gout[pos] = gsrc[v];
             else kout[pos] = k;
             vout[pos] = v;
@@ -281,15 +318,20 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
 
 template <typename K>
 void launch_scatter(int bits, const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, const int32_t* n_dev,
-                    int64_t n_host, int shift, const uint32_t* offs, const uint32_t* gsrc, uint32_t* gout,
-                    hipStream_t st) {
+                    int64_t n_host, int shift, const uint32_t* offs, const uint32_t* dtot, const uint32_t* gsrc,
+                    uint32_t* gout, bool pairs, hipStream_t st) {
+    if (gout && pairs && bits == 8) {  // the depth sort's last pass
+        hipLaunchKernelGGL((k_radix_scatter<K, 8, 2>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, n_dev,
+                           n_host, shift, offs, dtot, gsrc, gout);
+        return;
+    }
 #define GSC_SCATTER(B)                                                                                               \
     if (gout)                                                                                                        \
-        hipLaunchKernelGGL((k_radix_scatter<K, B, true>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, \
-                           n_dev, n_host, shift, offs, gsrc, gout);                                                  \
+        hipLaunchKernelGGL((k_radix_scatter<K, B, 1>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout,    \
+                           n_dev, n_host, shift, offs, dtot, gsrc, gout);                                            \
     else                                                                                                             \
-        hipLaunchKernelGGL((k_radix_scatter<K, B, false>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout, \
-                           n_dev, n_host, shift, offs, gsrc, gout)
+        hipLaunchKernelGGL((k_radix_scatter<K, B, 0>), dim3(kSortBlocks), dim3(NT), 0, st, kin, vin, kout, vout,    \
+                           n_dev, n_host, shift, offs, dtot, gsrc, gout)
     switch (bits) {
         case 1: GSC_SCATTER(1); break;
         case 2: GSC_SCATTER(2); break;
@@ -306,17 +348,17 @@ void launch_scatter(int bits, const K* kin, const uint32_t* vin, K* kout, uint32
 template <typename K>
 hipError_t radix_sort_impl(K* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0, int bit1,
                            uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st, const uint32_t* gsrc,
-                           uint32_t* gout) {
+                           uint32_t* gout, bool pairs) {
+    if (pairs && (!gout || (bit1 - bit0) % 8 != 0)) return hipErrorInvalidValue;
     int cur = 0;
     for (int shift = bit0; shift < bit1; shift += 8) {
         int bits = bit1 - shift < 8 ? bit1 - shift : 8;
         hipLaunchKernelGGL(k_radix_hist<K>, dim3(kSortBlocks), dim3(NT), 0, st, keys[cur], n_dev, n_host, shift,
                            bits, hist);
-        hipError_t e = scan_u32(hist, hist, nullptr, (int64_t)(1 << bits) * kSortBlocks, nullptr, block_sums, st);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << bits), dim3(NT), 0, st, hist, block_sums);
         const bool last = shift + 8 >= bit1;
         launch_scatter<K>(bits, keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, n_host, shift, hist,
-                          last ? gsrc : nullptr, last ? gout : nullptr, st);
+                          block_sums, last ? gsrc : nullptr, last ? gout : nullptr, last && pairs, st);
         cur ^= 1;
     }
     *which = cur;
@@ -341,20 +383,21 @@ hipError_t compact_u32(const uint32_t* flags, const int32_t* n_dev, int64_t n_ho
 
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st,
-                          const uint32_t* gsrc, uint32_t* gout) {
-    return radix_sort_impl<uint32_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, gsrc, gout);
+                          const uint32_t* gsrc, uint32_t* gout, bool pairs) {
+    return radix_sort_impl<uint32_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, gsrc, gout,
+                                     pairs);
 }
 
 hipError_t radix_sort_u16(uint16_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
     return radix_sort_impl<uint16_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, nullptr,
-                                     nullptr);
+                                     nullptr, false);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const int32_t* n_dev, int64_t n_host, int bit0,
                           int bit1, uint32_t* hist, uint32_t* block_sums, int* which, hipStream_t st) {
     return radix_sort_impl<uint64_t>(keys, vals, n_dev, n_host, bit0, bit1, hist, block_sums, which, st, nullptr,
-                                     nullptr);
+                                     nullptr, false);
 }
 
 }  // namespace gsc
