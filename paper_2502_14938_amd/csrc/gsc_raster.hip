@@ -580,21 +580,24 @@ __global__ __launch_bounds__(NT) void k_tall_rowmap(const uint32_t* __restrict__
 
 // One wave per 64 consecutive stored rows of the tall footprints (a
 // footprint's rows are consecutive, and so are their output ranges): each
-// lane takes one row (its span, first tile and output offset: the entry's
+// lane loads one row (its span, first tile and output offset: the entry's
 // offset, stored by k_dup_rows, plus the pairs of its earlier rows, stored
-// by k_tall_count), then the wave writes the 64 rows' pairs together, lane j
-// taking pairs j, j + 64, ... (consecutive lanes, consecutive slots within a
-// row).  A large footprint's rows spread over as many waves as they fill.
+// by k_tall_count) into LDS; then the wave writes the rows' pairs, kBigGW
+// lanes per row, 64 / kBigGW rows at a time: lane s of a group takes pairs
+// s, s + kBigGW, ... of its row (consecutive lanes, consecutive slots).  No
+// lane searches for its row, so the stores follow each other without LDS
+// round trips in between.  A large footprint's rows spread over as many
+// waves as they fill.
+constexpr int kBigGW = 16;
 template <bool kFull>
 __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_e,
                                                 const uint32_t* __restrict__ rowoff, const int32_t* __restrict__ rowmap,
                                                 const uint32_t* __restrict__ rowpre) {
-    __shared__ uint32_t s_ex[NT / 64][64];     // pairs before each of the wave's 64 rows
-    __shared__ uint32_t s_first[NT / 64][64];  // global tile id of each row's first tile
-    __shared__ uint32_t s_out[NT / 64][64];    // output position of each row's first pair
-    __shared__ uint32_t s_e[NT / 64][64];      // entry of each row
-    __shared__ uint32_t s_low[NT / 64][64];    // depth bits of each row's entry (full keys)
+    constexpr int NG = 64 / kBigGW;               // rows written at a time
+    __shared__ uint4 s_row[NT / 64][64];           // (first tile, pairs, output offset, entry) of each row
+    __shared__ uint32_t s_low[NT / 64][kFull ? 64 : 1];  // depth bits of each row's entry (full keys)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int grp = lane / kBigGW, sub = lane % kBigGW;
     int64_t nr = d.rc->n_rows;
     if (nr > d.span_cap) nr = d.span_cap;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -618,26 +621,20 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
                 low = kFull ? d.dkey[e] : 0u;
             }
         }
-        uint32_t tot;
-        const uint32_t ex = wave_excl_scan(np, tot);
-        s_ex[w][lane] = ex;
-        s_first[w][lane] = first;
-        s_out[w][lane] = out;
-        s_e[w][lane] = e;
-        s_low[w][lane] = low;
+        s_row[w][lane] = make_uint4(first, np, out, e);
+        if (kFull) s_low[w][lane] = low;
         __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
-        // lane j's row: the last one whose prefix is <= j (rows without pairs
-        // share the next row's prefix, rows past the end hold the total)
-        for (uint32_t j = lane; j < tot; j += 64) {
-            int lo2 = 0, hi2 = 63;
-            while (lo2 < hi2) {
-                const int mid = (lo2 + hi2 + 1) >> 1;
-                if (s_ex[w][mid] <= j) lo2 = mid;
-                else hi2 = mid - 1;
+        const uint64_t m = __ballot(np != 0u);
+        if (m) {
+            const int ng = (63 - __builtin_clzll(m)) / NG + 1;  // row groups up to the last non-empty row
+            uint4 nxt = s_row[w][grp];
+            for (int g = 0; g < ng; ++g) {
+                const uint4 rr = nxt;
+                const uint32_t lw = kFull ? s_low[w][NG * g + grp] : 0u;
+                if (g + 1 < ng) nxt = s_row[w][NG * (g + 1) + grp];
+                for (uint32_t k = (uint32_t)sub; k < rr.y; k += kBigGW)
+                    put_pair<kFull>(d, (int64_t)rr.z + k, rr.x + k, rr.w, (uint64_t)lw);
             }
-            const uint32_t k = j - s_ex[w][lo2];
-            put_pair<kFull>(d, (int64_t)s_out[w][lo2] + k, s_first[w][lo2] + k, s_e[w][lo2],
-                            (uint64_t)s_low[w][lo2]);
         }
         __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
     }
