@@ -264,6 +264,10 @@ struct PreArgs {
 // loads of an entry)
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(PreArgs p) {
     __shared__ uint32_t s_wtall[NT / 64];
+    // the block's records, copied out together once complete (whole lines,
+    // coalesced: a record written in two halves far apart in time would
+    // leave half-written lines for the L2 to evict)
+    __shared__ float4 s_rec[NT * kRec];
     __shared__ int32_t s_base[kMaxSeg + 1];
     __shared__ int32_t s_ne;
     if (threadIdx.x == 0) {
@@ -360,8 +364,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 }
             }
             // the projected record now: its registers are free for the row spans
-            p.rec[kRec * e] = A;
-            p.rec[kRec * e + 1] = B;
+            s_rec[kRec * threadIdx.x] = A;
+            s_rec[kRec * threadIdx.x + 1] = B;
             if (y1 - y0 + 1 <= kSmallRows) {
 #pragma unroll
                 for (int i = 0; i < kSmallRows; ++i) {
@@ -376,6 +380,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // tall footprints (more than kSmallRows tile rows) are counted later,
         // one thread per row (k_tall_rows); list them in this chunk's slots
         const bool tall = valid && y1 - y0 + 1 > kSmallRows;
+        if (valid) {
+            rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
+            s_rec[kRec * threadIdx.x + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
+                                                        __uint_as_float(count));
+            s_rec[kRec * threadIdx.x + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
+                                                        __uint_as_float(spans[2]), __uint_as_float(spans[3]));
+            p.ntiles[e] = count;
+            if (!p.shared_depth) {
+                p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
+                p.dval[e] = (uint32_t)e;
+            }
+        }
         const uint64_t m = __ballot(tall);
         if (lane == 0) s_wtall[threadIdx.x >> 6] = (uint32_t)__popcll(m);
         __syncthreads();
@@ -390,19 +406,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             for (int q = 0; q < NT / 64; ++q) n += s_wtall[q];
             p.tall_cnt[chunk] = (int32_t)n;
         }
-        __syncthreads();  // s_wtall is rewritten by the next step
-        if (valid) {
-            rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
-            p.rec[kRec * e + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
-                                              __uint_as_float(count));
-            p.rec[kRec * e + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
-                                              __uint_as_float(spans[2]), __uint_as_float(spans[3]));
-            p.ntiles[e] = count;
-            if (!p.shared_depth) {
-                p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
-                p.dval[e] = (uint32_t)e;
-            }
+        {
+            const int nv = (int)(ne - base < NT ? ne - base : NT);
+            float4* dst = p.rec + kRec * base;
+            for (int i = threadIdx.x; i < kRec * nv; i += NT) dst[i] = s_rec[i];
         }
+        __syncthreads();  // s_wtall and s_rec are rewritten by the next step
         if (p.shared_depth) {
             // The eyes' entries 2j, 2j+1 sit in neighbouring lanes.  With one
             // rotation for both eyes their view depths differ by a constant,
