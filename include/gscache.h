@@ -252,15 +252,21 @@ int gsc_reset_cache(gsc_ctx* ctx);
 #define GSC_DBG_MISSES 1    /* int32 [n_miss] anchor ids, ascending */
 #define GSC_DBG_GAUSS 2     /* int32 [n_gauss] (visible position * k + j) of the render buffer */
 #define GSC_DBG_DERIVED 3   /* float32 [n_gauss, 13]: mu3 cov6 rgb3 alpha, render-buffer order */
-#define GSC_DBG_PAIRS 4     /* int32 [n_pairs(eye), 2]: (tile, render-buffer index), sorted order */
-#define GSC_DBG_RANGES 5    /* int32 [n_tiles(eye), 2]: [start, end) per tile */
+#define GSC_DBG_PAIRS 4     /* int32 [n_pairs(eye), 2]: (tile, render-buffer index), each tile's
+                               depth-ordered list as the blend reads it, tiles in order */
+#define GSC_DBG_RANGES 5    /* int32 [n_tiles(eye), 2]: [start, end) of each tile's list in the above */
 #define GSC_DBG_PREPROC 6   /* float32 [n_gauss, 8]: mean2d.x, .y, conic a b c, alpha, depth,
                                tile count (as float) for eye */
 #define GSC_DBG_DEPTH 7     /* int32 [1]: current reuse depth */
-#define GSC_DBG_SORT_KEYS 8 /* uint32 [pairs of every image of the last raster batch]: the sorted
-                               tile keys (global tile ids, images in order), as the tile ranges read them */
-#define GSC_DBG_RAW_RANGES 9 /* int32 [global tiles, 2]: [start, end) of every tile in the sorted keys
-                               as the blend reads them ([0, 0) for a tile without pairs) */
+#define GSC_DBG_SORT_KEYS 8 /* uint32 [sorted items of the last raster batch]: the sorted keys, global
+                               super-tile ids (a super tile is 2x2 tiles; images in order), as the
+                               ranges read them */
+#define GSC_DBG_RAW_RANGES 9 /* int32 [global super tiles, 2]: [start, end) of every super tile in the
+                               sorted keys ([0, 0) for one without pairs) */
+#define GSC_DBG_SORT_VALS 10 /* uint32 [sorted items]: entry | mask << 28, the mask's bit
+                               2 (ty & 1) + (tx & 1) set for each tile of the super tile the entry's
+                               footprint covers; a tile's list (GSC_DBG_PAIRS) is its super tile's
+                               list filtered by its bit */
 /* Copies at most cap elements (of the unit above: ints, floats or rows) to
  * host_dst and writes the full count to *n. */
 int gsc_debug_copy(gsc_ctx* ctx, int what, int eye, void* host_dst, int64_t cap, int64_t* n);

@@ -22,7 +22,7 @@ PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 FLAG_DEREDUNDANCY, FLAG_REUSE, FLAG_PREDICTOR, FLAG_FULL_KEY_SORT, FLAG_LOD_FADE = 1, 2, 4, 8, 16
 GUIDE = {"linear": 0, "fixed": 1, "exp": 2, "staged": 3}
 DBG = {"visible": 0, "misses": 1, "gauss": 2, "derived": 3, "pairs": 4, "ranges": 5, "preproc": 6, "depth": 7,
-       "sort_keys": 8, "raw_ranges": 9}
+       "sort_keys": 8, "raw_ranges": 9, "sort_vals": 10}
 PRED_NPARAMS = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1  # 4673
 
 
@@ -297,7 +297,7 @@ class Renderer:
                      "derived": ((cnt, 13), np.float32), "pairs": ((cnt, 2), np.int32),
                      "ranges": ((cnt, 2), np.int32), "preproc": ((cnt, 8), np.float32),
                      "depth": ((cnt,), np.int32), "sort_keys": ((cnt,), np.uint32),
-                     "raw_ranges": ((cnt, 2), np.int32)}[what]
+                     "raw_ranges": ((cnt, 2), np.int32), "sort_vals": ((cnt,), np.uint32)}[what]
         out = np.zeros(shape, dt)
         if cnt:
             self._check(L.gsc_debug_copy(self.h, code, eye, out.ctypes.data, cnt, C.byref(n)))

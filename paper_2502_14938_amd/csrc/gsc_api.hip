@@ -625,6 +625,83 @@ int gsc_sync(gsc_ctx* c) {
     return GSC_OK;
 }
 
+}  // extern "C"
+
+namespace gsc {
+namespace {
+
+// One image's depth-ordered tile lists, as the blend reads them: tile t's
+// list is its super tile's sorted list filtered by the tile's mask bit.
+// Fills the lists' concatenation in tile order (sorted pair values: entry |
+// mask << kMaskShift) and start[t] (start[ntiles] = total).
+hipError_t image_tile_lists(const SegTable& last, const Raster& R, int eye, std::vector<uint32_t>& vals,
+                            std::vector<int64_t>& start) {
+    SegTable tab = last;
+    seg_supers(tab);
+    const Seg& s = tab.s[eye];
+    const int64_t nsup = (int64_t)s.nsx * s.nsy;
+    std::vector<int32_t> rg(2 * (size_t)nsup);
+    hipError_t e = hipMemcpy(rg.data(), R.ranges + 2 * (int64_t)s.sup_base, rg.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    // the image's super tiles are consecutive ids, so their lists form one
+    // contiguous span of the sorted values
+    int64_t lo = -1, hi = -1;
+    for (int64_t q = 0; q < nsup; ++q)
+        if (rg[2 * q + 1] > rg[2 * q]) {
+            if (lo < 0) lo = rg[2 * q];
+            hi = rg[2 * q + 1];
+        }
+    std::vector<uint32_t> sv(lo < 0 ? 0 : (size_t)(hi - lo));
+    if (!sv.empty()) {
+        e = hipMemcpy(sv.data(), R.pval[R.sorted_buf] + lo, sv.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+    }
+    vals.clear();
+    start.assign((size_t)s.ntx * s.nty + 1, 0);
+    for (int ty = 0; ty < s.nty; ++ty)
+        for (int tx = 0; tx < s.ntx; ++tx) {
+            const int64_t q = (int64_t)(ty >> kSupShift) * s.nsx + (tx >> kSupShift);
+            const uint32_t bit = 1u << (kMaskShift + ((ty & 1) << 1) + (tx & 1));
+            start[(size_t)ty * s.ntx + tx] = (int64_t)vals.size();
+            for (int64_t i = rg[2 * q]; i < rg[2 * q + 1]; ++i)
+                if (sv[(size_t)(i - lo)] & bit) vals.push_back(sv[(size_t)(i - lo)]);
+        }
+    start.back() = (int64_t)vals.size();
+    return hipSuccess;
+}
+
+// Tile pairs of each image of the last stereo batch (the sum of its entries'
+// tile counts), for the frame statistics.
+hipError_t image_tile_pairs(const SegTable& tab, const Raster& R, const RasterCounters& r, int64_t out[2]) {
+    out[0] = out[1] = 0;
+    const int64_t ne = r.n_entries;
+    if (ne <= 0) return hipSuccess;
+    std::vector<uint32_t> nt((size_t)ne);
+    hipError_t e = hipMemcpy(nt.data(), R.ntiles, nt.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    const int64_t stride = r.entry_stride > 1 ? r.entry_stride : 1;
+    for (int sg = 0; sg < tab.n && sg < 2; ++sg) {
+        int64_t b0, b1;
+        if (stride > 1) {  // the pair (sg & ~1, sg | 1) interleaves its two images' entries
+            const int q = sg & ~1;
+            b0 = r.entry_base[q] + (sg & 1);
+            b1 = r.entry_base[q + 2];
+        } else {
+            b0 = r.entry_base[sg];
+            b1 = r.entry_base[sg + 1];
+        }
+        int64_t n = 0;
+        for (int64_t i = b0; i < b1 && i < ne; i += stride) n += nt[(size_t)i];
+        out[sg] = n;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace gsc
+
+extern "C" {
+
 int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     if (!c || !st) return fail(c, GSC_E_INVALID_ARG, "gsc_get_stats: null argument");
     std::memset(st, 0, sizeof(*st));
@@ -640,16 +717,11 @@ int gsc_get_stats(gsc_ctx* c, gsc_frame_stats* st) {
     st->n_miss = k.n_miss;
     st->n_gauss = k.n_gauss;
     if (c->rendered && !c->explicit_render && c->last_tab.total_tiles > 0) {
-        // pairs per eye: the lengths of its tiles' runs
-        std::vector<int32_t> rg(2 * (size_t)c->last_tab.total_tiles);
-        HIP_OR_FAIL(c, hipMemcpy(rg.data(), SR.ranges, rg.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-        for (int sg = 0; sg < c->last_tab.n && sg < 2; ++sg) {
-            const Seg& g = c->last_tab.s[sg];
-            int64_t n = 0;
-            for (int t = 0; t < g.ntx * g.nty; ++t)
-                n += rg[2 * (size_t)(g.tile_base + t) + 1] - rg[2 * (size_t)(g.tile_base + t)];
-            st->n_pairs[sg] = n;
-        }
+        // tile pairs per eye: the sum of its entries' tile counts
+        int64_t np[2];
+        HIP_OR_FAIL(c, image_tile_pairs(c->last_tab, SR, r, np));
+        st->n_pairs[0] = np[0];
+        st->n_pairs[1] = np[1];
     }
     st->n_evicted = k.n_evict;
     st->depth_used = k.depth_used;
@@ -863,39 +935,30 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
             if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
             const SegTable& tab = c->last_tab;
             if (eye >= tab.n) return fail(c, GSC_E_INVALID_ARG, "gsc_debug_copy: no such eye");
-            int32_t total = r.n_pairs < R.max_pairs ? r.n_pairs : (int32_t)R.max_pairs;
-            std::vector<int32_t> ranges(2 * (size_t)tab.total_tiles);
-            HIP_OR_FAIL(c, hipMemcpy(ranges.data(), R.ranges, ranges.size() * 4, hipMemcpyDeviceToHost));
             const Seg& s = tab.s[eye];
-            int64_t lo = -1, hi = -1;
-            for (int64_t t = s.tile_base; t < s.tile_base + (int64_t)s.ntx * s.nty; ++t)
-                if (ranges[2 * t + 1] > ranges[2 * t]) {
-                    if (lo < 0) lo = ranges[2 * t];
-                    hi = ranges[2 * t + 1];
-                }
-            count = lo < 0 ? 0 : hi - lo;
+            std::vector<uint32_t> val;
+            std::vector<int64_t> st0;
+            HIP_OR_FAIL(c, image_tile_lists(tab, R, eye, val, st0));
+            count = (int64_t)val.size();
             int64_t m = count < cap ? count : cap;
             if (m <= 0) break;
-            std::vector<uint32_t> val(m);
-            HIP_OR_FAIL(c, hipMemcpy(val.data(), R.pval[R.sorted_buf] + lo, m * 4,
-                                     hipMemcpyDeviceToHost));
-            std::vector<int32_t> tile_of(m);
-            for (int64_t t = s.tile_base; t < s.tile_base + (int64_t)s.ntx * s.nty; ++t)
-                for (int64_t i = ranges[2 * t]; i < ranges[2 * t + 1]; ++i)
-                    if (i - lo < m) tile_of[i - lo] = (int32_t)(t - s.tile_base);
             if (R.order) {  // pair values are depth ranks: map them back to entries
                 int32_t ne = r.n_entries;
                 std::vector<uint32_t> ord(ne > 0 ? ne : 1);
                 if (ne > 0) HIP_OR_FAIL(c, hipMemcpy(ord.data(), R.order, (size_t)ne * 4, hipMemcpyDeviceToHost));
-                for (int64_t i = 0; i < m; ++i) val[i] = val[i] < (uint32_t)ne ? ord[val[i]] : 0xffffffffu;
+                for (auto& v : val) {
+                    const uint32_t x = v & kEntryMask;
+                    v = x < (uint32_t)ne ? ord[x] : kEntryMask;
+                }
             }
             int32_t* o = (int32_t*)dst;
             const uint32_t stride = r.entry_stride > 1 ? (uint32_t)r.entry_stride : 1u;
-            for (int64_t i = 0; i < m; ++i) {
-                o[2 * i] = tile_of[i];
-                o[2 * i + 1] = (int32_t)((val[i] - (uint32_t)r.entry_base[eye]) / stride);
-            }
-            (void)total;
+            int64_t i = 0;
+            for (int64_t t = 0; t < (int64_t)s.ntx * s.nty && i < m; ++t)
+                for (int64_t j = st0[(size_t)t]; j < st0[(size_t)t + 1] && i < m; ++j, ++i) {
+                    o[2 * i] = (int32_t)t;
+                    o[2 * i + 1] = (int32_t)(((val[(size_t)j] & kEntryMask) - (uint32_t)r.entry_base[eye]) / stride);
+                }
             break;
         }
         case GSC_DBG_RANGES: {
@@ -906,17 +969,14 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
             count = (int64_t)s.ntx * s.nty;
             int64_t m = count < cap ? count : cap;
             if (m <= 0) break;
-            std::vector<int32_t> rg(2 * m);
-            HIP_OR_FAIL(c, hipMemcpy(rg.data(), R.ranges + 2 * (int64_t)s.tile_base, 2 * m * 4,
-                                     hipMemcpyDeviceToHost));
-            int32_t base = -1;
-            for (int64_t t = 0; t < count && t < m; ++t)
-                if (rg[2 * t + 1] > rg[2 * t]) { base = rg[2 * t]; break; }
+            std::vector<uint32_t> val;
+            std::vector<int64_t> st0;
+            HIP_OR_FAIL(c, image_tile_lists(tab, R, eye, val, st0));
             int32_t* o = (int32_t*)dst;
             for (int64_t t = 0; t < m; ++t) {
-                bool empty = rg[2 * t + 1] <= rg[2 * t];
-                o[2 * t] = empty ? 0 : rg[2 * t] - base;
-                o[2 * t + 1] = empty ? 0 : rg[2 * t + 1] - base;
+                const bool empty = st0[(size_t)t + 1] <= st0[(size_t)t];
+                o[2 * t] = empty ? 0 : (int32_t)st0[(size_t)t];
+                o[2 * t + 1] = empty ? 0 : (int32_t)st0[(size_t)t + 1];
             }
             break;
         }
@@ -973,9 +1033,20 @@ int gsc_debug_copy(gsc_ctx* c, int what, int eye, void* dst, int64_t cap, int64_
             }
             break;
         }
+        case GSC_DBG_SORT_VALS: {
+            if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
+            int32_t ns = 0;
+            HIP_OR_FAIL(c, hipMemcpy(&ns, R.n_sort, sizeof(int32_t), hipMemcpyDeviceToHost));
+            count = ns;
+            int64_t m = count < cap ? count : cap;
+            if (m > 0) HIP_OR_FAIL(c, hipMemcpy(dst, R.pval[R.sorted_buf], m * 4, hipMemcpyDeviceToHost));
+            break;
+        }
         case GSC_DBG_RAW_RANGES: {
             if (!c->rendered) return fail(c, GSC_E_NOT_LOADED, "gsc_debug_copy: nothing rendered");
-            count = c->last_tab.total_tiles;
+            SegTable tab = c->last_tab;
+            seg_supers(tab);
+            count = tab.total_sup;
             int64_t m = count < cap ? count : cap;
             if (m > 0) HIP_OR_FAIL(c, hipMemcpy(dst, R.ranges, 2 * m * 4, hipMemcpyDeviceToHost));
             break;

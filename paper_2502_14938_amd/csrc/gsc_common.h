@@ -13,6 +13,14 @@
 namespace gsc {
 
 constexpr int kTile = 16;             // 16x16 pixel tiles
+// Binning unit of the sort: a super tile of 2x2 tiles (32x32 pixels).  A
+// (super tile, entry) pair carries in its value the entry id and a 4-bit
+// mask of the tiles of the super tile the footprint covers (bit
+// 2 (ty & 1) + (tx & 1)); each tile's depth-ordered list is its super
+// tile's list filtered by its bit.
+constexpr int kSupShift = 1;          // log2 tiles per super-tile side
+constexpr int kMaskShift = 28;        // value = entry | mask << kMaskShift
+constexpr uint32_t kEntryMask = (1u << kMaskShift) - 1u;
 constexpr int kBlendThreads = 64;     // one wave per 16x16 tile, four pixels per thread (blend)
 constexpr int kBlendBatch = 128;      // Gaussians staged in LDS per step (blend)
 constexpr int kBlendRun = 128;        // consecutive tiles one XCD takes in a row (blend)
@@ -50,7 +58,7 @@ struct RasterCounters {
     int32_t n_entries;            // total (segment, Gaussian) entries
     int32_t entry_base[kMaxSeg + 1];  // entry of Gaussian 0 of each segment (total last)
     int32_t entry_stride;             // 2 with paired segments, else 1
-    int32_t n_pairs;              // total tile pairs (all segments)
+    int32_t n_pairs;              // total (super tile, entry) pairs (all segments): the sorted items
     int32_t n_echunks;            // chunks of 256 entries (preprocess tall lists)
     int32_t n_tall_e;             // tall entries found by the preprocess
     int32_t n_rows;               // their tile rows (stored spans)
@@ -72,6 +80,8 @@ struct Seg {
     int32_t k;                   // entries per cache line
     int32_t W, H, ntx, nty;
     int32_t tile_base;  // first global tile id of this image
+    int32_t sup_base;   // first global super-tile id of this image (set by raster_batch)
+    int32_t nsx, nsy;   // super tiles per row and column
     float R[9];
     double pos[3];      // eye position (FP64: subtracted from FP32 anchor positions)
     float fx, fy, cx, cy, limx, limy, znear;
@@ -93,7 +103,7 @@ struct SegTable {
     int32_t n;
     int32_t total_tiles;
     int32_t paired;
-    int32_t pad;
+    int32_t total_sup;  // super tiles of all images (set by raster_batch)
     Seg s[kMaxSeg];
 };
 
@@ -179,7 +189,8 @@ struct Raster {
     uint32_t* rowpre = nullptr;   // [span_cap] pairs of the footprint's rows before each stored span
     int64_t span_cap = 0;
     uint32_t* ntiles = nullptr; // tile count per entry
-    uint32_t* scnt = nullptr;   // tile count per depth rank
+    uint32_t* nsup = nullptr;   // (super tile, entry) pair count per entry
+    uint32_t* scnt = nullptr;   // pair count per depth rank
     int32_t* n_sort = nullptr;  // [1] pairs to sort (clamped to capacity)
     uint32_t* dkey[2] = {nullptr, nullptr};  // depth keys (double buffer)
     uint32_t* dval[2] = {nullptr, nullptr};  // entry ids
@@ -302,6 +313,9 @@ inline dim3 grid_fit(K* kernel, int64_t n, int threads = 256) {
 
 // Fill a segment's camera fields from a public camera.
 void seg_camera(Seg& s, const gsc_camera& c);
+// Super-tile geometry of every segment (sup_base, nsx, nsy) and the total,
+// from the segments' tile grids, in segment order.
+void seg_supers(SegTable& tab);
 
 // Predictor kernels.
 hipError_t pred_forward_bwd(const float* w, const float* X, const float* y, int n, float pos_weight, float* grads,

@@ -45,7 +45,7 @@ template <class Fn>
 hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int64_t max_tiles, bool full_key, Fn&& A) {
     hipError_t e;
 #define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
-    A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.scnt, max_entries);
+    A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.nsup, max_entries); A_(r.scnt, max_entries);
     A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
     A_(r.pt_dense, max_entries); A_(r.pt_rowcnt, max_entries); A_(r.pt_rowoff, max_entries);
     A_(r.spans, 2 * max_entries); A_(r.rowmap, 2 * max_entries); A_(r.rowpre, 2 * max_entries);

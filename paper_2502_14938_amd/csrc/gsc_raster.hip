@@ -238,10 +238,56 @@ __device__ __forceinline__ float lod_fade_weight(float4 ap, int l, const Seg& s)
     return fminf(fmaxf(2.f - d / ldexpf(s.d_ref, -l), 0.f), 1.f);
 }
 
+// Span word of a tile row: lo | hi << 16, hi < lo (0xffff, 0) when empty.
+__device__ __forceinline__ int span_lo(uint32_t sp) { return (int)(sp & 0xffffu); }
+__device__ __forceinline__ int span_hi(uint32_t sp) { return (int)(sp >> 16); }
+
+// Super-tile columns [x0, x1] of a super row from the spans of its two tile
+// rows a (even) and b (odd), either possibly empty: the hull of the rows'
+// super columns (a convex footprint's rows give adjacent or overlapping
+// ranges; a column of the hull whose mask is empty is emitted with mask 0,
+// which no tile reads).  Returns the column count (0: both rows empty).
+__device__ __forceinline__ uint32_t sup_cols(uint32_t sa, uint32_t sb, int& x0) {
+    int lo = 0x7fffffff, hi = -1;
+    if (span_hi(sa) >= span_lo(sa)) { lo = span_lo(sa) >> kSupShift; hi = span_hi(sa) >> kSupShift; }
+    if (span_hi(sb) >= span_lo(sb)) {
+        lo = min(lo, span_lo(sb) >> kSupShift);
+        hi = max(hi, span_hi(sb) >> kSupShift);
+    }
+    x0 = lo;
+    return hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+}
+
+// Mask of the tiles of super column x covered by tile rows a and b: bit
+// 2 (ty & 1) + (tx & 1).
+__device__ __forceinline__ uint32_t sup_mask(uint32_t sa, uint32_t sb, int x) {
+    const int t0 = x << kSupShift, t1 = t0 + 1;
+    const int la = span_lo(sa), ha = span_hi(sa), lb = span_lo(sb), hb = span_hi(sb);
+    return (uint32_t)(la <= t0 && t0 <= ha) | ((uint32_t)(la <= t1 && t1 <= ha) << 1) |
+           ((uint32_t)(lb <= t0 && t0 <= hb) << 2) | ((uint32_t)(lb <= t1 && t1 <= hb) << 3);
+}
+
+constexpr uint32_t kEmptySpan = 0x0000ffffu;
+
+// Super pairs of a footprint of at most kSmallRows tile rows from y0 (row i
+// at y0 + i, empty rows past the footprint): its super rows are the pairs
+// (2 Y, 2 Y + 1) of tile rows.
+__device__ __forceinline__ uint32_t small_sup_count(const uint32_t (&sp)[4], int y0) {
+    uint32_t n = 0;
+    // super row of row 0 holds rows 0 and 1 when y0 is even, row 0 alone (as
+    // its row b) when y0 is odd; then rows (1, 2) or (2, 3), and so on
+    const int odd = y0 & 1;
+    int x0;
+    n += sup_cols(odd ? kEmptySpan : sp[0], odd ? sp[0] : sp[1], x0);
+    n += sup_cols(odd ? sp[1] : sp[2], odd ? sp[2] : sp[3], x0);
+    if (odd) n += sup_cols(sp[3], kEmptySpan, x0);
+    return n;
+}
+
 // Per-entry record, 4 x float4 (64 B, one cache line):
 //   A = (mean2d.x, mean2d.y, conic a, conic b)
 //   B = (conic c, alpha, r, g)
-//   C = (b, bits: tile rows y0 | y1 << 16, bits: segment, bits: tile count)
+//   C = (b, bits: tile rows y0 | y1 << 16, bits: segment, bits: (super tile, entry) pair count)
 //   D = bits: exact tile span lo | hi << 16 of each of up to kSmallRows rows
 //       (footprints of at most kSmallRows tile rows; hi < lo: empty row)
 constexpr int kRec = 4;
@@ -250,6 +296,7 @@ struct PreArgs {
     RasterCounters* rc;
     float4* rec;
     uint32_t* ntiles;
+    uint32_t* nsup;
     uint32_t* dkey;
     uint32_t* dval;
     int32_t* tall_list;  // tall entries of each chunk of 256 entries, in the chunk's slots
@@ -292,7 +339,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int64_t e = base + threadIdx.x;
         const bool valid = e < ne;
         int si = 0;
-        uint32_t count = 0, rows = 0;
+        uint32_t count = 0, scount = 0, rows = 0;
         float depth = 0.f;
         float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = make_float4(0.f, 0.f, 0.f, 0.f);
         float lb = 0.f;
@@ -375,6 +422,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     else lo = 0xffff, hi = 0;
                     spans[i] = (uint32_t)lo | ((uint32_t)hi << 16);
                 }
+                scount = small_sup_count(spans, y0);
             }
         }
         // tall footprints (more than kSmallRows tile rows) are counted later,
@@ -383,10 +431,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (valid) {
             rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
             s_rec[kRec * threadIdx.x + 2] = make_float4(lb, __uint_as_float(rows), __uint_as_float((uint32_t)si),
-                                                        __uint_as_float(count));
+                                                        __uint_as_float(scount));
             s_rec[kRec * threadIdx.x + 3] = make_float4(__uint_as_float(spans[0]), __uint_as_float(spans[1]),
                                                         __uint_as_float(spans[2]), __uint_as_float(spans[3]));
             p.ntiles[e] = count;
+            p.nsup[e] = scount;
             if (!p.shared_depth) {
                 p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
                 p.dval[e] = (uint32_t)e;
@@ -429,17 +478,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
+// Super-tile grid of one segment, as the pair emission needs it.
+struct SupGeo {
+    int32_t base;  // first global super-tile id
+    int32_t nsx;   // super tiles per row
+};
+
 struct DupArgs {
-    SegTable tab;
+    SupGeo sg[kMaxSeg];
     RasterCounters* rc;
     const uint32_t* order;   // depth rank -> entry (depth-presorted mode)
     const uint32_t* offs;    // pair offset per rank (per entry in full-key mode)
     float4* rec;             // (k_dup_rows stores a tall entry's output offset in D.y)
     const uint32_t* dkey;    // depth key per entry (full-key mode)
-    uint32_t* key32;         // global tile id (depth-presorted mode, more than 65,536 tiles)
-    uint16_t* key16;         // global tile id (depth-presorted mode, at most 65,536 tiles)
-    uint64_t* key64;         // (global tile << 32 | depth bits) (full-key mode)
-    uint32_t* val;           // entry id
+    uint32_t* key32;         // global super-tile id (depth-presorted mode, more than 65,536 super tiles)
+    uint16_t* key16;         // global super-tile id (depth-presorted mode, at most 65,536 super tiles)
+    uint64_t* key64;         // (global super tile << 32 | depth bits) (full-key mode)
+    uint32_t* val;           // entry id | tile mask << kMaskShift
     int64_t max_pairs;
     int32_t* n_sort;         // pairs to sort (set by k_dup_rows)
     const uint32_t* spans;   // row spans of the tall footprints
@@ -484,9 +539,14 @@ __device__ __forceinline__ void pairs_clamp(RasterCounters* rc, int32_t* n_sort,
 
 template <bool kFull>
 __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
-    // per thread (entry): pairs before each row's end, first tile id of each row
-    __shared__ uint32_t s_cum[kSmallRows][NT];
-    __shared__ uint32_t s_first[kSmallRows][NT];
+    constexpr int SR = 3;  // super rows of a footprint of at most kSmallRows tile rows
+    // per thread (entry) and super row: pairs before the row's end, super
+    // tile of its first column, first column, spans of its two tile rows
+    __shared__ uint32_t s_cum[SR][NT];
+    __shared__ uint32_t s_first[SR][NT];
+    __shared__ int32_t s_x0[SR][NT];
+    __shared__ uint32_t s_sa[SR][NT];
+    __shared__ uint32_t s_sb[SR][NT];
     __shared__ uint32_t s_start[NT];  // exclusive prefix of the wave's pair counts
     __shared__ uint32_t s_out[NT];    // output offset of the entry
     __shared__ uint32_t s_e[NT];      // entry id
@@ -497,7 +557,9 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ne; base += gstride()) {
         const int64_t r = base + threadIdx.x;
         uint32_t n_here = 0;
-        uint32_t cum[kSmallRows] = {0u, 0u, 0u, 0u}, first[kSmallRows] = {0u, 0u, 0u, 0u};
+        uint32_t cum[SR] = {0u, 0u, 0u}, first[SR] = {0u, 0u, 0u}, sa[SR] = {kEmptySpan, kEmptySpan, kEmptySpan},
+                 sb[SR] = {kEmptySpan, kEmptySpan, kEmptySpan};
+        int x0[SR] = {0, 0, 0};
         if (r < ne) {
             // two rounds of loads: (depth order, pair offset), then the
             // record's count / rows word and its spans together
@@ -515,14 +577,19 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
                 } else {
                     const uint32_t sp[kSmallRows] = {__float_as_uint(D.x), __float_as_uint(D.y), __float_as_uint(D.z),
                                                      __float_as_uint(D.w)};
-                    const Seg& sg = d.tab.s[__float_as_uint(C.z)];
+                    const SupGeo& sg = d.sg[__float_as_uint(C.z)];
+                    // super row i is Y = y0 / 2 + i: tile rows (0, 1), (2, 3)
+                    // from an even y0; (-, 0), (1, 2), (3, -) from an odd one
+                    const int odd = y0 & 1;
+                    sa[0] = odd ? kEmptySpan : sp[0]; sb[0] = odd ? sp[0] : sp[1];
+                    sa[1] = odd ? sp[1] : sp[2];      sb[1] = odd ? sp[2] : sp[3];
+                    sa[2] = odd ? sp[3] : kEmptySpan; sb[2] = kEmptySpan;
                     uint32_t acc = 0;
 #pragma unroll
-                    for (int i = 0; i < kSmallRows; ++i) {
-                        const int lo = sp[i] & 0xffff, hi = sp[i] >> 16;
-                        acc += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+                    for (int i = 0; i < SR; ++i) {
+                        acc += sup_cols(sa[i], sb[i], x0[i]);
                         cum[i] = acc;
-                        first[i] = (uint32_t)(sg.tile_base + (y0 + i) * sg.ntx + lo);
+                        first[i] = (uint32_t)(sg.base + ((y0 >> kSupShift) + i) * sg.nsx + x0[i]);
                     }
                     n_here = acc;  // equals cnt: the spans are what was counted
                     s_out[threadIdx.x] = out_at;
@@ -532,9 +599,12 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
             }
         }
 #pragma unroll
-        for (int i = 0; i < kSmallRows; ++i) {
+        for (int i = 0; i < SR; ++i) {
             s_cum[i][threadIdx.x] = cum[i];
             s_first[i][threadIdx.x] = first[i];
+            s_x0[i][threadIdx.x] = x0[i];
+            s_sa[i][threadIdx.x] = sa[i];
+            s_sb[i][threadIdx.x] = sb[i];
         }
         uint32_t tot;
         s_start[threadIdx.x] = wave_excl_scan(n_here, tot);
@@ -552,9 +622,10 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
             const uint32_t k = j - s_start[t];
             int row = 0;
 #pragma unroll
-            for (int i = 0; i < kSmallRows - 1; ++i) row += k >= s_cum[i][t] ? 1 : 0;
-            const uint32_t before = row ? s_cum[row - 1][t] : 0u;
-            put_pair<kFull>(d, (int64_t)s_out[t] + k, s_first[row][t] + (k - before), s_e[t], s_low[t]);
+            for (int i = 0; i < SR - 1; ++i) row += k >= s_cum[i][t] ? 1 : 0;
+            const uint32_t kk = k - (row ? s_cum[row - 1][t] : 0u);
+            const uint32_t m = sup_mask(s_sa[row][t], s_sb[row][t], s_x0[row][t] + (int)kk);
+            put_pair<kFull>(d, (int64_t)s_out[t] + k, s_first[row][t] + kk, s_e[t] | (m << kMaskShift), s_low[t]);
         }
         __builtin_amdgcn_wave_barrier();  // before the next step rewrites the wave's LDS
     }
@@ -588,23 +659,25 @@ __global__ __launch_bounds__(NT) void k_tall_rowmap(const uint32_t* __restrict__
 }
 
 // One wave per 64 consecutive stored rows of the tall footprints (a
-// footprint's rows are consecutive, and so are their output ranges): each
-// lane loads one row (its span, first tile and output offset: the entry's
-// offset, stored by k_dup_rows, plus the pairs of its earlier rows, stored
-// by k_tall_count) into LDS; then the wave writes the rows' pairs, kBigGW
-// lanes per row, 64 / kBigGW rows at a time: lane s of a group takes pairs
-// s, s + kBigGW, ... of its row (consecutive lanes, consecutive slots).  No
-// lane searches for its row, so the stores follow each other without LDS
-// round trips in between.  A large footprint's rows spread over as many
-// waves as they fill.
+// footprint's rows are consecutive, and so are their output ranges).  The
+// lane of a row that opens a super row (an even tile row, or the
+// footprint's first row) loads that super row: the spans of its two tile
+// rows (the next stored row is the footprint's next tile row), its columns,
+// first super tile and output offset (the entry's offset, stored by
+// k_dup_rows, plus the pairs of the footprint's earlier super rows, stored
+// by k_tall_count), into LDS; then the wave writes the super rows' pairs,
+// kBigGW lanes per super row, 64 / kBigGW at a time: lane s of a group
+// takes pairs s, s + kBigGW, ... of its super row (consecutive lanes,
+// consecutive slots).  No lane searches for its row, so the stores follow
+// each other without LDS round trips in between.
 constexpr int kBigGW = 16;
 template <bool kFull>
 __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_e,
                                                 const uint32_t* __restrict__ rowoff, const int32_t* __restrict__ rowmap,
                                                 const uint32_t* __restrict__ rowpre) {
-    constexpr int NG = 64 / kBigGW;               // rows written at a time
-    __shared__ uint4 s_row[NT / 64][64];           // (first tile, pairs, output offset, entry) of each row
-    __shared__ uint32_t s_low[NT / 64][kFull ? 64 : 1];  // depth bits of each row's entry (full keys)
+    constexpr int NG = 64 / kBigGW;               // super rows written at a time
+    __shared__ uint4 s_row[NT / 64][64];           // (first super tile, pairs, output offset, entry)
+    __shared__ uint4 s_sp[NT / 64][64];            // (span of tile row a, of tile row b, first column, depth bits)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int grp = lane / kBigGW, sub = lane % kBigGW;
     int64_t nr = d.rc->n_rows;
@@ -613,36 +686,50 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t q0 = wave * 64; q0 < nr; q0 += nwaves * 64) {
         const int64_t q = q0 + lane;
-        uint32_t np = 0, first = 0, out = 0, e = 0, low = 0;
+        uint32_t np = 0, first = 0, out = 0, e = 0, low = 0, sa = kEmptySpan, sb = kEmptySpan;
+        int x0 = 0;
         if (q < nr) {
-            const uint32_t sp = d.spans[q];
-            const int lo = sp & 0xffff, hi = sp >> 16;
-            if (hi >= lo) {
-                const int32_t f = rowmap[q];
-                e = (uint32_t)tall_e[f];
-                const float4* rp = d.rec + kRec * (int64_t)e;
-                const float4 C = rp[2];
-                const Seg& s = d.tab.s[__float_as_uint(C.z)];
-                const int y = (int)(__float_as_uint(C.y) & 0xffffu) + (int)(q - (int64_t)rowoff[f]);
-                np = (uint32_t)(hi - lo + 1);
-                first = (uint32_t)(s.tile_base + y * s.ntx + lo);
-                out = __float_as_uint(rp[3].y) + rowpre[q];
-                low = kFull ? d.dkey[e] : 0u;
+            const int32_t f = rowmap[q];
+            e = (uint32_t)tall_e[f];
+            const float4* rp = d.rec + kRec * (int64_t)e;
+            const float4 C = rp[2];
+            const uint32_t rows = __float_as_uint(C.y);
+            const int y0 = (int)(rows & 0xffffu), y1 = (int)(rows >> 16);
+            const int y = y0 + (int)(q - (int64_t)rowoff[f]);
+            if (!(y & 1) || y == y0) {
+                const uint32_t own = d.spans[q];
+                if (y & 1) {
+                    sb = own;
+                } else {
+                    sa = own;
+                    if (y + 1 <= y1 && q + 1 < nr) sb = d.spans[q + 1];
+                }
+                np = sup_cols(sa, sb, x0);
+                if (np) {
+                    const SupGeo& sg = d.sg[__float_as_uint(C.z)];
+                    first = (uint32_t)(sg.base + (y >> kSupShift) * sg.nsx + x0);
+                    out = __float_as_uint(rp[3].y) + rowpre[q];
+                    low = kFull ? d.dkey[e] : 0u;
+                }
             }
         }
         s_row[w][lane] = make_uint4(first, np, out, e);
-        if (kFull) s_low[w][lane] = low;
+        s_sp[w][lane] = make_uint4(sa, sb, (uint32_t)x0, low);
         __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
         const uint64_t m = __ballot(np != 0u);
         if (m) {
             const int ng = (63 - __builtin_clzll(m)) / NG + 1;  // row groups up to the last non-empty row
-            uint4 nxt = s_row[w][grp];
+            uint4 nxt = s_row[w][grp], nsp = s_sp[w][grp];
             for (int g = 0; g < ng; ++g) {
-                const uint4 rr = nxt;
-                const uint32_t lw = kFull ? s_low[w][NG * g + grp] : 0u;
-                if (g + 1 < ng) nxt = s_row[w][NG * (g + 1) + grp];
-                for (uint32_t k = (uint32_t)sub; k < rr.y; k += kBigGW)
-                    put_pair<kFull>(d, (int64_t)rr.z + k, rr.x + k, rr.w, (uint64_t)lw);
+                const uint4 rr = nxt, sp = nsp;
+                if (g + 1 < ng) {
+                    nxt = s_row[w][NG * (g + 1) + grp];
+                    nsp = s_sp[w][NG * (g + 1) + grp];
+                }
+                for (uint32_t k = (uint32_t)sub; k < rr.y; k += kBigGW) {
+                    const uint32_t mk = sup_mask(sp.x, sp.y, (int)sp.z + (int)k);
+                    put_pair<kFull>(d, (int64_t)rr.z + k, rr.x + k, rr.w | (mk << kMaskShift), (uint64_t)sp.w);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();  // before the next 64 rows overwrite the arrays
@@ -673,34 +760,52 @@ __global__ __launch_bounds__(NT) void k_tall_rows(SegTable tab, const int32_t* _
     }
 }
 
-// One thread per tall footprint: its tile count from the stored spans, and
-// for each stored row the pairs of the footprint's earlier rows (rowpre);
-// the record keeps the offset of its first span (in the spans slot D.x).
+// One thread per tall footprint: its tile count and (super tile, entry)
+// pair count from the stored spans, and for each stored row that opens a
+// super row (an even tile row, or the footprint's first row) the pairs of
+// the footprint's earlier super rows (rowpre); the record keeps the offset
+// of its first span (in the spans slot D.x).
 __global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ tall_e, const uint32_t* __restrict__ rowoff,
                                                    const uint32_t* __restrict__ rowcnt,
                                                    const uint32_t* __restrict__ spans, const RasterCounters* rc,
                                                    int64_t cap, float4* __restrict__ rec, uint32_t* __restrict__ ntiles,
-                                                   uint32_t* __restrict__ dkey, uint32_t* __restrict__ rowpre) {
+                                                   uint32_t* __restrict__ nsup, uint32_t* __restrict__ dkey,
+                                                   uint32_t* __restrict__ rowpre) {
     const int64_t n = rc->n_tall_e;
     for (int64_t i = gtid(); i < n; i += gstride()) {
         const int64_t e = tall_e[i];
+        float4* rp = rec + kRec * e;
+        const int y0 = (int)(__float_as_uint(rp[2].y) & 0xffffu);
         const int64_t r0 = rowoff[i], r1 = r0 + rowcnt[i] < cap ? r0 + rowcnt[i] : cap;
-        uint32_t count = 0;
+        uint32_t count = 0, scount = 0;
+        int clo = 0x7fffffff, chi = -1;  // super columns of the open super row
         for (int64_t q0 = r0; q0 < r1; q0 += 4) {  // four independent loads per step
             uint32_t sp[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) sp[u] = q0 + u < r1 ? spans[q0 + u] : 0x0000ffffu;
+            for (int u = 0; u < 4; ++u) sp[u] = q0 + u < r1 ? spans[q0 + u] : kEmptySpan;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int lo = sp[u] & 0xffff, hi = sp[u] >> 16;
-                if (q0 + u < r1) rowpre[q0 + u] = count;
-                count += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+                if (q0 + u >= r1) continue;
+                const int y = y0 + (int)(q0 + u - r0);
+                if (!(y & 1) || q0 + u == r0) {  // a new super row opens here
+                    if (chi >= clo) scount += (uint32_t)(chi - clo + 1);
+                    clo = 0x7fffffff;
+                    chi = -1;
+                    rowpre[q0 + u] = scount;
+                }
+                const int lo = span_lo(sp[u]), hi = span_hi(sp[u]);
+                if (hi >= lo) {
+                    count += (uint32_t)(hi - lo + 1);
+                    clo = min(clo, lo >> kSupShift);
+                    chi = max(chi, hi >> kSupShift);
+                }
             }
         }
-        float4* rp = rec + kRec * e;
-        rp[2].w = __uint_as_float(count);
+        if (chi >= clo) scount += (uint32_t)(chi - clo + 1);
+        rp[2].w = __uint_as_float(scount);
         rp[3].x = __uint_as_float((uint32_t)r0);
         ntiles[e] = count;
+        nsup[e] = scount;
         if (!count && dkey) dkey[e] = 0u;  // (no per-entry keys when the eyes share the depth sort)
     }
 }
@@ -828,30 +933,50 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
         nc[i] = 0; stp[i] = -1;
         d[i] = !in[i];
     }
-    const int32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    for (int32_t base = start; base < end; base += BB) {
+    // the tile's list: the entries of its super tile's list whose mask has
+    // the tile's bit, in list order
+    const int S = s.sup_base + (ty >> kSupShift) * s.nsx + (tx >> kSupShift);
+    const uint32_t bit = 1u << (kMaskShift + ((ty & 1) << 1) + (tx & 1));
+    const int32_t end = ranges[2 * S + 1];
+    int32_t rd = ranges[2 * S];  // next list position to read
+    int32_t own = 0;             // the tile's entries staged so far
+    const uint64_t below = (1ull << threadIdx.x) - 1ull;  // lanes before this one
+    while (rd < end) {
         if (__all(d[0] && d[1] && d[2] && d[3])) break;
-        for (int l = threadIdx.x; l < BB; l += kBlendThreads) {
-            const int32_t i = base + l;
-            if (i >= end) {
-                // padding past the tile's last entry: alpha = 2^-inf = 0 is
-                // below the 1/255 cut, so these change no pixel and the
-                // unrolled loop below needs no bound of its own
-                sA[l] = make_float4(0.f, 0.f, 0.f, 0.f);
-                sB[l] = make_float4(0.f, -INFINITY, 0.f, 0.f);
-                sC[l] = 0.f;
-            } else {
-                uint32_t e = vals[i];
+        // stage up to BB of the tile's entries: 64 list positions a step,
+        // the tile's ones packed in order
+        int nb = 0;
+        while (nb < BB && rd < end) {
+            const int32_t i = rd + (int32_t)threadIdx.x;
+            const uint32_t v = i < end ? vals[i] : 0u;
+            const bool mine = (v & bit) != 0u;
+            const uint64_t mm = __ballot(mine);
+            const int at = nb + (int)__popcll(mm & below);
+            const bool take = mine && at < BB;
+            const uint64_t tk = __ballot(take);
+            if (take) {
+                uint32_t e = v & kEntryMask;
                 e = e < max_entries ? e : 0u;  // entries always are; keeps a stray id in bounds
                 const float4* rp = rec + kRec * (int64_t)e;
                 const float4 A = rp[0], B = rp[1];
-                sA[l] = make_float4(A.x, A.y, -0.5f * kL2e * A.z, -kL2e * A.w);
-                sB[l] = make_float4(-0.5f * kL2e * B.x, __log2f(B.y), B.z, B.w);
-                sC[l] = rp[2].x;
+                sA[at] = make_float4(A.x, A.y, -0.5f * kL2e * A.z, -kL2e * A.w);
+                sB[at] = make_float4(-0.5f * kL2e * B.x, __log2f(B.y), B.z, B.w);
+                sC[at] = rp[2].x;
             }
+            nb += (int)__popcll(tk);
+            // past the last position read: the whole step, or up to the last
+            // entry taken when the batch filled
+            rd = __popcll(mm) == __popcll(tk) ? rd + 64 : rd + 64 - (int)__builtin_clzll(tk);
+        }
+        // padding to the next group of 8: alpha = 2^-inf = 0 is below the
+        // 1/255 cut, so these change no pixel and the unrolled loop below
+        // needs no bound of its own
+        for (int l = nb + (int)threadIdx.x; l < ((nb + 7) & ~7); l += kBlendThreads) {
+            sA[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sB[l] = make_float4(0.f, -INFINITY, 0.f, 0.f);
+            sC[l] = 0.f;
         }
         __syncthreads();
-        const int nb = min(BB, end - base);
         // groups of 8: the done flags stay in scalar masks inside a group
         // and the LDS reads take immediate offsets; the padding above makes
         // a partial last group safe
@@ -881,20 +1006,22 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(SegTable tab, const int
                     T[i] = ac ? tn : T[i];
                     if (kCount) {
                         nc[i] += ac ? 1 : 0;
-                        stp[i] = st ? base + k : stp[i];
+                        stp[i] = st ? own + k : stp[i];
                     }
                     d[i] = d[i] || st;
                 }
             }
         }
+        own += nb;
         __syncthreads();  // the batch is read before the next one is staged
     }
     if (kCount) {
-        const int32_t len = end - start;
+        // a pixel that never stopped visited the whole list: the loop then
+        // ran to the list's end, so `own` is its length
         int32_t ne = 0, nce = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            ne += in[i] ? (stp[i] >= 0 ? stp[i] - start + 1 : len) : 0;
+            ne += in[i] ? (stp[i] >= 0 ? stp[i] + 1 : own) : 0;
             nce += nc[i];
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -944,6 +1071,19 @@ void seg_camera(Seg& s, const gsc_camera& c) {
     s.nty = (c.height + kTile - 1) / kTile;
 }
 
+void seg_supers(SegTable& tab) {
+    constexpr int side = 1 << kSupShift;
+    int32_t b = 0;
+    for (int q = 0; q < tab.n; ++q) {
+        Seg& s = tab.s[q];
+        s.nsx = (s.ntx + side - 1) >> kSupShift;
+        s.nsy = (s.nty + side - 1) >> kSupShift;
+        s.sup_base = b;
+        b += s.nsx * s.nsy;
+    }
+    tab.total_sup = b;
+}
+
 // Paired eyes whose FP32 rotations are equal bit for bit see every point at
 // view depths that differ by one constant per view (the eye offset along the
 // shared optical axis), so one depth order serves both eyes up to rounding.
@@ -971,18 +1111,22 @@ hipError_t tall_spans(const SegTable& tab, Raster& r, hipStream_t st) {
     hipLaunchKernelGGL(k_tall_rows, grid_fit(k_tall_rows, r.span_cap), dim3(NT), 0, st, tab, r.pt_dense, r.pt_rowoff,
                        r.rowmap, r.rec, rc, r.spans, r.span_cap);
     hipLaunchKernelGGL(k_tall_count, grid_fit(k_tall_count, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.pt_rowoff,
-                       r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles,
+                       r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles, r.nsup,
                        r.shared_depth ? nullptr : r.dkey[0], r.rowpre);
     return hipGetLastError();
 }
 
-hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool count_work, hipStream_t st,
+hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, bool count_work, hipStream_t st,
                         Marks* mk, hipStream_t blend_st, hipEvent_t front_done) {
+    if (r.max_entries > (int64_t)kEntryMask + 1) return hipErrorInvalidValue;  // entry ids share the value with the masks
+    SegTable tab = tab_in;
+    seg_supers(tab);
     RasterCounters* rc = r.cnt;
     mark(mk, 3, st);
     PreArgs pa;
-    pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.dkey = r.dkey[0]; pa.dval = r.dval[0];
-    pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_tiles;
+    pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.nsup = r.nsup; pa.dkey = r.dkey[0];
+    pa.dval = r.dval[0];
+    pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_sup;
     pa.max_entries = r.max_entries;
     r.shared_depth = !full_key_sort && eyes_share_rotation(tab);
     pa.shared_depth = r.shared_depth ? 1 : 0;
@@ -991,9 +1135,10 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
     hipError_t e0 = tall_spans(tab, r, st);
     if (e0 != hipSuccess) return e0;
     mark(mk, 5, st);
-    const int tile_bits = bits_for(tab.total_tiles);
+    const int tile_bits = bits_for(tab.total_sup);  // the sort's key: the global super-tile id
     DupArgs da;
-    da.tab = tab; da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
+    for (int q = 0; q < kMaxSeg; ++q) da.sg[q] = SupGeo{q < tab.n ? tab.s[q].sup_base : 0, q < tab.n ? tab.s[q].nsx : 0};
+    da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
     da.spans = r.spans; da.span_cap = r.span_cap; da.n_sort = r.n_sort;
     hipError_t e;
     if (!full_key_sort) {
@@ -1003,14 +1148,14 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         // with a shared sort it sorts the Gaussians and lays out both eyes'
         // entries of each at neighbouring ranks
         e = radix_sort_u32(r.dkey, r.dval, r.shared_depth ? &rc->n_gpairs : &rc->n_entries, 0, 0, 32, r.hist,
-                           r.block_sums, &which, st, r.ntiles, r.scnt, r.shared_depth);
+                           r.block_sums, &which, st, r.nsup, r.scnt, r.shared_depth);
         if (e != hipSuccess) return e;
         mark(mk, 6, st);
         e = scan_u32(r.scnt, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         mark(mk, 7, st);
-        // tile keys in 16 bits when the batch's global tile ids fit
-        const bool k16 = tab.total_tiles <= 65536;
+        // keys in 16 bits when the batch's global super-tile ids fit
+        const bool k16 = tab.total_sup <= 65536;
         uint16_t* pk16[2] = {reinterpret_cast<uint16_t*>(r.pkey[0]), reinterpret_cast<uint16_t*>(r.pkey[1])};
         da.order = r.dval[which]; da.offs = r.offs; da.key64 = nullptr; da.val = r.pval[0];
         da.key32 = k16 ? nullptr : r.pkey[0];
@@ -1031,13 +1176,13 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         r.key16 = k16;
         if (k16)
             hipLaunchKernelGGL(k_ranges<uint16_t>, grid_fit(k_ranges<uint16_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st,
-                               pk16[pw], r.n_sort, 0, r.ranges, (uint32_t)tab.total_tiles);
+                               pk16[pw], r.n_sort, 0, r.ranges, (uint32_t)tab.total_sup);
         else
             hipLaunchKernelGGL(k_ranges<uint32_t>, grid_fit(k_ranges<uint32_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st,
-                               r.pkey[pw], r.n_sort, 0, r.ranges, (uint32_t)tab.total_tiles);
+                               r.pkey[pw], r.n_sort, 0, r.ranges, (uint32_t)tab.total_sup);
     } else {
         mark(mk, 6, st);  // no per-Gaussian depth pass in this mode
-        e = scan_u32(r.ntiles, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
+        e = scan_u32(r.nsup, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         mark(mk, 7, st);
         da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key16 = nullptr; da.key64 = r.pkey64[0];
@@ -1055,7 +1200,7 @@ hipError_t raster_batch(const SegTable& tab, Raster& r, bool full_key_sort, bool
         mark(mk, 11, st);
         r.sorted_buf = pw;
         hipLaunchKernelGGL(k_ranges<uint64_t>, grid_fit(k_ranges<uint64_t>, r.max_pairs / 8 + 1), dim3(NT), 0, st, r.pkey64[pw], r.n_sort,
-                           32, r.ranges, (uint32_t)tab.total_tiles);
+                           32, r.ranges, (uint32_t)tab.total_sup);
     }
     r.order = nullptr;
     hipStream_t bs = st;

@@ -127,9 +127,16 @@ def assert_pairs_large(gpu_pairs, codes_gpu, ora_eye, codes_ora, excluded, depth
     return {"pairs": int(len(gp)), "sure": int(sure.sum()), "marginal_or_excluded": int(len(gp) - free_g.sum())}
 
 
+def mask_tiles(sort_vals) -> int:
+    """Tiles the sorted (super tile, entry) items cover: the set bits of
+    their 4-bit masks (value bits 28-31)."""
+    m = (np.asarray(sort_vals, np.uint32) >> 28).astype(np.int64)
+    return int(((m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1)).sum())
+
+
 def assert_ranges_from_keys(raw_keys, raw_ranges):
-    """Tile ranges (as the blend reads them, global tile ids, cleared to
-    [0, 0) for an empty tile) against the run boundaries of the sorted keys."""
+    """Ranges of the sorted keys (global super-tile ids, cleared to [0, 0)
+    for an empty one) against the run boundaries of the keys."""
     keys = np.asarray(raw_keys, np.int64)
     rg = np.asarray(raw_ranges, np.int64).reshape(-1, 2)
     assert np.all(np.diff(keys) >= 0), "sorted keys not ascending"

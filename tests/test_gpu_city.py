@@ -22,7 +22,7 @@ import pytest
 import oracle
 import synth
 from parity import (assert_image, assert_pairs_large, assert_ranges_from_keys, assert_visible_and_buffer,
-                    excluded_codes, gauss_codes)
+                    excluded_codes, gauss_codes, mask_tiles)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -72,6 +72,7 @@ def test_city_frame_plain_fp32_matches_oracle(gs, city, traj, frame):
     pairs = [r.debug("pairs", 0), r.debug("pairs", 1)]
     keys = r.debug("sort_keys")
     ranges = r.debug("raw_ranges")
+    r_vals = r.debug("sort_vals")
     r.close()
     ref = oracle.render_frame(city, L, R, debug=True)
     levels = np.bincount(city.level[vis], minlength=city.l_max + 1)
@@ -88,7 +89,11 @@ def test_city_frame_plain_fp32_matches_oracle(gs, city, traj, frame):
         print("  %s: %s" % (key, rep))
     # ranges as the blend reads them: the runs of the sorted keys of both eyes
     n_nonempty = assert_ranges_from_keys(keys, ranges)
-    assert len(keys) == len(pairs[0]) + len(pairs[1])
+    # the sorted items carry the tile pairs in their masks, one item per
+    # (super tile, entry), each covering 1-4 tiles
+    vals = r_vals
+    assert len(vals) == len(keys) and mask_tiles(vals) == len(pairs[0]) + len(pairs[1])
+    assert len(keys) < len(pairs[0]) + len(pairs[1])
     assert n_nonempty > 0
     for key, img in (("left", iL), ("right", iR)):
         rep = assert_image(img, ref[key])

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from parity import assert_image, assert_visible_and_buffer, gauss_codes
+from parity import assert_image, assert_visible_and_buffer, gauss_codes, mask_tiles
 
 pytestmark = pytest.mark.gpu
 
@@ -187,8 +187,10 @@ def test_wide_stereo_frame_with_32bit_tile_keys(gs, tiny):
     vis, G = r.debug("visible"), r.debug("gauss")
     pairs = [r.debug("pairs", 0), r.debug("pairs", 1)]
     keys = r.debug("sort_keys")
+    vals = r.debug("sort_vals")
     r.close()
-    assert len(keys) == len(pairs[0]) + len(pairs[1]) and np.all(np.diff(keys.astype(np.int64)) >= 0)
+    assert len(vals) == len(keys) and np.all(np.diff(keys.astype(np.int64)) >= 0)
+    assert mask_tiles(vals) == len(pairs[0]) + len(pairs[1])
     ref = oracle.render_frame(tiny, L, R, debug=True)
     codes_g = assert_visible_and_buffer(vis, G, ref, tiny.k)
     codes_o = gauss_codes(ref["G"], ref["visible"], tiny.k)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from parity import assert_image, assert_pairs, assert_ranges_from_keys
+from parity import assert_image, assert_pairs, assert_ranges_from_keys, mask_tiles
 
 pytestmark = pytest.mark.gpu
 
@@ -95,16 +95,21 @@ def test_large_footprints_match_oracle(gs, seed):
 
 
 def test_many_tiles_two_pass_sort_and_ranges(gs):
-    # 640x360: 40 x 23 = 920 tiles, so the tile sort takes two radix passes
-    # (8 + 2 bits); the pair count is not a multiple of 1024, so the tile
-    # ranges see both their full 1024-key steps and the ragged tail
-    mu, cov, rgb, al = synth.random_gaussians(20000, seed=6, box=6.0, zc=9.0)
-    cam = synth.look_camera((0.1, -0.2, 0), (0.05, 0.02, 1), (0, -1, 0), 640, 360, math.radians(70))
+    # 1000x560: 63 x 35 tiles, 32 x 18 = 576 super tiles, so the sort takes
+    # two radix passes (8 + 2 bits); the item count is not a multiple of
+    # 1024, so the ranges see both their full 1024-key steps and the ragged
+    # tail; the odd tile counts leave a half-filled super tile at the right
+    # and bottom edges
+    mu, cov, rgb, al = synth.random_gaussians(40000, seed=6, box=6.0, zc=12.0, s_hi=0.25)
+    cam = synth.look_camera((0.1, -0.2, 0), (0.05, 0.02, 1), (0, -1, 0), 1000, 560, math.radians(70))
     img, T, nc, pairs, r = run(gs, mu, cov, rgb, al, cam)
     keys = r.debug("sort_keys")
+    vals = r.debug("sort_vals")
     ranges = r.debug("raw_ranges")
     ref = oracle.render_gaussians(mu, cov, rgb, al, cam, debug=True)
-    assert len(keys) == len(pairs) and len(pairs) % 1024 != 0 and len(pairs) > 100000, len(pairs)
+    assert len(ranges) == 32 * 18 and keys.max() >= 256
+    assert len(vals) == len(keys) and mask_tiles(vals) == len(pairs)
+    assert len(keys) % 1024 != 0 and len(pairs) > 100000, (len(keys), len(pairs))
     assert_ranges_from_keys(keys, ranges)
     assert_pairs(pairs, ref, ref["pre"]["depth"])
     assert_image(img, ref)
