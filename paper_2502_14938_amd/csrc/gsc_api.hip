@@ -204,7 +204,7 @@ hipError_t alloc_raster(AllocSet& set, Raster& r, int64_t max_entries, int64_t m
     r.max_entries = max_entries;
     r.max_pairs = max_pairs;
     r.max_tiles = max_tiles;
-    r.span_cap = 2 * max_entries;
+    r.srow_cap = max_entries;
     hipError_t e = raster_layout(r, max_entries, max_pairs, max_tiles, full_key,
                                  [&](auto*& p, int64_t cnt) { return dalloc(set, r.bytes, &p, cnt); });
     if (e != hipSuccess) return e;
@@ -614,13 +614,13 @@ int gsc_sync(gsc_ctx* c) {
     if (c->rendered) {
         Raster& R = c->explicit_render ? c->xraster : stereo_raster(c);
         HIP_OR_FAIL(c, hipMemcpy(R.cnt_host, R.cnt, sizeof(RasterCounters), hipMemcpyDeviceToHost));
-        of |= (R.cnt_host->overflow & 7) ? 1 : 0;  // tile pairs, entries or tall-row spans
+        of |= (R.cnt_host->overflow & 7) ? 1 : 0;  // tile pairs, entries or tall-footprint rows
     }
     if (c->loaded && c->derived) {
         HIP_OR_FAIL(c, hipMemcpy(c->view[0].cnt_host, c->view[0].cnt, sizeof(Counters), hipMemcpyDeviceToHost));
         of |= c->view[0].cnt_host->overflow & 2;
     }
-    if (of) return fail(c, GSC_E_CAPACITY, of & 1 ? "raster capacity exceeded (tile pairs, entries or tall-row spans)"
+    if (of) return fail(c, GSC_E_CAPACITY, of & 1 ? "raster capacity exceeded (tile pairs, entries or tall-footprint rows)"
                                                   : "cache capacity exceeded");
     return GSC_OK;
 }

@@ -61,8 +61,8 @@ struct RasterCounters {
     int32_t n_pairs;              // total (super tile, entry) pairs (all segments): the sorted items
     int32_t n_echunks;            // chunks of 256 entries (preprocess tall lists)
     int32_t n_tall_e;             // tall entries found by the preprocess
-    int32_t n_rows;               // their tile rows (stored spans)
-    int32_t overflow;             // bit0: pair capacity, bit1: entries, bit2: tall-row spans
+    int32_t n_srows;              // their super rows (pairs of tile rows), stored
+    int32_t overflow;             // bit0: pair capacity, bit1: entries, bit2: tall footprints' super rows
     int32_t n_gpairs;             // entries / 2: the depth sort's length when the eyes share it
 };
 
@@ -182,12 +182,12 @@ struct Raster {
     int32_t* pt_cnt = nullptr;    // [max_entries / 256 + 1] per chunk of entries
     uint32_t* pt_off = nullptr;   // [max_entries / 256 + 1]
     int32_t* pt_dense = nullptr;  // [max_entries] tall entries (entry ids), dense
-    uint32_t* pt_rowcnt = nullptr;  // [max_entries] tile rows of each
-    uint32_t* pt_rowoff = nullptr;  // [max_entries] first stored span of each
-    uint32_t* spans = nullptr;    // [span_cap] row spans of the tall footprints (lo | hi << 16)
-    int32_t* rowmap = nullptr;    // [span_cap] footprint (dense index) of each stored span
-    uint32_t* rowpre = nullptr;   // [span_cap] pairs of the footprint's rows before each stored span
-    int64_t span_cap = 0;
+    uint32_t* pt_srcnt = nullptr;  // [max_entries] super rows of each
+    uint32_t* pt_sroff = nullptr;  // [max_entries] first stored super row of each
+    uint4* srow = nullptr;        // [srow_cap] super rows of the tall footprints: span of tile row 2 Y,
+                                  // of tile row 2 Y + 1 (lo | hi << 16), entry, items of the earlier ones
+    int32_t* srow_y = nullptr;    // [srow_cap] Y of each stored super row
+    int64_t srow_cap = 0;
     uint32_t* ntiles = nullptr; // tile count per entry
     uint32_t* nsup = nullptr;   // (super tile, entry) pair count per entry
     uint32_t* scnt = nullptr;   // pair count per depth rank

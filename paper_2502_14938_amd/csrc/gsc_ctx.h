@@ -47,8 +47,8 @@ hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int6
 #define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
     A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.nsup, max_entries); A_(r.scnt, max_entries);
     A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
-    A_(r.pt_dense, max_entries); A_(r.pt_rowcnt, max_entries); A_(r.pt_rowoff, max_entries);
-    A_(r.spans, 2 * max_entries); A_(r.rowmap, 2 * max_entries); A_(r.rowpre, 2 * max_entries);
+    A_(r.pt_dense, max_entries); A_(r.pt_srcnt, max_entries); A_(r.pt_sroff, max_entries);
+    A_(r.srow, max_entries); A_(r.srow_y, max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);

@@ -82,7 +82,7 @@ int na_setup(int dev, NaDevice*& out) {
         t.r.max_entries = n;
         t.r.max_pairs = GSC_NOALLOC_MAX_PAIRS;
         t.r.max_tiles = kNaTiles;
-        t.r.span_cap = 2 * n;
+        t.r.srow_cap = n;
         t.r.cnt_host = nullptr;  // counters are read on the device only
         t.ready = true;
         d = t;

@@ -4,7 +4,8 @@
 //   k_preprocess       EWA projection, conic, opacity-aware extent, depth
 //                      key, exact tile spans of footprints up to 4 tile
 //                      rows (per entry); segment bases; clears the ranges
-//   tall spans         one thread per tile row of the taller footprints
+//   tall spans         the taller footprints' super rows (pairs of tile rows),
+//                      a group of lanes per footprint, one tile row per lane
 //   depth radix pass   stable sort of entries by float32 depth (the low 32
 //                      bits of the (tile | depth) key, applied per Gaussian
 //                      before duplication); the last pass also lays the tile
@@ -12,16 +13,18 @@
 //                      share its rotation, one key per Gaussian orders both
 //                      eyes' entries (half the keys)
 //   scan + k_dup_rows / k_dup_big
-//                      one (global tile id, entry) pair per covered tile,
-//                      emitted in depth order (LDS-staged, coalesced)
-//   tile radix pass    stable sort of pairs by global tile id (the high bits)
-//   k_ranges           [start, end) of every tile's run
+//                      one (global super-tile id, entry | tile mask) item per
+//                      covered super tile (2x2 tiles), emitted in depth order
+//   super-tile radix pass
+//                      stable sort of the items by global super-tile id
+//   k_ranges           [start, end) of every super tile's run
 //   k_blend            front-to-back compositing, one launch over every
 //                      (segment, tile) of the batch, one block per 16x16
-//                      tile (interleaved tile runs per XCD), LDS-staged Gaussian
-//                      batches, block-wide early exit
-// With full_key_sort the pairs carry the whole 64-bit (tile << 32 | depth)
-// key and are sorted after duplication instead; the order is the same.
+//                      tile (interleaved tile runs per XCD); a tile stages the
+//                      entries of its super tile's list that carry its mask
+//                      bit, LDS batches, block-wide early exit
+// With full_key_sort the items carry the whole 64-bit (super tile << 32 |
+// depth) key and are sorted after duplication instead; the order is the same.
 #include <cmath>
 #include <cstring>
 
@@ -497,8 +500,9 @@ struct DupArgs {
     uint32_t* val;           // entry id | tile mask << kMaskShift
     int64_t max_pairs;
     int32_t* n_sort;         // pairs to sort (set by k_dup_rows)
-    const uint32_t* spans;   // row spans of the tall footprints
-    int64_t span_cap;
+    const uint4* srow;       // super rows of the tall footprints (see k_tall_spans)
+    const int32_t* srow_y;   // their super-row index in the image
+    int64_t srow_cap;
 };
 
 // Kernel arguments (the segment table travels by value) stay within the
@@ -632,56 +636,42 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
 }
 
 // Dense list of the tall entries the preprocess listed per chunk of 256
-// entries: chunk c's entries at off[c] + i, and the tile rows of each.
+// entries: chunk c's entries at off[c] + i, and the super rows (pairs of
+// tile rows 2 Y, 2 Y + 1) each spans.
 __global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ list, const int32_t* __restrict__ cnt,
                                                      const uint32_t* __restrict__ off, const int32_t* n_chunks,
                                                      int32_t* __restrict__ dense, const float4* __restrict__ rec,
-                                                     uint32_t* __restrict__ rowcnt) {
+                                                     uint32_t* __restrict__ srcnt) {
     const int64_t nc = *n_chunks;
     for (int64_t c = blockIdx.x; c < nc; c += gridDim.x)
         if ((int32_t)threadIdx.x < cnt[c]) {
             const int32_t x = list[c * NT + threadIdx.x];
             dense[off[c] + threadIdx.x] = x;
             const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)x + 2].y);
-            rowcnt[off[c] + threadIdx.x] = (rows >> 16) - (rows & 0xffff) + 1;
+            srcnt[off[c] + threadIdx.x] = ((rows >> 16) >> kSupShift) - ((rows & 0xffff) >> kSupShift) + 1;
         }
 }
 
-// Footprint (dense index) of every stored row span.
-__global__ __launch_bounds__(NT) void k_tall_rowmap(const uint32_t* __restrict__ rowoff,
-                                                    const uint32_t* __restrict__ rowcnt, const RasterCounters* rc,
-                                                    int64_t cap, int32_t* __restrict__ rowmap) {
-    const int64_t n = rc->n_tall_e;
-    for (int64_t i = gtid(); i < n; i += gstride()) {
-        const int64_t r0 = rowoff[i], r1 = r0 + rowcnt[i] < cap ? r0 + rowcnt[i] : cap;
-        for (int64_t q = r0; q < r1; ++q) rowmap[q] = (int32_t)i;
-    }
-}
-
-// One wave per 64 consecutive stored rows of the tall footprints (a
-// footprint's rows are consecutive, and so are their output ranges).  The
-// lane of a row that opens a super row (an even tile row, or the
-// footprint's first row) loads that super row: the spans of its two tile
-// rows (the next stored row is the footprint's next tile row), its columns,
-// first super tile and output offset (the entry's offset, stored by
-// k_dup_rows, plus the pairs of the footprint's earlier super rows, stored
-// by k_tall_count), into LDS; then the wave writes the super rows' pairs,
-// kBigGW lanes per super row, 64 / kBigGW at a time: lane s of a group
-// takes pairs s, s + kBigGW, ... of its super row (consecutive lanes,
-// consecutive slots).  No lane searches for its row, so the stores follow
-// each other without LDS round trips in between.
+// One wave per 64 consecutive stored super rows of the tall footprints (a
+// footprint's super rows are consecutive, and so are their output ranges):
+// each lane loads one super row (the spans of its two tile rows, its entry
+// and the items of the footprint's earlier super rows, stored by
+// k_tall_spans; its columns, first super tile and output offset: the
+// entry's offset, stored by k_dup_rows, plus those items) into LDS; then the
+// wave writes the super rows' items, kBigGW lanes per super row, 64 /
+// kBigGW at a time: lane s of a group takes items s, s + kBigGW, ... of its
+// super row (consecutive lanes, consecutive slots).  No lane searches for its
+// row, so the stores follow each other without LDS round trips in between.
 constexpr int kBigGW = 16;
 template <bool kFull>
-__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __restrict__ tall_e,
-                                                const uint32_t* __restrict__ rowoff, const int32_t* __restrict__ rowmap,
-                                                const uint32_t* __restrict__ rowpre) {
+__global__ __launch_bounds__(NT) void k_dup_big(DupArgs d) {
     constexpr int NG = 64 / kBigGW;               // super rows written at a time
-    __shared__ uint4 s_row[NT / 64][64];           // (first super tile, pairs, output offset, entry)
+    __shared__ uint4 s_row[NT / 64][64];           // (first super tile, items, output offset, entry)
     __shared__ uint4 s_sp[NT / 64][64];            // (span of tile row a, of tile row b, first column, depth bits)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int grp = lane / kBigGW, sub = lane % kBigGW;
-    int64_t nr = d.rc->n_rows;
-    if (nr > d.span_cap) nr = d.span_cap;
+    int64_t nr = d.rc->n_srows;
+    if (nr > d.srow_cap) nr = d.srow_cap;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t q0 = wave * 64; q0 < nr; q0 += nwaves * 64) {
@@ -689,28 +679,18 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
         uint32_t np = 0, first = 0, out = 0, e = 0, low = 0, sa = kEmptySpan, sb = kEmptySpan;
         int x0 = 0;
         if (q < nr) {
-            const int32_t f = rowmap[q];
-            e = (uint32_t)tall_e[f];
-            const float4* rp = d.rec + kRec * (int64_t)e;
-            const float4 C = rp[2];
-            const uint32_t rows = __float_as_uint(C.y);
-            const int y0 = (int)(rows & 0xffffu), y1 = (int)(rows >> 16);
-            const int y = y0 + (int)(q - (int64_t)rowoff[f]);
-            if (!(y & 1) || y == y0) {
-                const uint32_t own = d.spans[q];
-                if (y & 1) {
-                    sb = own;
-                } else {
-                    sa = own;
-                    if (y + 1 <= y1 && q + 1 < nr) sb = d.spans[q + 1];
-                }
-                np = sup_cols(sa, sb, x0);
-                if (np) {
-                    const SupGeo& sg = d.sg[__float_as_uint(C.z)];
-                    first = (uint32_t)(sg.base + (y >> kSupShift) * sg.nsx + x0);
-                    out = __float_as_uint(rp[3].y) + rowpre[q];
-                    low = kFull ? d.dkey[e] : 0u;
-                }
+            const uint4 sr = d.srow[q];
+            const int y = d.srow_y[q];
+            sa = sr.x;
+            sb = sr.y;
+            np = sup_cols(sa, sb, x0);
+            if (np) {
+                e = sr.z;
+                const float4* rp = d.rec + kRec * (int64_t)e;
+                const SupGeo& sg = d.sg[__float_as_uint(rp[2].z)];
+                first = (uint32_t)(sg.base + y * sg.nsx + x0);
+                out = __float_as_uint(rp[3].y) + sr.w;
+                low = kFull ? d.dkey[e] : 0u;
             }
         }
         s_row[w][lane] = make_uint4(first, np, out, e);
@@ -736,77 +716,77 @@ __global__ __launch_bounds__(NT) void k_dup_big(DupArgs d, const int32_t* __rest
     }
 }
 
-// One thread per row of every tall footprint: its exact tile span, stored as
-// lo | hi << 16 (hi < lo: empty).
-__global__ __launch_bounds__(NT) void k_tall_rows(SegTable tab, const int32_t* __restrict__ tall_e,
-                                                  const uint32_t* __restrict__ rowoff, const int32_t* __restrict__ rowmap,
-                                                  const float4* __restrict__ rec, RasterCounters* rc,
-                                                  uint32_t* __restrict__ spans, int64_t cap) {
-    int64_t nr = rc->n_rows;
-    if (nr > cap) {
-        if (gtid() == 0) rc->overflow |= 4;
-        nr = cap;
-    }
-    for (int64_t q = gtid(); q < nr; q += gstride()) {
-        const int64_t lo = rowmap[q];
-        const float4* rp = rec + kRec * (int64_t)tall_e[lo];
+// Lanes per tall footprint in k_tall_spans (even: a super row's two tile
+// rows sit in neighbouring lanes).
+constexpr int kTallGW = 8;
+static_assert(kTallGW % 2 == 0, "super rows pair neighbouring lanes");
+
+// Tall footprints, kTallGW lanes each: lane s takes the footprint's tile
+// rows 2 Y0 + s, 2 Y0 + s + kTallGW, ... (Y0: the footprint's first super
+// row; rows outside the footprint are empty) and their exact tile spans;
+// the even lane of each pair stores the pair's super row at the footprint's
+// offset: (span of row 2 Y, span of row 2 Y + 1, entry, items of the
+// footprint's earlier super rows) and its index Y.  The group's totals give
+// the entry's tile count and its (super tile, entry) item count.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tall_spans(SegTable tab, const int32_t* __restrict__ tall_e,
+                                                   const uint32_t* __restrict__ sroff, RasterCounters* rc,
+                                                   float4* __restrict__ rec, uint4* __restrict__ srow,
+                                                   int32_t* __restrict__ srow_y, int64_t cap,
+                                                   uint32_t* __restrict__ ntiles, uint32_t* __restrict__ nsup,
+                                                   uint32_t* __restrict__ dkey) {
+    const int64_t n = rc->n_tall_e;
+    if (gtid() == 0 && (int64_t)rc->n_srows > cap) rc->overflow |= 4;
+    const int sub = (int)(threadIdx.x % kTallGW);
+    const int64_t ngrp = gstride() / kTallGW;
+    for (int64_t f = gtid() / kTallGW; f < n; f += ngrp) {
+        const int64_t e = tall_e[f];
+        float4* rp = rec + kRec * e;
         const float4 A = rp[0], B = rp[1], C = rp[2];
         const uint32_t rows = __float_as_uint(C.y);
+        const int y0 = (int)(rows & 0xffffu), y1 = (int)(rows >> 16);
         const Seg& s = tab.s[__float_as_uint(C.z)];
         const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
-        int slo, shi;
-        row_span(el, (int)(rows & 0xffff) + (int)(q - (int64_t)rowoff[lo]), s.ntx, s.W, s.H, slo, shi);
-        spans[q] = shi >= slo ? ((uint32_t)slo | ((uint32_t)shi << 16)) : 0x0000ffffu;
-    }
-}
-
-// One thread per tall footprint: its tile count and (super tile, entry)
-// pair count from the stored spans, and for each stored row that opens a
-// super row (an even tile row, or the footprint's first row) the pairs of
-// the footprint's earlier super rows (rowpre); the record keeps the offset
-// of its first span (in the spans slot D.x).
-__global__ __launch_bounds__(NT) void k_tall_count(const int32_t* __restrict__ tall_e, const uint32_t* __restrict__ rowoff,
-                                                   const uint32_t* __restrict__ rowcnt,
-                                                   const uint32_t* __restrict__ spans, const RasterCounters* rc,
-                                                   int64_t cap, float4* __restrict__ rec, uint32_t* __restrict__ ntiles,
-                                                   uint32_t* __restrict__ nsup, uint32_t* __restrict__ dkey,
-                                                   uint32_t* __restrict__ rowpre) {
-    const int64_t n = rc->n_tall_e;
-    for (int64_t i = gtid(); i < n; i += gstride()) {
-        const int64_t e = tall_e[i];
-        float4* rp = rec + kRec * e;
-        const int y0 = (int)(__float_as_uint(rp[2].y) & 0xffffu);
-        const int64_t r0 = rowoff[i], r1 = r0 + rowcnt[i] < cap ? r0 + rowcnt[i] : cap;
-        uint32_t count = 0, scount = 0;
-        int clo = 0x7fffffff, chi = -1;  // super columns of the open super row
-        for (int64_t q0 = r0; q0 < r1; q0 += 4) {  // four independent loads per step
-            uint32_t sp[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) sp[u] = q0 + u < r1 ? spans[q0 + u] : kEmptySpan;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (q0 + u >= r1) continue;
-                const int y = y0 + (int)(q0 + u - r0);
-                if (!(y & 1) || q0 + u == r0) {  // a new super row opens here
-                    if (chi >= clo) scount += (uint32_t)(chi - clo + 1);
-                    clo = 0x7fffffff;
-                    chi = -1;
-                    rowpre[q0 + u] = scount;
-                }
-                const int lo = span_lo(sp[u]), hi = span_hi(sp[u]);
+        const int ybase = (y0 >> kSupShift) << kSupShift;  // tile row 2 Y0
+        const int64_t q0 = sroff[f];
+        uint32_t tiles = 0, before = 0;
+        for (int b = 0; b <= y1 - ybase; b += kTallGW) {  // the group's lanes share the trip count
+            const int y = ybase + b + sub;
+            uint32_t sp = kEmptySpan;
+            if (y >= y0 && y <= y1) {
+                int lo, hi;
+                row_span(el, y, s.ntx, s.W, s.H, lo, hi);
                 if (hi >= lo) {
-                    count += (uint32_t)(hi - lo + 1);
-                    clo = min(clo, lo >> kSupShift);
-                    chi = max(chi, hi >> kSupShift);
+                    sp = (uint32_t)lo | ((uint32_t)hi << 16);
+                    tiles += (uint32_t)(hi - lo + 1);
                 }
             }
+            // the pair (2 Y, 2 Y + 1) of neighbouring lanes: its columns, and
+            // the items of the group's earlier pairs (inclusive scan)
+            const uint32_t other = (uint32_t)__shfl_xor((int)sp, 1, kTallGW);
+            const bool even = !(sub & 1);
+            int x0;
+            const uint32_t w = even ? sup_cols(sp, other, x0) : 0u;
+            uint32_t incl = w;
+#pragma unroll
+            for (int o = 1; o < kTallGW; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o, kTallGW);
+                if (sub >= o) incl += t;
+            }
+            const int si = (b + sub) >> kSupShift;  // super row within the footprint
+            if (even && ybase + b + sub <= y1 && q0 + si < cap) {
+                srow[q0 + si] = make_uint4(sp, other, (uint32_t)e, before + incl - w);
+                srow_y[q0 + si] = (ybase >> kSupShift) + si;
+            }
+            before += __shfl(incl, kTallGW - 1, kTallGW);
         }
-        if (chi >= clo) scount += (uint32_t)(chi - clo + 1);
-        rp[2].w = __uint_as_float(scount);
-        rp[3].x = __uint_as_float((uint32_t)r0);
-        ntiles[e] = count;
-        nsup[e] = scount;
-        if (!count && dkey) dkey[e] = 0u;  // (no per-entry keys when the eyes share the depth sort)
+#pragma unroll
+        for (int o = kTallGW / 2; o > 0; o >>= 1) tiles += __shfl_xor(tiles, o, kTallGW);
+        if (sub == 0) {
+            rp[2].w = __uint_as_float(before);
+            ntiles[e] = tiles;
+            nsup[e] = before;
+            if (!tiles && dkey) dkey[e] = 0u;  // (no per-entry keys when the eyes share the depth sort)
+        }
     }
 }
 
@@ -1095,24 +1075,20 @@ static bool eyes_share_rotation(const SegTable& tab) {
 }
 
 // Tall footprints (more than kSmallRows tile rows): dense list of the
-// entries k_preprocess listed per chunk, offsets of their rows, one thread
-// per row for the exact spans, then each footprint's count.
+// entries k_preprocess listed per chunk, offsets of their super rows, then
+// each footprint's super rows, spans and counts.
 hipError_t tall_spans(const SegTable& tab, Raster& r, hipStream_t st) {
     RasterCounters* rc = r.cnt;
     hipError_t e = scan_u32(reinterpret_cast<const uint32_t*>(r.pt_cnt), r.pt_off, &rc->n_echunks, 0, &rc->n_tall_e,
                             r.block_sums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.pt_list, r.pt_cnt, r.pt_off,
-                       &rc->n_echunks, r.pt_dense, r.rec, r.pt_rowcnt);
-    e = scan_u32(r.pt_rowcnt, r.pt_rowoff, &rc->n_tall_e, 0, &rc->n_rows, r.block_sums, st);
+                       &rc->n_echunks, r.pt_dense, r.rec, r.pt_srcnt);
+    e = scan_u32(r.pt_srcnt, r.pt_sroff, &rc->n_tall_e, 0, &rc->n_srows, r.block_sums, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tall_rowmap, grid_fit(k_tall_rowmap, r.max_entries), dim3(NT), 0, st, r.pt_rowoff,
-                       r.pt_rowcnt, rc, r.span_cap, r.rowmap);
-    hipLaunchKernelGGL(k_tall_rows, grid_fit(k_tall_rows, r.span_cap), dim3(NT), 0, st, tab, r.pt_dense, r.pt_rowoff,
-                       r.rowmap, r.rec, rc, r.spans, r.span_cap);
-    hipLaunchKernelGGL(k_tall_count, grid_fit(k_tall_count, r.max_entries), dim3(NT), 0, st, r.pt_dense, r.pt_rowoff,
-                       r.pt_rowcnt, r.spans, rc, r.span_cap, r.rec, r.ntiles, r.nsup,
-                       r.shared_depth ? nullptr : r.dkey[0], r.rowpre);
+    hipLaunchKernelGGL(k_tall_spans, grid_fit(k_tall_spans, (int64_t)r.max_entries * kTallGW), dim3(NT), 0, st, tab,
+                       r.pt_dense, r.pt_sroff, rc, r.rec, r.srow, r.srow_y, r.srow_cap, r.ntiles, r.nsup,
+                       r.shared_depth ? nullptr : r.dkey[0]);
     return hipGetLastError();
 }
 
@@ -1139,7 +1115,7 @@ hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, b
     DupArgs da;
     for (int q = 0; q < kMaxSeg; ++q) da.sg[q] = SupGeo{q < tab.n ? tab.s[q].sup_base : 0, q < tab.n ? tab.s[q].nsx : 0};
     da.rc = rc; da.rec = r.rec; da.max_pairs = r.max_pairs; da.dkey = r.dkey[0];
-    da.spans = r.spans; da.span_cap = r.span_cap; da.n_sort = r.n_sort;
+    da.srow = r.srow; da.srow_y = r.srow_y; da.srow_cap = r.srow_cap; da.n_sort = r.n_sort;
     hipError_t e;
     if (!full_key_sort) {
         // low 32 key bits (depth) first, per Gaussian
@@ -1162,9 +1138,8 @@ hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, b
         da.key16 = k16 ? pk16[0] : nullptr;
         hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da);
         mark(mk, 8, st);
-        mark(mk, 9, st);  // (no kernel in the tall-list stage: k_dup_big reads the stored rows)
-        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, r.span_cap), dim3(NT), 0, st, da,
-                           r.pt_dense, r.pt_rowoff, r.rowmap, r.rowpre);
+        mark(mk, 9, st);  // (no kernel in the tall-list stage: k_dup_big reads the stored super rows)
+        hipLaunchKernelGGL(k_dup_big<false>, grid_fit(k_dup_big<false>, r.srow_cap), dim3(NT), 0, st, da);
         mark(mk, 10, st);
         // then the tile bits, on the pairs (stable: depth order kept per tile)
         int pw = 0;
@@ -1191,8 +1166,7 @@ hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, b
         hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da);
         mark(mk, 8, st);
         mark(mk, 9, st);
-        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, r.span_cap), dim3(NT), 0, st, da,
-                           r.pt_dense, r.pt_rowoff, r.rowmap, r.rowpre);
+        hipLaunchKernelGGL(k_dup_big<true>, grid_fit(k_dup_big<true>, r.srow_cap), dim3(NT), 0, st, da);
         mark(mk, 10, st);
         int pw = 0;
         e = radix_sort_u64(r.pkey64, r.pval, r.n_sort, 0, 0, 32 + tile_bits, r.hist, r.block_sums, &pw, st);
