@@ -205,6 +205,7 @@ hipError_t alloc_raster(AllocSet& set, Raster& r, int64_t max_entries, int64_t m
     r.max_pairs = max_pairs;
     r.max_tiles = max_tiles;
     r.srow_cap = max_entries;
+    r.tall_cap = max_entries / 4 + 256;
     hipError_t e = raster_layout(r, max_entries, max_pairs, max_tiles, full_key,
                                  [&](auto*& p, int64_t cnt) { return dalloc(set, r.bytes, &p, cnt); });
     if (e != hipSuccess) return e;

@@ -27,22 +27,25 @@ __device__ __forceinline__ void chunk_of(int64_t n, int64_t align, int64_t& b0, 
     b1 = b0 + per < n ? b0 + per : n;
 }
 
-// Exclusive scan across the 256 threads of a block (one value each).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+// Exclusive scan across the 256 threads of a block (one value each); T is
+// uint32_t or uint64_t (two 32-bit counts packed in one value add
+// independently while neither field overflows).
+template <typename T = uint32_t>
+__device__ __forceinline__ T block_excl_scan(T v, T* wsum, T& total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = v;
+    T x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
+        T y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
     if (lane == 63) wsum[w] = x;
     __syncthreads();
-    uint32_t pre = 0, tot = 0;
+    T pre = 0, tot = 0;
 #pragma unroll
     for (int i = 0; i < kThreads / 64; ++i) {
-        uint32_t s = wsum[i];
-        pre += i < w ? s : 0u;
+        T s = wsum[i];
+        pre += i < w ? s : (T)0;
         tot += s;
     }
     __syncthreads();
@@ -50,20 +53,26 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
     return pre + x - v;
 }
 
-__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* wsum) {
-    uint32_t t;
-    block_excl_scan(v, wsum, t);
+template <typename T = uint32_t>
+__device__ __forceinline__ T block_sum(T v, T* wsum) {
+    T t;
+    block_excl_scan<T>(v, wsum, t);
     return t;
 }
 
 // Down-sweep carry of this block: the sum of the preceding blocks' sums (at
 // most gridDim.x values, a block reduction, so no pass over the block sums
 // of its own); the last block also writes the total (when asked).
+template <typename T = uint32_t>
+__device__ __forceinline__ T block_carry(const T* __restrict__ block_sums, T* wsum) {
+    T part = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kThreads) part += block_sums[i];
+    return block_sum<T>(part, wsum);
+}
+
 __device__ __forceinline__ uint32_t block_carry(const uint32_t* __restrict__ block_sums, uint32_t* wsum,
                                                 int32_t* total) {
-    uint32_t part = 0;
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kThreads) part += block_sums[i];
-    const uint32_t carry = block_sum(part, wsum);
+    const uint32_t carry = block_carry<uint32_t>(block_sums, wsum);
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = (int32_t)(carry + block_sums[blockIdx.x]);
     return carry;
 }

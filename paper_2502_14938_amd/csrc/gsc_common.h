@@ -173,17 +173,26 @@ struct View {
     size_t bytes = 0;
 };
 
+// A tall footprint (more than four tile rows) as the span kernel reads it:
+// its ellipse (the conic, opacity-aware threshold and the extents the row
+// spans start from), entry, tile rows and segment.
+struct TallRec {
+    float mx, my, ca, cb, cc, tau, det, xmax, ymax, kr, margin, ia, ic;
+    uint32_t e, rows, seg;
+};
+static_assert(sizeof(TallRec) == 64, "tall footprint record: four 16-byte words");
+
 // Raster batch buffers.
 struct Raster {
     int64_t max_entries = 0, max_pairs = 0, max_tiles = 0;
     float4* rec = nullptr;      // [4 * entries]: (mean2d, conic a b), (conic c, alpha, r g), (b, rows, seg, count),
                                 // spans (tall footprints: first stored span, output offset)
     int32_t* pt_list = nullptr;   // [max_entries] tall entries (entry ids) in their chunk's slots
-    int32_t* pt_cnt = nullptr;    // [max_entries / 256 + 1] per chunk of entries
-    uint32_t* pt_off = nullptr;   // [max_entries / 256 + 1]
-    int32_t* pt_dense = nullptr;  // [max_entries] tall entries (entry ids), dense
-    uint32_t* pt_srcnt = nullptr;  // [max_entries] super rows of each
-    uint32_t* pt_sroff = nullptr;  // [max_entries] first stored super row of each
+    uint64_t* pt_pack = nullptr;  // [max_entries / 256 + 1] per chunk of entries: tall ones | their super rows << 32
+    uint64_t* pt_off = nullptr;   // [max_entries / 256 + 1] exclusive prefix of pt_pack
+    TallRec* trec = nullptr;  // [tall_cap] the tall footprints (ellipse, entry, rows, segment), dense
+    uint32_t* pt_sroff = nullptr;  // [tall_cap] first stored super row of each
+    int64_t tall_cap = 0;
     uint4* srow = nullptr;        // [srow_cap] super rows of the tall footprints: span of tile row 2 Y,
                                   // of tile row 2 Y + 1 (lo | hi << 16), entry, items of the earlier ones
     int32_t* srow_y = nullptr;    // [srow_cap] Y of each stored super row
@@ -202,6 +211,7 @@ struct Raster {
     int32_t* ranges = nullptr;  // [max_tiles][2]
     uint32_t* hist = nullptr;   // [256 * kSortBlocks] radix digit counts per block
     uint32_t* block_sums = nullptr;
+    uint64_t* block_sums64 = nullptr;  // [kScanBlocks] scan scratch of the tall path's 64-bit scan
     RasterCounters* cnt = nullptr;
     RasterCounters* cnt_host = nullptr;
     int sorted_buf = 0;         // which pkey/pval buffer holds the sorted pairs
@@ -218,6 +228,11 @@ struct Raster {
 // writing exclusive prefixes to out and the total to *total (device).
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int64_t n_host, int32_t* total,
                     uint32_t* block_sums, hipStream_t st);
+// Exclusive scan of n (from *n_dev) uint64 values, each two 32-bit counts
+// (low, high) that scan independently; the totals of the two go to
+// *total_lo and *total_hi (device).  block_sums: kScanBlocks values.
+hipError_t scan_u64(const uint64_t* in, uint64_t* out, const int32_t* n_dev, int32_t* total_lo, int32_t* total_hi,
+                    uint64_t* block_sums, hipStream_t st);
 // Stream compaction: ids[k] = the k-th i with flags[i] != 0 (flags 0 or 1,
 // n from *n_dev if non-null), the count to *total (device).
 hipError_t compact_u32(const uint32_t* flags, const int32_t* n_dev, int64_t n_host, int32_t* total, int32_t* ids,

@@ -46,15 +46,16 @@ hipError_t raster_layout(Raster& r, int64_t max_entries, int64_t max_pairs, int6
     hipError_t e;
 #define A_(p, cnt) if ((e = A(p, cnt)) != hipSuccess) return e
     A_(r.rec, 4 * max_entries); A_(r.ntiles, max_entries); A_(r.nsup, max_entries); A_(r.scnt, max_entries);
-    A_(r.pt_list, max_entries); A_(r.pt_cnt, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
-    A_(r.pt_dense, max_entries); A_(r.pt_srcnt, max_entries); A_(r.pt_sroff, max_entries);
+    A_(r.pt_list, max_entries); A_(r.pt_pack, max_entries / 256 + 1); A_(r.pt_off, max_entries / 256 + 1);
+    // tall footprints: at most a quarter of the entries (more are flagged as overflow)
+    A_(r.trec, max_entries / 4 + 256); A_(r.pt_sroff, max_entries / 4 + 256);
     A_(r.srow, max_entries); A_(r.srow_y, max_entries);
     A_(r.dkey[0], max_entries); A_(r.dkey[1], max_entries);
     A_(r.dval[0], max_entries); A_(r.dval[1], max_entries); A_(r.offs, max_entries);
     A_(r.pkey[0], max_pairs); A_(r.pkey[1], max_pairs); A_(r.pval[0], max_pairs); A_(r.pval[1], max_pairs);
     if (full_key) { A_(r.pkey64[0], max_pairs); A_(r.pkey64[1], max_pairs); }
     A_(r.ranges, 2 * max_tiles); A_(r.tile_eval, 2 * max_tiles); A_(r.hist, 256 * kSortBlocks);
-    A_(r.block_sums, kScanBlocks);
+    A_(r.block_sums, kScanBlocks); A_(r.block_sums64, kScanBlocks);
     A_(r.n_sort, 1); A_(r.cnt, 1);
 #undef A_
     return hipSuccess;

@@ -83,6 +83,7 @@ int na_setup(int dev, NaDevice*& out) {
         t.r.max_pairs = GSC_NOALLOC_MAX_PAIRS;
         t.r.max_tiles = kNaTiles;
         t.r.srow_cap = n;
+        t.r.tall_cap = n / 4 + 256;
         t.r.cnt_host = nullptr;  // counters are read on the device only
         t.ready = true;
         d = t;

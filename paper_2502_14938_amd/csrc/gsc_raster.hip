@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "gsc_blockscan.h"
 #include "gsc_common.h"
 
 namespace gsc {
@@ -302,8 +303,8 @@ struct PreArgs {
     uint32_t* nsup;
     uint32_t* dkey;
     uint32_t* dval;
-    int32_t* tall_list;  // tall entries of each chunk of 256 entries, in the chunk's slots
-    int32_t* tall_cnt;   // per chunk
+    int32_t* tall_list;   // tall entries of each chunk of 256 entries, in the chunk's slots
+    uint64_t* tall_pack;  // per chunk: its tall entries | their super rows << 32
     int32_t* ranges;     // [2 * tiles] cleared here for this batch's ranges
     int64_t n_ranges;
     int64_t max_entries;
@@ -314,6 +315,7 @@ struct PreArgs {
 // loads of an entry)
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(PreArgs p) {
     __shared__ uint32_t s_wtall[NT / 64];
+    __shared__ uint32_t s_srows;  // super rows of the step's tall footprints
     // the block's records, copied out together once complete (whole lines,
     // coalesced: a record written in two halves far apart in time would
     // leave half-written lines for the L2 to evict)
@@ -332,6 +334,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             p.rc->n_echunks = (s_ne + NT - 1) / NT;
         }
     }
+    if (threadIdx.x == 0) s_srows = 0u;
     for (int64_t i = gtid(); i < p.n_ranges; i += gstride()) p.ranges[i] = 0;
     __syncthreads();
     const int64_t ne = s_ne;
@@ -446,6 +449,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         const uint64_t m = __ballot(tall);
         if (lane == 0) s_wtall[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        if (tall) atomicAdd(&s_srows, (uint32_t)((y1 >> kSupShift) - (y0 >> kSupShift) + 1));
         __syncthreads();
         const int64_t chunk = base / NT;
         if (tall) {
@@ -456,7 +460,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (threadIdx.x == 0) {
             uint32_t n = 0;
             for (int q = 0; q < NT / 64; ++q) n += s_wtall[q];
-            p.tall_cnt[chunk] = (int32_t)n;
+            p.tall_pack[chunk] = (uint64_t)n | ((uint64_t)s_srows << 32);
+            s_srows = 0u;  // (read above; the next step's adds come after the barrier below)
         }
         {
             const int nv = (int)(ne - base < NT ? ne - base : NT);
@@ -635,21 +640,50 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
     }
 }
 
-// Dense list of the tall entries the preprocess listed per chunk of 256
-// entries: chunk c's entries at off[c] + i, and the super rows (pairs of
-// tile rows 2 Y, 2 Y + 1) each spans.
-__global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ list, const int32_t* __restrict__ cnt,
-                                                     const uint32_t* __restrict__ off, const int32_t* n_chunks,
-                                                     int32_t* __restrict__ dense, const float4* __restrict__ rec,
-                                                     uint32_t* __restrict__ srcnt) {
+
+// Dense records of the tall entries the preprocess listed per chunk of 256
+// entries: chunk c's footprints at f = its offset + i (the scan's low half),
+// their super rows (pairs of tile rows 2 Y, 2 Y + 1) from the chunk's
+// super-row offset (the high half) on, in list order.
+__global__ __launch_bounds__(NT) void k_tall_compact(const int32_t* __restrict__ list, const uint64_t* __restrict__ pack,
+                                                     const uint64_t* __restrict__ off, const int32_t* n_chunks,
+                                                     const float4* __restrict__ rec, TallRec* __restrict__ trec,
+                                                     uint32_t* __restrict__ sroff, int64_t tall_cap,
+                                                     RasterCounters* rc) {
+    __shared__ uint32_t wsum[NT / 64];
     const int64_t nc = *n_chunks;
-    for (int64_t c = blockIdx.x; c < nc; c += gridDim.x)
-        if ((int32_t)threadIdx.x < cnt[c]) {
-            const int32_t x = list[c * NT + threadIdx.x];
-            dense[off[c] + threadIdx.x] = x;
-            const uint32_t rows = __float_as_uint(rec[kRec * (int64_t)x + 2].y);
-            srcnt[off[c] + threadIdx.x] = ((rows >> 16) >> kSupShift) - ((rows & 0xffff) >> kSupShift) + 1;
+    for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {  // block-uniform
+        const uint32_t n = (uint32_t)pack[c];
+        const uint64_t o = off[c];
+        const bool mine = threadIdx.x < n;
+        int32_t x = 0;
+        float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A, C = A;
+        uint32_t nsr = 0;
+        if (mine) {
+            x = list[c * NT + threadIdx.x];
+            const float4* rp = rec + kRec * (int64_t)x;
+            A = rp[0]; B = rp[1]; C = rp[2];
+            const uint32_t rows = __float_as_uint(C.y);
+            nsr = ((rows >> 16) >> kSupShift) - ((rows & 0xffff) >> kSupShift) + 1;
         }
+        uint32_t tot;
+        const uint32_t pre = blockscan::block_excl_scan(nsr, wsum, tot);
+        const int64_t f = (int64_t)(uint32_t)o + threadIdx.x;
+        if (mine) {
+            if (f < tall_cap) {
+                const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
+                TallRec t;
+                t.mx = el.mx; t.my = el.my; t.ca = el.ca; t.cb = el.cb; t.cc = el.cc; t.tau = el.tau;
+                t.det = el.det; t.xmax = el.xmax; t.ymax = el.ymax; t.kr = el.kr; t.margin = el.margin;
+                t.ia = el.ia; t.ic = el.ic;
+                t.e = (uint32_t)x; t.rows = __float_as_uint(C.y); t.seg = __float_as_uint(C.z);
+                trec[f] = t;
+                sroff[f] = (uint32_t)(o >> 32) + pre;
+            } else {
+                atomicOr(&rc->overflow, 4);
+            }
+        }
+    }
 }
 
 // One wave per 64 consecutive stored super rows of the tall footprints (a
@@ -728,24 +762,26 @@ static_assert(kTallGW % 2 == 0, "super rows pair neighbouring lanes");
 // offset: (span of row 2 Y, span of row 2 Y + 1, entry, items of the
 // footprint's earlier super rows) and its index Y.  The group's totals give
 // the entry's tile count and its (super tile, entry) item count.
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tall_spans(SegTable tab, const int32_t* __restrict__ tall_e,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tall_spans(SegTable tab, const TallRec* __restrict__ trec,
                                                    const uint32_t* __restrict__ sroff, RasterCounters* rc,
-                                                   float4* __restrict__ rec, uint4* __restrict__ srow,
+                                                   int64_t tall_cap, float4* __restrict__ rec, uint4* __restrict__ srow,
                                                    int32_t* __restrict__ srow_y, int64_t cap,
                                                    uint32_t* __restrict__ ntiles, uint32_t* __restrict__ nsup,
                                                    uint32_t* __restrict__ dkey) {
-    const int64_t n = rc->n_tall_e;
+    int64_t n = rc->n_tall_e;
+    if (n > tall_cap) n = tall_cap;
     if (gtid() == 0 && (int64_t)rc->n_srows > cap) rc->overflow |= 4;
     const int sub = (int)(threadIdx.x % kTallGW);
     const int64_t ngrp = gstride() / kTallGW;
     for (int64_t f = gtid() / kTallGW; f < n; f += ngrp) {
-        const int64_t e = tall_e[f];
+        const TallRec t = trec[f];
+        const int64_t e = t.e;
         float4* rp = rec + kRec * e;
-        const float4 A = rp[0], B = rp[1], C = rp[2];
-        const uint32_t rows = __float_as_uint(C.y);
-        const int y0 = (int)(rows & 0xffffu), y1 = (int)(rows >> 16);
-        const Seg& s = tab.s[__float_as_uint(C.z)];
-        const Ellipse el = make_ellipse(A.x, A.y, A.z, A.w, B.x, fmaxf(2.0f * logf(255.0f * B.y), 0.f));
+        const int y0 = (int)(t.rows & 0xffffu), y1 = (int)(t.rows >> 16);
+        const Seg& s = tab.s[t.seg];
+        Ellipse el;
+        el.mx = t.mx; el.my = t.my; el.ca = t.ca; el.cb = t.cb; el.cc = t.cc; el.tau = t.tau; el.det = t.det;
+        el.xmax = t.xmax; el.ymax = t.ymax; el.kr = t.kr; el.margin = t.margin; el.ia = t.ia; el.ic = t.ic;
         const int ybase = (y0 >> kSupShift) << kSupShift;  // tile row 2 Y0
         const int64_t q0 = sroff[f];
         uint32_t tiles = 0, before = 0;
@@ -1079,15 +1115,14 @@ static bool eyes_share_rotation(const SegTable& tab) {
 // each footprint's super rows, spans and counts.
 hipError_t tall_spans(const SegTable& tab, Raster& r, hipStream_t st) {
     RasterCounters* rc = r.cnt;
-    hipError_t e = scan_u32(reinterpret_cast<const uint32_t*>(r.pt_cnt), r.pt_off, &rc->n_echunks, 0, &rc->n_tall_e,
-                            r.block_sums, st);
+    // one scan gives each chunk's first footprint (low half) and first super
+    // row (high half), and the totals
+    hipError_t e = scan_u64(r.pt_pack, r.pt_off, &rc->n_echunks, &rc->n_tall_e, &rc->n_srows, r.block_sums64, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.pt_list, r.pt_cnt, r.pt_off,
-                       &rc->n_echunks, r.pt_dense, r.rec, r.pt_srcnt);
-    e = scan_u32(r.pt_srcnt, r.pt_sroff, &rc->n_tall_e, 0, &rc->n_srows, r.block_sums, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tall_spans, grid_fit(k_tall_spans, (int64_t)r.max_entries * kTallGW), dim3(NT), 0, st, tab,
-                       r.pt_dense, r.pt_sroff, rc, r.rec, r.srow, r.srow_y, r.srow_cap, r.ntiles, r.nsup,
+    hipLaunchKernelGGL(k_tall_compact, dim3(kGridBlocks), dim3(NT), 0, st, r.pt_list, r.pt_pack, r.pt_off,
+                       &rc->n_echunks, r.rec, r.trec, r.pt_sroff, r.tall_cap, rc);
+    hipLaunchKernelGGL(k_tall_spans, grid_fit(k_tall_spans, r.tall_cap * kTallGW), dim3(NT), 0, st, tab, r.trec,
+                       r.pt_sroff, rc, r.tall_cap, r.rec, r.srow, r.srow_y, r.srow_cap, r.ntiles, r.nsup,
                        r.shared_depth ? nullptr : r.dkey[0]);
     return hipGetLastError();
 }
@@ -1102,7 +1137,7 @@ hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, b
     PreArgs pa;
     pa.tab = tab; pa.rc = rc; pa.rec = r.rec; pa.ntiles = r.ntiles; pa.nsup = r.nsup; pa.dkey = r.dkey[0];
     pa.dval = r.dval[0];
-    pa.tall_list = r.pt_list; pa.tall_cnt = r.pt_cnt; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_sup;
+    pa.tall_list = r.pt_list; pa.tall_pack = r.pt_pack; pa.ranges = r.ranges; pa.n_ranges = 2 * (int64_t)tab.total_sup;
     pa.max_entries = r.max_entries;
     r.shared_depth = !full_key_sort && eyes_share_rotation(tab);
     pa.shared_depth = r.shared_depth ? 1 : 0;

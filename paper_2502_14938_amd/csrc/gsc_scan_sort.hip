@@ -66,6 +66,50 @@ __global__ __launch_bounds__(NT) void k_scan_down(const uint32_t* __restrict__ i
     }
 }
 
+// 64-bit form: each value packs two 32-bit counts (low, high) that scan
+// independently; the totals go to total_lo and total_hi.
+__global__ __launch_bounds__(NT) void k_scan_reduce64(const uint64_t* __restrict__ in, const int32_t* n_dev,
+                                                      uint64_t* __restrict__ block_sums) {
+    __shared__ uint64_t wsum[NT / 64];
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, 0), SCAN_TILE, b0, b1);
+    uint64_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) s += in[i];
+    uint64_t t = block_sum<uint64_t>(s, wsum);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(NT) void k_scan_down64(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                    const int32_t* n_dev, const uint64_t* __restrict__ block_sums,
+                                                    int32_t* total_lo, int32_t* total_hi) {
+    __shared__ uint64_t wsum[NT / 64];
+    uint64_t carry = block_carry<uint64_t>(block_sums, wsum);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const uint64_t t = carry + block_sums[blockIdx.x];
+        *total_lo = (int32_t)(uint32_t)t;
+        *total_hi = (int32_t)(uint32_t)(t >> 32);
+    }
+    int64_t b0, b1;
+    chunk_of(count_of(n_dev, 0), SCAN_TILE, b0, b1);
+    for (int64_t base = b0; base < b1; base += SCAN_TILE) {
+        uint64_t v[4], s = 0;
+        int64_t i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v[r] = i0 + r < b1 ? in[i0 + r] : 0ull;
+            s += v[r];
+        }
+        uint64_t tot;
+        uint64_t e = carry + block_excl_scan<uint64_t>(s, wsum, tot);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (i0 + r < b1) out[i0 + r] = e;
+            e += v[r];
+        }
+        carry += tot;
+    }
+}
+
 // Compaction form of the down-sweep: flags in `in` (0 or 1), and
 // ids[prefix] = i for every flagged i (ascending).
 __global__ __launch_bounds__(NT) void k_scan_compact(const uint32_t* __restrict__ in, int32_t* __restrict__ ids,
@@ -371,6 +415,14 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, const int32_t* n_dev, int
                     uint32_t* block_sums, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(NT), 0, st, in, n_dev, n_host, block_sums);
     hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(NT), 0, st, in, out, n_dev, n_host, block_sums, total);
+    return hipGetLastError();
+}
+
+hipError_t scan_u64(const uint64_t* in, uint64_t* out, const int32_t* n_dev, int32_t* total_lo, int32_t* total_hi,
+                    uint64_t* block_sums, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_reduce64, dim3(kScanBlocks), dim3(NT), 0, st, in, n_dev, block_sums);
+    hipLaunchKernelGGL(k_scan_down64, dim3(kScanBlocks), dim3(NT), 0, st, in, out, n_dev, block_sums, total_lo,
+                       total_hi);
     return hipGetLastError();
 }
 
