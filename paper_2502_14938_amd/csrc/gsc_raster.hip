@@ -88,21 +88,32 @@ __device__ __forceinline__ void locate_entry(const SegTable& tab, const int32_t*
 // Minimum of q(d) = a dx^2 + 2 b dx dy + c dy^2 over the closed rectangle
 // [x0,x1] x [y0,y1] of offsets d (q convex: 0 inside, else on an edge; the
 // edge minimiser of a 1-D quadratic, clamped).  ia = 1/a, ic = 1/c.
-// Every footprint's tile spans are computed once (here or in k_tall_rows)
+// Every footprint's tile spans are computed once (here or in k_tall_spans)
 // and stored, so counting and emission read the same decisions.
+// Minimum over the vertical edge x = dx and the horizontal edge y = ey.
+__device__ __forceinline__ float edge_min_q(float a, float b, float c, float ia, float ic, float x0, float x1,
+                                            float y0, float y1, float dx, float ey) {
+    float dy = fminf(fmaxf(-b * dx * ic, y0), y1);
+    float ex = fminf(fmaxf(-b * ey * ia, x0), x1);
+    return fminf(a * dx * dx + 2.f * b * dx * dy + c * dy * dy, a * ex * ex + 2.f * b * ex * ey + c * ey * ey);
+}
+
+// kRolled keeps the two edge pairs in a loop: unrolled, the compiler keeps
+// both pairs' terms of every inlined call live at once, which costs
+// k_preprocess (one footprint per lane, many rows) about 60 VGPRs; the tall
+// kernel (one row per lane, a serial tile scan) runs faster unrolled.
+template <bool kRolled>
 __device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia, float ic, float x0, float x1,
                                             float y0, float y1) {
     if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
     float best = INFINITY;
     float fx[2] = {x0, x1}, fy[2] = {y0, y1};
+    if constexpr (kRolled) {
+#pragma unroll 1
+        for (int i = 0; i < 2; ++i) best = fminf(best, edge_min_q(a, b, c, ia, ic, x0, x1, y0, y1, fx[i], fy[i]));
+    } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        float dx = fx[i];
-        float dy = fminf(fmaxf(-b * dx * ic, y0), y1);
-        best = fminf(best, a * dx * dx + 2.f * b * dx * dy + c * dy * dy);
-        float ey = fy[i];
-        float ex = fminf(fmaxf(-b * ey * ia, x0), x1);
-        best = fminf(best, a * ex * ex + 2.f * b * ex * ey + c * ey * ey);
+        for (int i = 0; i < 2; ++i) best = fminf(best, edge_min_q(a, b, c, ia, ic, x0, x1, y0, y1, fx[i], fy[i]));
     }
     return best;
 }
@@ -139,13 +150,15 @@ __device__ __forceinline__ Ellipse make_ellipse(float mx, float my, float ca, fl
 }
 
 // Does the footprint reach the pixel-centre rectangle of tile (tx, ty)?
+template <bool kRolled>
 __device__ __forceinline__ bool tile_hit(const Ellipse& e, int tx, int ty, int W, int H) {
     float x0 = (float)(kTile * tx) + 0.5f, y0 = (float)(kTile * ty) + 0.5f;
     float x1 = (float)min(kTile * tx + kTile - 1, W - 1) + 0.5f;
     float y1 = (float)min(kTile * ty + kTile - 1, H - 1) + 0.5f;
-    return rect_min_q(e.ca, e.cb, e.cc, e.ia, e.ic, x0 - e.mx, x1 - e.mx, y0 - e.my, y1 - e.my) <= e.tau;
+    return rect_min_q<kRolled>(e.ca, e.cb, e.cc, e.ia, e.ic, x0 - e.mx, x1 - e.mx, y0 - e.my, y1 - e.my) <= e.tau;
 }
 
+template <bool kRolled>
 __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int W, int H, int& lo, int& hi) {
     lo = 0;
     hi = -1;
@@ -187,7 +200,7 @@ __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int 
     int l = -1;
     int lim = has_s ? s_lo - 1 : c_hi;
     for (int tx = c_lo; tx <= lim; ++tx)
-        if (tile_hit(e, tx, ty, W, H)) { l = tx; break; }
+        if (tile_hit<kRolled>(e, tx, ty, W, H)) { l = tx; break; }
     if (l < 0) {
         if (!has_s) return;
         l = s_lo;
@@ -197,7 +210,7 @@ __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int 
     int h = -1;
     int stop = has_s ? s_hi + 1 : l + 1;
     for (int tx = c_hi; tx >= stop; --tx)
-        if (tile_hit(e, tx, ty, W, H)) { h = tx; break; }
+        if (tile_hit<kRolled>(e, tx, ty, W, H)) { h = tx; break; }
     if (h < 0) h = has_s ? s_hi : l;
     lo = l;
     hi = h;
@@ -423,7 +436,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                 for (int i = 0; i < kSmallRows; ++i) {
                     int lo = 0xffff, hi = 0;
-                    if (y0 + i <= y1) row_span(el, y0 + i, s.ntx, s.W, s.H, lo, hi);
+                    if (y0 + i <= y1) row_span<true>(el, y0 + i, s.ntx, s.W, s.H, lo, hi);
                     if (hi >= lo) count += (uint32_t)(hi - lo + 1);
                     else lo = 0xffff, hi = 0;
                     spans[i] = (uint32_t)lo | ((uint32_t)hi << 16);
@@ -790,7 +803,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             uint32_t sp = kEmptySpan;
             if (y >= y0 && y <= y1) {
                 int lo, hi;
-                row_span(el, y, s.ntx, s.W, s.H, lo, hi);
+                row_span<false>(el, y, s.ntx, s.W, s.H, lo, hi);
                 if (hi >= lo) {
                     sp = (uint32_t)lo | ((uint32_t)hi << 16);
                     tiles += (uint32_t)(hi - lo + 1);
