@@ -13,9 +13,15 @@ namespace {
 
 constexpr int NT = 256;        // threads per block (4 waves)
 constexpr int SCAN_TILE = 1024;  // elements per scan step (4 per thread)
-constexpr int SORT_IPT = 16;     // elements per thread per sort step
-constexpr int SORT_TILE = NT * SORT_IPT;
-constexpr int SORT_WSEG = SORT_TILE / 4;  // elements per wave per step
+constexpr int SORT_IPT_U32 = 8;
+constexpr int SORT_IPT_U16 = 16;
+// Elements per thread per sort step, by key width: the depth sort (32-bit
+// keys, one per Gaussian) is small enough that 16 per thread would leave
+// most of the chip idle, so its tiles are half as long.
+template <typename K>
+constexpr int sort_ipt() { return sizeof(K) == 4 ? SORT_IPT_U32 : sizeof(K) == 2 ? SORT_IPT_U16 : 16; }
+template <typename K>
+constexpr int sort_tile() { return NT * sort_ipt<K>(); }
 
 using blockscan::block_carry;
 using blockscan::block_excl_scan;
@@ -163,10 +169,11 @@ __device__ __forceinline__ uint64_t peers_of(uint32_t d, bool valid) {
     return ~(((uint64_t)hi << 32) | (uint64_t)lo);
 }
 
-// SORT_IPT consecutive keys starting at a 16-byte aligned element.
-template <typename K>
-__device__ __forceinline__ void load_run(const K* __restrict__ p, K (&k)[SORT_IPT]) {
-    constexpr int NV = SORT_IPT * (int)sizeof(K) / 16;
+// IPT consecutive keys starting at a 16-byte aligned element.
+template <typename K, int IPT>
+__device__ __forceinline__ void load_run(const K* __restrict__ p, K (&k)[IPT]) {
+    static_assert(IPT * sizeof(K) % 16 == 0, "whole 16-byte loads");
+    constexpr int NV = IPT * (int)sizeof(K) / 16;
     const uint4* q = reinterpret_cast<const uint4*>(p);
     uint4 v[NV];
 #pragma unroll
@@ -181,6 +188,7 @@ __device__ __forceinline__ void load_run(const K* __restrict__ p, K (&k)[SORT_IP
 template <typename K>
 __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ keys, const int32_t* n_dev, int64_t n_host,
                                                    int shift, int bits, uint32_t* __restrict__ hist) {
+    constexpr int SORT_IPT = sort_ipt<K>(), SORT_TILE = sort_tile<K>();
     __shared__ uint32_t h[4][256];
     const int w = threadIdx.x >> 6;
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
@@ -255,6 +263,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const K* __restrict__ kin,
                                                       const uint32_t* __restrict__ dtot,
                                                       const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gout) {
     constexpr int bits = BITS;
+    constexpr int SORT_IPT = sort_ipt<K>(), SORT_TILE = sort_tile<K>(), SORT_WSEG = SORT_TILE / 4;
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t texcl[256];
