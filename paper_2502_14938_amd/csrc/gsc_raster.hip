@@ -168,9 +168,20 @@ __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int 
     float L, R;       // x-extent of E inside the band (offsets from mx)
     bool certain;     // extent reliable enough to classify interior tiles
     const float b0 = fmaxf(y0, -e.ymax), b1 = fminf(y1, e.ymax);
-    if (b0 > b1) {    // band grazes a tip of E: let the exact test decide
-        L = -e.xmax;
-        R = e.xmax;
+    if (b0 > b1) {
+        // The band lies beyond a tip of E, within the margin: E can reach it
+        // only near that tip, so the exact test decides over a short range.
+        // The chords of E at |dy| >= d1 lie inside the chord at d1 (they
+        // shrink towards the tip) shifted by at most |cb| / ca per unit of
+        // dy (their centres move along dx = -cb dy / ca) over the rest of
+        // the way to the tip, which is less than ymax - d1 + margin.
+        const float d1 = fmaxf(e.ymax - e.margin, 0.f);
+        const float dy1 = y0 > 0.f ? d1 : -d1;
+        const float s1 = __builtin_amdgcn_sqrtf(fmaxf(e.ca * e.tau - e.det * dy1 * dy1, 0.f));
+        const float cen = -e.cb * dy1 * e.ia;
+        const float wid = s1 * e.ia + fabsf(e.cb) * e.ia * (e.ymax - d1 + e.margin);
+        L = cen - wid;
+        R = cen + wid;
         certain = false;
     } else {
         float dyr = fminf(fmaxf(-e.cb * e.kr, b0), b1);
