@@ -208,21 +208,48 @@ __device__ __forceinline__ void row_span(const Ellipse& e, int ty, int ntx, int 
         s_hi = (int)fminf(fmaxf(sb, (float)(s_lo - 1)), (float)min(c_hi, last_full));
     }
     const bool has_s = s_lo <= s_hi;
-    int l = -1;
-    int lim = has_s ? s_lo - 1 : c_hi;
-    for (int tx = c_lo; tx <= lim; ++tx)
-        if (tile_hit<kRolled>(e, tx, ty, W, H)) { l = tx; break; }
-    if (l < 0) {
-        if (!has_s) return;
-        l = s_lo;
+    // Exact tests: from the left over [c_lo, lim] up to the first hit l
+    // (none: the interior's first tile, or no tile at all without an
+    // interior), then from the right over [stop, c_hi] down to the first hit
+    // (none: the interior's last tile, or l, which is hit).  One loop runs
+    // both scans, one test a trip, so a wave pays for the most tests any of
+    // its lanes needs rather than for its longest left scan plus its longest
+    // right scan.
+    const int lim = has_s ? s_lo - 1 : c_hi;
+    int l = s_lo, h = s_hi, stop = s_hi + 1;
+    int tx = c_lo;
+    bool left = true, done = false;
+    if (lim < c_lo) {  // nothing to test on the left (then there is an interior)
+        left = false;
+        tx = c_hi;
+        done = tx < stop;
     }
-    // tile l is hit (found by the scan above, or the interior's first), so
-    // the scan from the right stops short of it
-    int h = -1;
-    int stop = has_s ? s_hi + 1 : l + 1;
-    for (int tx = c_hi; tx >= stop; --tx)
-        if (tile_hit<kRolled>(e, tx, ty, W, H)) { h = tx; break; }
-    if (h < 0) h = has_s ? s_hi : l;
+    while (!done) {
+        const bool hit = tile_hit<kRolled>(e, tx, ty, W, H);
+        if (left) {
+            if (hit || tx == lim) {
+                if (!hit && !has_s) return;  // no tile of the row is hit
+                if (hit) l = tx;
+                left = false;
+                if (!has_s) {
+                    stop = l + 1;
+                    h = l;
+                }
+                tx = c_hi;
+                done = tx < stop;
+            } else {
+                ++tx;
+            }
+        } else {
+            if (hit) {
+                h = tx;
+                done = true;
+            } else {
+                --tx;
+                done = tx < stop;
+            }
+        }
+    }
     lo = l;
     hi = h;
 }
