@@ -515,6 +515,16 @@ def run_frames(args):
                      "launches": launches, "frames": timed_frames})
     if drow == "blend":
         roofline["alu_flop_per_launch"] = round(f / launches)
+        if roofline["bound"] == "hbm":
+            # the byte model counts every tile pair's record as read from HBM;
+            # the tiles of a super tile share those records through L2 and LDS
+            alu = f / sec / 1e12 if sec > 0 else 0.0
+            roofline.update({"alu_achieved_tflops": round(alu, 2), "alu_frac": round(alu / ALU_FP32_PUBLISHED_TFS, 4),
+                             "alu_frac_vs_nonpacked_fp32": round(alu / VALU_FP32_NONPACKED_TFS, 4),
+                             "note": "achieved counts every tile pair's 40-B record as an HBM read (the rasterizer "
+                                     "rows' byte model), so frac can reach 1; the records are shared through L2 "
+                                     "and LDS (measured HBM bytes: traffic) and the kernel is bound by its "
+                                     "vector ALU (alu_frac)"})
     dstat = rows_out["derive"]
     derive_mfma = None
     if per_frame["derive"] > 0:

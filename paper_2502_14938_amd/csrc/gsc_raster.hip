@@ -279,7 +279,7 @@ __device__ __forceinline__ Ellipse shfl_ellipse(const Ellipse& el, int src) {
 }
 
 // Footprints taller than this many tile rows get one thread per row for
-// their spans (k_tall_rows) and are emitted row by row (k_dup_big); shorter
+// their spans (k_tall_spans) and are emitted by super rows (k_dup_big); shorter
 // ones keep their row spans in the record and are emitted from them.
 constexpr int kSmallRows = 4;
 
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
             }
         }
         // tall footprints (more than kSmallRows tile rows) are counted later,
-        // one thread per row (k_tall_rows); list them in this chunk's slots
+        // one thread per row (k_tall_spans); list them in this chunk's slots
         const bool tall = valid && y1 - y0 + 1 > kSmallRows;
         if (valid) {
             rows = y0 <= y1 ? ((uint32_t)y0 | ((uint32_t)y1 << 16)) : 0u;
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
             p.ntiles[e] = count;
             p.nsup[e] = scount;
             if (!p.shared_depth) {
-                p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_count
+                p.dkey[e] = (count || tall) ? __float_as_uint(depth) : 0u;  // tall: settled by k_tall_spans
                 p.dval[e] = (uint32_t)e;
             }
         }
