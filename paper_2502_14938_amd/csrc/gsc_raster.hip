@@ -362,9 +362,9 @@ struct PreArgs {
     int32_t shared_depth;  // paired eyes of one rotation: one depth key per Gaussian
 };
 
-// (at most 80 VGPRs, no spill: six waves per SIMD to cover the chain of
+// (at most 72 VGPRs, no spill: seven waves per SIMD to cover the chain of
 // dependent loads of an entry)
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_preprocess(PreArgs p) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_preprocess(PreArgs p) {
     __shared__ uint32_t s_wtall[NT / 64];
     __shared__ uint32_t s_srows;  // super rows of the step's tall footprints
     // the block's records, copied out together once complete (whole lines,
