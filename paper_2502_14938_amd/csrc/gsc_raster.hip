@@ -548,6 +548,7 @@ struct DupArgs {
     RasterCounters* rc;
     const uint32_t* order;   // depth rank -> entry (depth-presorted mode)
     const uint32_t* offs;    // pair offset per rank (per entry in full-key mode)
+    const uint32_t* items;   // item count per rank, the scan's input (an entry without items is skipped unread)
     float4* rec;             // (k_dup_rows stores a tall entry's output offset in D.y)
     const uint32_t* dkey;    // depth key per entry (full-key mode)
     uint32_t* key32;         // global super-tile id (depth-presorted mode, more than 65,536 super tiles)
@@ -626,8 +627,11 @@ __global__ __launch_bounds__(NT) void k_dup_rows(DupArgs d) {
             const uint32_t e = kFull ? (uint32_t)r : d.order[r];
             const uint32_t out_at = d.offs[r];
             float4* rp = d.rec + kRec * (int64_t)e;
-            const float4 C = rp[2];
-            const float4 D = rp[3];
+            float4 C = make_float4(0.f, 0.f, 0.f, 0.f), D = C;
+            if (d.items[r]) {  // (the entry's record is not read when it has no items)
+                C = rp[2];
+                D = rp[3];
+            }
             const uint32_t cnt = __float_as_uint(C.w);
             if (cnt) {
                 const uint32_t rows = __float_as_uint(C.y);
@@ -1219,7 +1223,7 @@ hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, b
         // keys in 16 bits when the batch's global super-tile ids fit
         const bool k16 = tab.total_sup <= 65536;
         uint16_t* pk16[2] = {reinterpret_cast<uint16_t*>(r.pkey[0]), reinterpret_cast<uint16_t*>(r.pkey[1])};
-        da.order = r.dval[which]; da.offs = r.offs; da.key64 = nullptr; da.val = r.pval[0];
+        da.order = r.dval[which]; da.offs = r.offs; da.items = r.scnt; da.key64 = nullptr; da.val = r.pval[0];
         da.key32 = k16 ? nullptr : r.pkey[0];
         da.key16 = k16 ? pk16[0] : nullptr;
         hipLaunchKernelGGL(k_dup_rows<false>, grid_fit(k_dup_rows<false>, r.max_entries), dim3(NT), 0, st, da);
@@ -1246,7 +1250,7 @@ hipError_t raster_batch(const SegTable& tab_in, Raster& r, bool full_key_sort, b
         e = scan_u32(r.nsup, r.offs, &rc->n_entries, 0, &rc->n_pairs, r.block_sums, st);
         if (e != hipSuccess) return e;
         mark(mk, 7, st);
-        da.order = nullptr; da.offs = r.offs; da.key32 = nullptr; da.key16 = nullptr; da.key64 = r.pkey64[0];
+        da.order = nullptr; da.offs = r.offs; da.items = r.nsup; da.key32 = nullptr; da.key16 = nullptr; da.key64 = r.pkey64[0];
         da.val = r.pval[0];
         r.key16 = false;
         hipLaunchKernelGGL(k_dup_rows<true>, grid_fit(k_dup_rows<true>, r.max_entries), dim3(NT), 0, st, da);
