@@ -817,7 +817,7 @@ static_assert(kTallGW % 2 == 0, "super rows pair neighbouring lanes");
 // offset: (span of row 2 Y, span of row 2 Y + 1, entry, items of the
 // footprint's earlier super rows) and its index Y.  The group's totals give
 // the entry's tile count and its (super tile, entry) item count.
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tall_spans(SegTable tab, const TallRec* __restrict__ trec,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_tall_spans(SegTable tab, const TallRec* __restrict__ trec,
                                                    const uint32_t* __restrict__ sroff, RasterCounters* rc,
                                                    int64_t tall_cap, float4* __restrict__ rec, uint4* __restrict__ srow,
                                                    int32_t* __restrict__ srow_y, int64_t cap,
